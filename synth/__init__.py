@@ -1,0 +1,104 @@
+"""Seeded synthetic label volumes (inputs for tests and the benchmark).
+
+The volumes stand in for the paper's Cells, Fiber and Cortex data sets
+(Section 5), which are not available here.  This module holds no part of the
+compression method: it only generates labels.  The generators are plain C
+(``synth.c``) driven through ctypes; volumes are numpy uint32 arrays of shape
+(nz, ny, nx), x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "synth.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile synth.c into libsynth.so next to it."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        lib.synth_voronoi_bg.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64]
+        lib.synth_cells.argtypes = [u32p, u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64]
+        lib.synth_blobs.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64]
+        lib.synth_neurite.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def voronoi_bg(n: int = 64, sites: int = 200, bg: float = 0.30, seed: int = 1) -> np.ndarray:
+    """Voronoi of `sites` uniform sites, labels 1..sites, then whole sites
+    cleared to 0 in seeded order until >= bg of the voxels are 0."""
+    out = np.empty((n, n, n), dtype=np.uint32)
+    rc = _load().synth_voronoi_bg(_ptr(out), n, sites, bg, seed)
+    assert rc == 0, rc
+    return out
+
+
+def cells(n: int = 512, grid: int = 37, p_noise: float = 0.5, seed: int = 2) -> np.ndarray:
+    """Jittered-grid Voronoi of grid^3 cells with 1-voxel boundary noise."""
+    out = np.empty((n, n, n), dtype=np.uint32)
+    tmp = np.empty((n, n, n), dtype=np.uint32)
+    rc = _load().synth_cells(_ptr(out), _ptr(tmp), n, grid, p_noise, seed)
+    assert rc == 0, rc
+    return out
+
+
+def blobs(n: int = 512, sites: int = 50, amp: float = 24.0, seed: int = 4) -> np.ndarray:
+    """Voronoi of `sites` sites over a smoothly warped space (large blobs)."""
+    out = np.empty((n, n, n), dtype=np.uint32)
+    rc = _load().synth_blobs(_ptr(out), n, sites, amp, seed)
+    assert rc == 0, rc
+    return out
+
+
+# fraction of the volume given to tubes before overlaps; chosen so that about
+# 45 % of the voxels stay background 0 at the default density
+NEURITE_FILL = 1.45
+
+
+def neurite(nx: int = 1024, ny: int = 1024, nz: int = 1024, labels: int = 20000, fill: float = NEURITE_FILL,
+            seed: int = 3) -> np.ndarray:
+    """Branching random-walk tubes of radius 2..8 with Zipf sizes."""
+    out = np.empty((nz, ny, nx), dtype=np.uint32)
+    painted = ctypes.c_uint64(0)
+    rc = _load().synth_neurite(_ptr(out), nx, ny, nz, labels, fill, seed, ctypes.byref(painted))
+    assert rc == 0, rc
+    return out
+
+
+def random_brick(b: int, n_labels: int, seed: int, smooth: int = 0) -> np.ndarray:
+    """A b^3 brick of labels 1..n_labels for property tests: i.i.d. labels,
+    optionally smoothed by repeated majority copying from a random axis
+    neighbour so that the brick has regions of equal labels."""
+    rng = np.random.default_rng(seed)
+    a = rng.integers(1, n_labels + 1, size=(b, b, b), dtype=np.uint32)
+    for _ in range(smooth):
+        ax = int(rng.integers(0, 3))
+        sh = np.roll(a, 1, axis=ax)
+        take = rng.random(a.shape) < 0.6
+        a = np.where(take, sh, a).astype(np.uint32)
+    return a
