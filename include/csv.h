@@ -1,0 +1,160 @@
+/*
+ * csv.h -- C ABI of the MI355X compressed-segmentation-volume library.
+ *
+ * The method is that of Piochowiak & Dachsbacher, "Fast Compressed
+ * Segmentation Volumes for Scientific Visualization" (IEEE TVCG 2023):
+ * a label volume is cut into 32^3 bricks (Sec. 3.1); each brick is stored as
+ * a palette of labels plus a stream of 4-bit (operation, stop) nibbles that
+ * rebuild the brick's resolution pyramid coarse to fine (Sec. 3.2, Alg. 1,
+ * Alg. 2); the nibbles are rANS coded against two static frequency tables
+ * per volume (Sec. 3.3).  Decoding a brick to level of detail t yields level
+ * L_t of its pyramid: (32 >> t)^3 labels (Sec. 3.4).
+ *
+ * Conventions for every function:
+ *   - return value: CSV_OK (0) or a negative CSV_E* code; nothing aborts or
+ *     throws across this interface;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory of the pool's GPU; the caller owns every buffer it
+ *     passes in, the library owns what it allocates (pools, blobs it
+ *     returns, servers);
+ *   - volumes are C order [z][y][x] with x fastest, labels uint32; brick ids
+ *     run x fastest: id = bx + nbx * (by + nby * bz);
+ *   - decoded bricks are dense [z][y][x] blocks of (32 >> lod)^3 uint32.
+ *   - a `stream` argument is a hipStream_t (NULL = the default stream).
+ */
+#ifndef CSV_H
+#define CSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CSV_OK = 0,
+    CSV_EINVAL = -1,   /* bad argument (null pointer, unsupported parameter) */
+    CSV_ERANGE = -2,   /* brick id or level of detail out of range */
+    CSV_ECORRUPT = -3, /* malformed container or record */
+    CSV_ENOMEM = -4,   /* host or device allocation failed */
+    CSV_EHIP = -5,     /* a HIP runtime call failed */
+    CSV_EBUSY = -6     /* resource temporarily exhausted (server admission) */
+};
+
+#define CSV_ABI_VERSION 1u
+uint32_t csv_abi_version(void);
+
+/* Human-readable name of a CSV_E* code (static string). */
+const char *csv_strerror(int code);
+
+/* ------------------------------------------------------------------ */
+/* Encoding (Sec. 3.1-3.4; the paper's compressor is a CPU program)    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t brick_log2;    /* log2 of the brick edge; 5 (32^3) is what the GPU decodes; 1..6 */
+    uint32_t scale_bits;    /* rANS table precision: frequencies sum to 2^scale_bits; 8..11 */
+    uint32_t lane_k;        /* interleaving rule: W = largest power of two <= min(lane_max, n_symbols / lane_k) */
+    uint32_t lane_max;      /* at most this many interleaved rANS states per brick (power of two <= 64) */
+    uint32_t sample_stride; /* frequency-table prepass samples every sample_stride-th brick; 0 = 512,
+                               or 4096 above 2^20 bricks (Sec. 3.4) */
+    uint32_t threads;       /* host threads; 0 = all hardware threads */
+} csv_encode_opts;
+
+/* Defaults: brick_log2 5, scale_bits 10, lane_k 64, lane_max 64, sample_stride 0, threads 0. */
+void csv_encode_opts_default(csv_encode_opts *o);
+
+/*
+ * Compress a label volume (host memory, nx*ny*nz uint32, x fastest) into a
+ * container blob.  Bricks that reach past the volume are padded with label
+ * 0.  On success *blob points to *blob_bytes bytes allocated by the library;
+ * release them with csv_free.  opts may be NULL for the defaults.
+ * Errors: CSV_EINVAL (null pointers, zero dims, options out of range),
+ * CSV_ERANGE (2^32 or more bricks), CSV_ENOMEM.
+ */
+int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t nz, const csv_encode_opts *opts,
+                      uint8_t **blob, size_t *blob_bytes);
+
+void csv_free(void *p);
+
+typedef struct {
+    uint32_t nx, ny, nz, brick_log2, nbx, nby, nbz, n_bricks;
+    uint32_t scale_bits, lane_k, lane_max, sample_stride;
+    uint32_t freq[2][16]; /* interior table (children on levels >= 1), leaf table (children on L_0) */
+    uint64_t record_bytes; /* sum of all brick records */
+    uint64_t blob_bytes;
+} csv_volume_info;
+
+/* Parse and validate a container header (host memory). */
+int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info);
+
+/* ------------------------------------------------------------------ */
+/* Device pool: compressed volumes resident in HBM (Sec. 4)            */
+/* ------------------------------------------------------------------ */
+typedef struct csv_pool csv_pool;
+
+/* Create an empty pool on HIP device `device`.  Pools are immutable while
+ * decodes are in flight, so csv_decode_* may run concurrently on several
+ * streams; csv_pool_add_volume must not overlap them. */
+int csv_pool_create(csv_pool **pool, int device);
+void csv_pool_destroy(csv_pool *pool);
+
+/*
+ * Copy one container blob (host memory) into the pool's HBM.  The pool keeps
+ * its own copy, so the blob may be freed afterwards.  Its bricks get the
+ * global ids first_brick_id .. first_brick_id + n_bricks - 1 (volumes are
+ * numbered in the order they are added; each keeps its own table pair).
+ * Only 32^3 bricks (brick_log2 5) and scale_bits <= 11 are accepted.
+ * Synchronous.  Errors: CSV_EINVAL, CSV_ECORRUPT, CSV_ENOMEM, CSV_EHIP.
+ */
+int csv_pool_add_volume(csv_pool *pool, const uint8_t *blob, size_t blob_bytes, uint32_t *first_brick_id);
+
+typedef struct {
+    uint32_t n_volumes, n_bricks;
+    uint64_t device_bytes; /* HBM held by the pool */
+    int device;
+} csv_pool_info;
+int csv_pool_info_get(const csv_pool *pool, csv_pool_info *info);
+
+/*
+ * Output layout helper: for n requests at levels lods_host[i] (host memory,
+ * each 0..5), offsets[i] (may be NULL) receives the element offset of
+ * request i when bricks are packed back to back in request order, and
+ * *total the number of uint32 elements of that packing.
+ */
+int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total);
+
+/*
+ * THE HOT PATH: decode n bricks on the GPU, asynchronously on `stream`.
+ *   brick_ids    device, uint32[n], global pool ids
+ *   lods         device, uint8[n] levels of detail 0..5, or NULL: every
+ *                request uses lod_scalar (Sec. 3.4: LOD t reads only the
+ *                stream prefix of levels >= t; t = 5 is palette[0], Sec. 4)
+ *   out_offsets  device, uint64[n] element offsets into out, or NULL: request
+ *                i is written at i * (32 >> lod_scalar)^3 (requires lods NULL)
+ *   out          device, uint32 destination of the decoded blocks
+ * Decodes every brick bit-exactly: the result is level L_lod of the brick's
+ * resolution pyramid.  One workgroup per request in a single launch.
+ * Argument errors are returned synchronously.  Errors found on the device
+ * (bad brick id or level, malformed record) are recorded in the pool's
+ * error word (first error wins, read with csv_pool_last_error after the
+ * stream is synchronised) and the affected brick's output is zero-filled.
+ */
+int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
+                      const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
+
+/* Baseline: the same kernel with one launch per brick (grid of one
+ * workgroup, n launches on `stream`).  Same arguments and results. */
+int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
+                            const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
+
+/* First device-side error since the last call (synchronises the pool's
+ * device and clears the word): *code is CSV_OK or a CSV_E* code,
+ * *brick_id the global id it concerns (or the request index when the id
+ * itself was out of range). */
+int csv_pool_last_error(csv_pool *pool, int *code, uint32_t *brick_id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSV_H */

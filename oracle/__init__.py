@@ -66,6 +66,7 @@ def _load():
         L.orc_rans_encode.argtypes = [vp, u32, u32, u32, vp, u32, vp, vp, vp]
         L.orc_rans_decode.argtypes = [vp, u32, vp, u32, u32, vp, u32, u32, vp, vp]
         L.orc_free.argtypes = [vp]
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -84,6 +85,11 @@ class OracleError(RuntimeError):
 def _chk(rc):
     if rc != 0:
         raise OracleError(rc)
+
+
+def num_threads() -> int:
+    """Host threads the oracle's parallel loops (over bricks) use."""
+    return int(_load().orc_num_threads())
 
 
 # ---------------------------------------------------------------- volume --

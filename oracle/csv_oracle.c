@@ -35,10 +35,13 @@
  *       R_p 0, R_x 1, R_y 2, R_z 3, P_0 4, P_delta 5, P_a 6 (7 is invalid);
  *       a nibble is code | stop << 3.
  *   R8  Stream layout: one segment per child level, coarse to fine.  A
- *       segment holds the 8 operation nibbles of every expanded parent in
- *       Morton order, followed by the delta nibbles of that level's P_delta
- *       operations in the same order.  Segments of children at level >= 1
- *       use the interior table, the L_0 segment uses the leaf table.
+ *       segment holds the delta nibbles of that level's P_delta operations
+ *       (in operation order) followed by the 8 operation nibbles of every
+ *       expanded parent in Morton order: the encoder emits a delta before
+ *       its (op, stop) nibble, as in Alg. 2, grouped per level.  The decoder
+ *       knows how many deltas precede the operations: the segment length
+ *       minus 8 per expanded parent.  Segments of children at level >= 1 use
+ *       the interior table, the L_0 segment uses the leaf table.
  *   R9  rANS: 32-bit state, lower bound 2^16, 16-bit renormalisation words,
  *       table precision 2^scale_bits, encoding in reverse symbol order
  *       starting from state 2^16.  W interleaved states (W a power of two)
@@ -51,6 +54,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -213,10 +219,11 @@ static int encode_brick_stream(const uint32_t *brick, int N, brick_stream *s) {
     int rc = pyr_build(&p, brick, N);
     if (rc) return rc;
     rc = vpush(&s->pal, p.lab[N][0]); /* palette <- root label */
-    uint8_t *dl = (uint8_t *)malloc(2 * pow8(N) + 16); /* deltas of one level */
-    if (!dl) rc = ORC_ENOMEM;
+    uint8_t *dl = (uint8_t *)malloc(pow8(N) + 16); /* deltas of one level */
+    uint8_t *ops = (uint8_t *)malloc(pow8(N) + 16); /* (op, stop) nibbles of one level */
+    if (!dl || !ops) rc = ORC_ENOMEM;
     for (int l = N; l >= 1 && !rc; l--) {
-        uint32_t nd = 0;
+        uint32_t nd = 0, no = 0;
         for (uint64_t m = 0; m < pow8(N - l) && !rc; m++) {
             if (p.cst[l][m]) continue; /* constant subtree: no operations below */
             for (int k = 0; k < 8 && !rc; k++) {
@@ -228,13 +235,15 @@ static int encode_brick_stream(const uint32_t *brick, int N, brick_stream *s) {
                 if (op == OP_PA) rc = vpush(&s->pal, L);
                 if (op == OP_PD) dl[nd++] = (uint8_t)delta;
                 s->op_hist[op]++;
-                if (!rc) rc = spush(s, (uint8_t)(op | (stop << 3)));
+                ops[no++] = (uint8_t)(op | (stop << 3));
             }
         }
         for (uint32_t i = 0; i < nd && !rc; i++) rc = spush(s, dl[i]); /* R8 */
+        for (uint32_t i = 0; i < no && !rc; i++) rc = spush(s, ops[i]);
         s->cum[l - 1] = s->n;
     }
     free(dl);
+    free(ops);
     pyr_free(&p);
     if (rc) bs_free(s);
     return rc;
@@ -360,8 +369,9 @@ static int replay_brick(const uint8_t *sym, const uint32_t *cum, int N, const ui
         /* expanded parents of this level: their last child is still empty */
         uint64_t E = 0;
         for (uint64_t m = 0; m < pow8(N - l); m++) if (!set[m * sp + 7 * csp]) E++;
-        uint32_t opc = seg0, dc = seg0 + (uint32_t)(8 * E);
-        if (dc > seg1) { rc = ORC_ECORRUPT; break; }
+        if ((uint64_t)seg0 + 8 * E > seg1) { rc = ORC_ECORRUPT; break; }
+        uint32_t nd = seg1 - seg0 - (uint32_t)(8 * E);  /* deltas precede the operations (R8) */
+        uint32_t dc = seg0, opc = seg0 + nd;
         for (uint64_t m = 0; m < pow8(N - l) && !rc; m++) {
             uint64_t i = m * sp;
             if (set[i + 7 * csp]) continue; /* constant area */
@@ -392,7 +402,7 @@ static int replay_brick(const uint8_t *sym, const uint32_t *cum, int N, const ui
                 } else if (op == OP_P0) {
                     v = pal[ip];
                 } else if (op == OP_PD) {
-                    if (dc >= seg1) { rc = ORC_ECORRUPT; break; }
+                    if (dc >= seg0 + nd) { rc = ORC_ECORRUPT; break; }
                     uint32_t d = sym[dc++];
                     if (ip < d + 1) { rc = ORC_ECORRUPT; break; }
                     v = pal[ip - d - 1];
@@ -406,7 +416,7 @@ static int replay_brick(const uint8_t *sym, const uint32_t *cum, int N, const ui
                     for (uint64_t q = 0; q < csp; q++) { out[jo + q] = v; set[jo + q] = 1; }
             }
         }
-        if (!rc && (opc != seg0 + 8 * E || dc != seg1)) rc = ORC_ECORRUPT;
+        if (!rc && (opc != seg1 || dc != seg0 + nd)) rc = ORC_ECORRUPT;
     }
     if (!rc) {
         uint32_t G = 1u << (N - t);
@@ -484,6 +494,15 @@ static int build_record(const brick_stream *s, int N, const rans_tables *t, uint
 }
 
 void orc_free(void *p) { free(p); }
+
+/* host threads the parallel loops use */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 uint32_t orc_abi_version(void) { return 1; }
 
 /*

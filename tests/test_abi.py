@@ -1,0 +1,90 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, and its host-side pieces behave (no GPU calls here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "csv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(csv_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("csv_encode_volume", "csv_decode_bricks", "csv_decode_bricks_plain", "csv_pool_create",
+                 "csv_pool_add_volume", "csv_pool_last_error", "csv_blob_info", "csv_free"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2308_16619_amd as csv
+    L = csv.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.csv_abi_version() == 1
+
+
+def test_strerror():
+    import paper_2308_16619_amd as csv
+    assert csv.lib().csv_strerror(-3) == b"corrupt data"
+
+
+@pytest.mark.parametrize("case", ["cfg1", "random", "padded", "bits8", "k1", "b16"])
+def test_encoder_bytes_identical_to_oracle(orc, case):
+    import paper_2308_16619_amd as csv
+    kw = {}
+    if case == "cfg1":
+        vol = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+    elif case == "random":
+        vol = np.concatenate([synth.random_brick(32, 40, 5, smooth=2), synth.random_brick(32, 3, 6, smooth=5)], axis=2)
+    elif case == "padded":
+        vol = np.ascontiguousarray(synth.voronoi_bg(n=64, sites=30, seed=3)[:40, :50, :33])
+    elif case == "bits8":
+        vol = synth.voronoi_bg(n=64, sites=90, seed=4)
+        kw = dict(scale_bits=8, sample_stride=3)
+    elif case == "k1":
+        vol = synth.voronoi_bg(n=64, sites=90, seed=5)
+        kw = dict(lane_k=1, lane_max=16)
+    else:
+        vol = synth.voronoi_bg(n=64, sites=90, seed=6)
+        kw = dict(brick_log2=4)
+    mine = csv.encode_volume(vol, **kw)
+    ref = orc.encode_volume(vol, **{"scale_bits": 10, "lane_k": 64, **kw})
+    assert mine == ref
+
+
+def test_blob_info_matches_oracle(orc):
+    import paper_2308_16619_amd as csv
+    vol = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+    blob = csv.encode_volume(vol)
+    a, b = csv.blob_info(blob), orc.volume_info(blob)
+    for k in ("nx", "ny", "nz", "brick_log2", "nbx", "nby", "nbz", "n_bricks", "scale_bits", "lane_k", "lane_max",
+              "sample_stride"):
+        assert a[k] == b[k]
+    np.testing.assert_array_equal(a["freq"], b["freq"])
+    assert a["blob_bytes"] == len(blob)
+
+
+def test_blob_info_rejects_garbage():
+    import paper_2308_16619_amd as csv
+    with pytest.raises(csv.CsvError):
+        csv.blob_info(b"\0" * 256)
+
+
+def test_output_offsets():
+    import paper_2308_16619_amd as csv
+    off, tot = csv.output_offsets([0, 2, 1, 5, 3])
+    assert list(off) == [0, 32768, 32768 + 512, 32768 + 512 + 4096, 32768 + 512 + 4096 + 1]
+    assert tot == 32768 + 512 + 4096 + 1 + 64
+    with pytest.raises(csv.CsvError):
+        csv.output_offsets([6])

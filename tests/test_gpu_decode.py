@@ -1,0 +1,188 @@
+"""GPU parity: the HIP decoder against the oracle, element by element."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import gpu_decode, gpu_decode_uniform, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def log(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def csvlib():
+    torch_cuda()
+    import paper_2308_16619_amd as csv
+    csv.lib()
+    return csv
+
+
+@pytest.fixture(scope="module")
+def cfg1(orc):
+    vol = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+    return vol, orc.encode_volume(vol, scale_bits=10, lane_k=64)
+
+
+def test_config1_every_brick_every_lod(csvlib, orc, cfg1):
+    vol, blob = cfg1
+    pool = csvlib.Pool()
+    first = pool.add_volume(blob)
+    assert first == 0
+    for t in range(6):
+        log("cfg1 lod %d" % t)
+        got = gpu_decode_uniform(pool, np.arange(8), t)
+        want = orc.decode_bricks(blob, np.arange(8), [t] * 8)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_config1_mixed_lods_and_repeats(csvlib, orc, cfg1):
+    vol, blob = cfg1
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    rng = np.random.default_rng(3)
+    ids = rng.integers(0, 8, 300)
+    lods = rng.integers(0, 6, 300)
+    log("cfg1 mixed")
+    got, _ = gpu_decode(pool, ids, lods)
+    np.testing.assert_array_equal(got, orc.decode_bricks(blob, ids, lods))
+
+
+def golden_volume():
+    z, y, x = np.meshgrid(np.arange(32), np.arange(32), np.arange(32), indexing="ij")
+    A, B = 17, 4
+    uniform = np.full((32, 32, 32), A, np.uint32)
+    half = np.where(x < 16, A, B).astype(np.uint32)
+    checker = np.where((x + y + z) % 2 == 0, A, B).astype(np.uint32)
+    rng = np.random.default_rng(12)
+    distinct = rng.permutation(1 << 20)[:32768].astype(np.uint32).reshape(32, 32, 32) + 1  # P > 32768
+    many = rng.integers(1, 6000, size=(32, 32, 32)).astype(np.uint32)  # P > 4096, long word stream
+    delta_heavy = rng.integers(1, 18, size=(32, 32, 32)).astype(np.uint32)  # many P_delta
+    smooth = synth.random_brick(32, 9, 5, smooth=8)
+    bricks = [uniform, half, checker, distinct, many, delta_heavy, smooth, np.zeros((32, 32, 32), np.uint32)]
+    return np.concatenate(bricks, axis=2)
+
+
+def test_edge_bricks(csvlib, orc):
+    vol = golden_volume()
+    blob = orc.encode_volume(vol, scale_bits=11, lane_k=64)
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    n = vol.shape[2] // 32
+    for t in range(6):
+        log("edge bricks lod %d" % t)
+        got = gpu_decode_uniform(pool, np.arange(n), t)
+        np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(n), [t] * n))
+    # full LOD is lossless
+    got = gpu_decode_uniform(pool, np.arange(n), 0).reshape(n, 32, 32, 32)
+    for i in range(n):
+        np.testing.assert_array_equal(got[i], vol[:, :, 32 * i:32 * (i + 1)])
+
+
+@pytest.mark.parametrize("scale_bits,lane_k,lane_max", [(8, 1, 64), (11, 1000000, 64), (10, 16, 8), (11, 64, 1)])
+def test_format_parameters(csvlib, orc, scale_bits, lane_k, lane_max):
+    vol = synth.voronoi_bg(n=64, sites=300, bg=0.2, seed=scale_bits + lane_k)
+    blob = orc.encode_volume(vol, scale_bits=scale_bits, lane_k=lane_k, lane_max=lane_max)
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    for t in (0, 1, 3):
+        log("format S=%d K=%d Wmax=%d lod %d" % (scale_bits, lane_k, lane_max, t))
+        got = gpu_decode_uniform(pool, np.arange(8), t)
+        np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(8), [t] * 8))
+
+
+def test_plain_per_brick_launch_matches(csvlib, orc, cfg1):
+    vol, blob = cfg1
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    ids = np.array([7, 0, 3, 3, 5])
+    lods = np.array([0, 1, 2, 0, 4])
+    log("plain per-brick launches")
+    got, _ = gpu_decode(pool, ids, lods, plain=True)
+    np.testing.assert_array_equal(got, orc.decode_bricks(blob, ids, lods))
+
+
+def test_two_volumes_one_pool(csvlib, orc, cfg1):
+    vol, blob = cfg1
+    vol2 = synth.blobs(n=128, sites=12, amp=10, seed=4)
+    blob2 = orc.encode_volume(vol2, scale_bits=10, lane_k=32)
+    pool = csvlib.Pool()
+    assert pool.add_volume(blob) == 0
+    assert pool.add_volume(blob2) == 8
+    rng = np.random.default_rng(8)
+    ids = rng.integers(0, 8 + 64, 200)
+    lods = rng.integers(0, 3, 200)
+    log("two volumes")
+    got, _ = gpu_decode(pool, ids, lods)
+    want = []
+    for i, t in zip(ids, lods):
+        want.append(orc.decode_brick(blob, int(i), int(t)) if i < 8 else orc.decode_brick(blob2, int(i) - 8, int(t)))
+    np.testing.assert_array_equal(got, np.concatenate([w.ravel() for w in want]))
+
+
+def test_out_of_range_request_is_reported(csvlib, orc, cfg1):
+    vol, blob = cfg1
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    ids = np.array([1, 99, 2])
+    log("out of range id")
+    got, err = gpu_decode(pool, ids, [0, 0, 0], check_error=False)
+    assert err == (csvlib.CSV_ERANGE, 1)
+    np.testing.assert_array_equal(got[32768:65536], 0)
+    np.testing.assert_array_equal(got[:32768], orc.decode_brick(blob, 1, 0).ravel())
+    np.testing.assert_array_equal(got[65536:], orc.decode_brick(blob, 2, 0).ravel())
+    assert pool.last_error() == (0, 0)
+
+
+def test_corrupt_record_is_reported(csvlib, orc, cfg1):
+    vol, blob = cfg1
+    info = orc.volume_info(blob)
+    B = info["n_bricks"]
+    idx = np.frombuffer(blob, np.uint64, B + 1, 128)
+    rs = (128 + 8 * (B + 1) + 15) & ~15
+    w = np.frombuffer(blob, np.uint32, 8, rs + int(idx[4]))
+    P, W, nw = int(w[0]), int(w[1]), int(w[2])
+    bad = bytearray(blob)
+    bad[rs + int(idx[4]) + 4 * (8 + P + W) + 2 * (nw // 2)] ^= 0x10
+    pool = csvlib.Pool()
+    pool.add_volume(bytes(bad))
+    log("corrupt record")
+    got, err = gpu_decode(pool, [3, 4, 5], [0, 0, 0], check_error=False)
+    assert err == (csvlib.CSV_ECORRUPT, 4)
+    np.testing.assert_array_equal(got[32768:65536], 0)
+    np.testing.assert_array_equal(got[:32768], orc.decode_brick(blob, 3, 0).ravel())
+
+
+@pytest.fixture(scope="module")
+def cfg2(orc):
+    log("generating config 2 (512^3 cells)")
+    vol = synth.cells(n=512, grid=37, seed=2)
+    return vol, orc.encode_volume(vol, scale_bits=10, lane_k=64)
+
+
+def test_config2_full_lod_one_launch(csvlib, orc, cfg2):
+    vol, blob = cfg2
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    log("cfg2 full LOD, 4096 bricks, one launch")
+    got = gpu_decode_uniform(pool, np.arange(4096), 0)
+    want = orc.decode_bricks(blob, np.arange(4096), [0] * 4096)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("lod", [1, 2, 3])
+def test_config2_lower_lods(csvlib, orc, cfg2, lod):
+    vol, blob = cfg2
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    log("cfg2 lod %d" % lod)
+    got = gpu_decode_uniform(pool, np.arange(4096), lod)
+    np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(4096), [lod] * 4096))

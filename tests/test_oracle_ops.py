@@ -64,7 +64,9 @@ def check_brick(orc, brick):
         seg_end = int(cum[m_lvl])
         nodes = [morton_coords(m, N - l) for m in range(8 ** (N - l))]
         expanded = [c for c in nodes if not consts[l][c[2], c[1], c[0]]]
-        opc, dc = seg_start, seg_start + 8 * len(expanded)
+        nd = seg_end - seg_start - 8 * len(expanded)  # deltas come first
+        assert nd >= 0
+        dc, opc = seg_start, seg_start + nd
         for (X, Y, Z) in expanded:
             parent = levels[l][Z, Y, X]
             for k in range(8):
@@ -82,8 +84,8 @@ def check_brick(orc, brick):
                     dc += 1
                 if ORDER[op] == "Pa":
                     pal.append(L)
-        assert opc == seg_start + 8 * len(expanded)
-        assert dc == seg_end
+        assert opc == seg_end
+        assert dc == seg_start + nd
         seg_start = seg_end
     assert [int(v) for v in palette] == [int(v) for v in pal]
 
