@@ -110,6 +110,19 @@ def main():
     code, who = pool.last_error()
     assert code == 0, ("decode error", code, who)
 
+    # launch-shape sweep (logged): waves per workgroup x work queue
+    for shape in [(4, 1, 1), (5, 1, 1), (6, 1, 1), (8, 1, 1), (5, 1, 0), (5, 1, 1, 1)]:
+        pool.decode(ids, out, lod=lod, shape=shape)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            pool.decode(ids, out, lod=lod, shape=shape)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sms = ev0.elapsed_time(ev1) / args.steps
+        log("shape %s: %.4f ms/step, %.1f GB/s" % (shape, sms, out_bytes / (sms * 1e-3) / 1e9))
+    assert pool.last_error()[0] == 0
+
     # per-launch kernel time: one launch per step, so the event time per step
     achieved = (in_bytes + out_bytes) / (ms * 1e-3) / 1e9
 

@@ -93,9 +93,10 @@ int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info)
 /* ------------------------------------------------------------------ */
 typedef struct csv_pool csv_pool;
 
-/* Create an empty pool on HIP device `device`.  Pools are immutable while
- * decodes are in flight, so csv_decode_* may run concurrently on several
- * streams; csv_pool_add_volume must not overlap them. */
+/* Create an empty pool on HIP device `device`.  Decodes only read the pool,
+ * so csv_decode_* may run concurrently on several streams (each launch takes
+ * one of 256 device work counters in turn, so at most 256 launches may be in
+ * flight on one pool); csv_pool_add_volume must not overlap them. */
 int csv_pool_create(csv_pool **pool, int device);
 void csv_pool_destroy(csv_pool *pool);
 
@@ -134,7 +135,9 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
  *                i is written at i * (32 >> lod_scalar)^3 (requires lods NULL)
  *   out          device, uint32 destination of the decoded blocks
  * Decodes every brick bit-exactly: the result is level L_lod of the brick's
- * resolution pyramid.  One workgroup per request in a single launch.
+ * resolution pyramid.  One launch: a workgroup per compute unit whose
+ * wavefronts each take the next request from a device work counter and
+ * decode that brick alone.
  * Argument errors are returned synchronously.  Errors found on the device
  * (bad brick id or level, malformed record) are recorded in the pool's
  * error word (first error wins, read with csv_pool_last_error after the
@@ -148,11 +151,117 @@ int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uin
 int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                             const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
+/* Launch shape of a batched decode.  Every shape gives the same bytes. */
+typedef struct {
+    int waves_per_group;    /* wavefronts per workgroup: 4, 5, 6 or 8; each wave decodes its own
+                               bricks in an equal share of the LDS left after the decode tables */
+    uint32_t groups_per_cu; /* workgroups per compute unit in the grid (1..16) */
+    int use_queue;          /* 1: waves take requests from a device work counter; 0: static round robin */
+    int lpt_order;          /* 1: requests are first ordered longest-first (binned by log2 of their
+                               symbols + output voxels / 8; three small kernels before the decode) */
+    float ms;               /* csv_autotune: the measured time per launch of this shape */
+} csv_shape;
+
+/* csv_decode_bricks with an explicit launch shape.  Errors as csv_decode_bricks;
+ * CSV_EBUSY if lpt_order is requested inside a stream capture before the
+ * pool's order buffer was sized for n requests by an uncaptured call. */
+int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
+                             uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
+                             void *stream, const csv_shape *shape);
+
+/* The shape csv_decode_bricks uses (default {5, 1, 1, 0}). */
+int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape);
+int csv_pool_get_shape(const csv_pool *pool, csv_shape *shape);
+
+/* Autotuner: decodes the given request set (same arguments as
+ * csv_decode_bricks; `out` is overwritten) with every candidate shape, one
+ * warm-up and `reps` timed launches each (HIP events on `stream`), makes
+ * the fastest the pool's shape and returns it in *best (may be NULL).
+ * Synchronous.  Not allowed while `stream` is being captured. */
+int csv_autotune(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
+                 const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream, uint32_t reps,
+                 csv_shape *best);
+
+/* A decode captured once into a HIP graph and replayed.  The graph holds
+ * the pointers and n given here and the pool's shape at creation; replays
+ * decode the current contents of those buffers.  Replays of one graph must
+ * not overlap each other (they share one work counter).  `stream` is the
+ * capture stream (NULL: a private stream); launch on any stream. */
+typedef struct csv_graph csv_graph;
+int csv_graph_create(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
+                     const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream, csv_graph **graph);
+int csv_graph_launch(csv_graph *graph, void *stream);
+void csv_graph_destroy(csv_graph *graph);
+
 /* First device-side error since the last call (synchronises the pool's
  * device and clears the word): *code is CSV_OK or a CSV_E* code,
  * *brick_id the global id it concerns (or the request index when the id
  * itself was out of range). */
 int csv_pool_last_error(csv_pool *pool, int *code, uint32_t *brick_id);
+
+/* ------------------------------------------------------------------ */
+/* Serving (Sec. 4, Sec. 4.1: requested bricks are decoded into a GPU    */
+/* cache in parallel; here continuously, request by request)            */
+/* ------------------------------------------------------------------ */
+typedef struct csv_server csv_server;
+
+typedef struct {
+    uint64_t cache_bytes;    /* decoded-brick cache in HBM (LRU per LOD class, 128 KiB pages) */
+    uint64_t inflight_bytes; /* admission budget: decoded bytes of admitted, unfinished requests */
+    uint32_t max_batch;      /* bricks per launch */
+    uint32_t streams;        /* batches that may run on the GPU at once (1..16) */
+} csv_server_opts;
+
+/* Defaults: 1 GiB cache, 256 MiB in flight, 4096 bricks per batch, 4 streams. */
+void csv_server_opts_default(csv_server_opts *o);
+
+typedef struct {
+    uint32_t brick_id;     /* global pool id */
+    uint32_t lod;          /* 0..5 */
+    uint64_t tag;          /* returned with the completion */
+    uint64_t t_arrival_ns; /* csv_now_ns() clock */
+} csv_request;
+
+typedef struct {
+    uint64_t tag;
+    uint32_t brick_id, lod;
+    const uint32_t *data;  /* device pointer into the cache: (32 >> lod)^3 labels, dense [z][y][x];
+                              valid until the next csv_server_poll call returns */
+    uint32_t elems;
+    int32_t status;        /* CSV_OK, CSV_ERANGE (bad id or LOD) or a decode error */
+    uint32_t hit;          /* 1: served from the cache */
+    uint32_t pad;
+    uint64_t t_arrival_ns, t_done_ns;
+} csv_completion;
+
+typedef struct {
+    uint64_t requests, hits, misses, joined, completed, batches, evictions, rebuilds;
+    uint64_t decoded_bytes, cache_bytes_used;
+    double p50_us, p99_us, p50_miss_us, p99_miss_us, max_us; /* arrival -> completion */
+    int32_t error;
+} csv_stats;
+
+/* Clock of arrival and completion times (steady, nanoseconds). */
+uint64_t csv_now_ns(void);
+
+/* Start a server on a pool (its own worker thread, streams, HBM cache).
+ * The pool must outlive the server and gain no volumes while it runs. */
+int csv_server_create(csv_pool *pool, const csv_server_opts *opts, csv_server **server);
+/* Queue n requests (host memory; thread safe; returns at once). */
+int csv_server_submit(csv_server *server, const csv_request *requests, uint32_t n);
+/* Take up to cap completions (host memory).  Calling poll again releases the
+ * cache entries of the completions returned by the previous call; a client
+ * that stops polling eventually blocks admission. */
+int csv_server_poll(csv_server *server, csv_completion *completions, uint32_t cap, uint32_t *got);
+int csv_server_stats(csv_server *server, csv_stats *stats);
+/* Copy a completion's brick to host memory (elems uint32); valid until the
+ * next csv_server_poll, like the completion itself. */
+int csv_server_read(csv_server *server, const csv_completion *completion, uint32_t *host_dst);
+int csv_server_reset_stats(csv_server *server);
+/* Replay a trace in real time (arrival times relative to the start); see csv_server.cpp. */
+int csv_server_run_trace(csv_server *server, const csv_request *requests, uint32_t n, csv_completion *done,
+                         uint64_t timeout_ns, uint32_t *n_done);
+void csv_server_destroy(csv_server *server);
 
 #ifdef __cplusplus
 }

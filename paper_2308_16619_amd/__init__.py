@@ -39,6 +39,32 @@ class VolumeInfo(ctypes.Structure):
         ("freq", (ctypes.c_uint32 * 16) * 2), ("record_bytes", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64)]
 
 
+class Shape(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_int), ("groups_per_cu", ctypes.c_uint32), ("use_queue", ctypes.c_int),
+                ("lpt_order", ctypes.c_int), ("ms", ctypes.c_float)]
+
+    def as_tuple(self):
+        return (self.waves_per_group, self.groups_per_cu, self.use_queue, self.lpt_order)
+
+
+REQUEST_DTYPE = np.dtype([("brick_id", "<u4"), ("lod", "<u4"), ("tag", "<u8"), ("t_arrival_ns", "<u8")])
+COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("brick_id", "<u4"), ("lod", "<u4"), ("data", "<u8"), ("elems", "<u4"),
+                             ("status", "<i4"), ("hit", "<u4"), ("pad", "<u4"), ("t_arrival_ns", "<u8"),
+                             ("t_done_ns", "<u8")])
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("cache_bytes", ctypes.c_uint64), ("inflight_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("requests", "hits", "misses", "joined", "completed", "batches",
+                                              "evictions", "rebuilds", "decoded_bytes", "cache_bytes_used")] + [
+        (n, ctypes.c_double) for n in ("p50_us", "p99_us", "p50_miss_us", "p99_miss_us", "max_us")] + [
+        ("error", ctypes.c_int32)]
+
+
 class PoolInfo(ctypes.Structure):
     _fields_ = [("n_volumes", ctypes.c_uint32), ("n_bricks", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
                 ("device", ctypes.c_int)]
@@ -68,7 +94,24 @@ def lib():
         L.csv_output_elems.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
         for f in ("csv_decode_bricks", "csv_decode_bricks_plain"):
             getattr(L, f).argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
+        L.csv_decode_bricks_shaped.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(Shape)]
+        L.csv_pool_set_shape.argtypes = [vp, ctypes.POINTER(Shape)]
+        L.csv_pool_get_shape.argtypes = [vp, ctypes.POINTER(Shape)]
+        L.csv_autotune.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, u32, ctypes.POINTER(Shape)]
+        L.csv_graph_create.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(vp)]
+        L.csv_graph_launch.argtypes = [vp, vp]
+        L.csv_graph_destroy.argtypes = [vp]
         L.csv_pool_last_error.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(u32)]
+        L.csv_now_ns.restype = u64
+        L.csv_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+        L.csv_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        L.csv_server_submit.argtypes = [vp, vp, u32]
+        L.csv_server_poll.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
+        L.csv_server_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.csv_server_reset_stats.argtypes = [vp]
+        L.csv_server_read.argtypes = [vp, vp, vp]
+        L.csv_server_run_trace.argtypes = [vp, vp, u32, vp, u64, ctypes.POINTER(u32)]
+        L.csv_server_destroy.argtypes = [vp]
         if L.csv_abi_version() != 1:
             raise RuntimeError("libcsv.so ABI mismatch")
         _lib = L
@@ -154,19 +197,144 @@ class Pool:
         _chk(lib().csv_pool_info_get(self._p, ctypes.byref(i)), "csv_pool_info_get")
         return {f: getattr(i, f) for f, _ in PoolInfo._fields_}
 
-    def decode(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None, plain: bool = False):
+    def _args(self, ids, out, lods, lod, out_offsets, stream):
+        return [self._p, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(lods.data_ptr() if lods is not None else 0),
+                lod, ctypes.c_void_p(out_offsets.data_ptr() if out_offsets is not None else 0), int(ids.numel()),
+                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)]
+
+    def decode(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None, plain: bool = False, shape=None):
         """Decode bricks `ids` (int32 cuda tensor) into `out` (int32 cuda
         tensor viewed as uint32).  `lods`: uint8 cuda tensor or None (all at
         `lod`); `out_offsets`: int64 cuda tensor of element offsets (needed
-        with `lods`) or None (request i at i * (32 >> lod)^3)."""
-        fn = lib().csv_decode_bricks_plain if plain else lib().csv_decode_bricks
-        n = int(ids.numel())
-        _chk(fn(self._p, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(lods.data_ptr() if lods is not None else 0),
-                lod, ctypes.c_void_p(out_offsets.data_ptr() if out_offsets is not None else 0), n,
-                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "csv_decode_bricks")
+        with `lods`) or None (request i at i * (32 >> lod)^3).  `plain`: one
+        launch per brick.  `shape`: (waves_per_group, groups_per_cu,
+        use_queue[, lpt_order]) launch shape; default: the pool's shape."""
+        args = self._args(ids, out, lods, lod, out_offsets, stream)
+        if shape is not None:
+            sh = Shape(int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3]) if len(shape) > 3 else 0, 0.0)
+            _chk(lib().csv_decode_bricks_shaped(*args, ctypes.byref(sh)), "csv_decode_bricks_shaped")
+        elif plain:
+            _chk(lib().csv_decode_bricks_plain(*args), "csv_decode_bricks_plain")
+        else:
+            _chk(lib().csv_decode_bricks(*args), "csv_decode_bricks")
+
+    def set_shape(self, shape):
+        sh = Shape(int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3]) if len(shape) > 3 else 0, 0.0)
+        _chk(lib().csv_pool_set_shape(self._p, ctypes.byref(sh)), "csv_pool_set_shape")
+
+    def get_shape(self):
+        sh = Shape()
+        _chk(lib().csv_pool_get_shape(self._p, ctypes.byref(sh)), "csv_pool_get_shape")
+        return sh.as_tuple()
+
+    def autotune(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None, reps: int = 3):
+        """Time every launch shape on this request set; the fastest becomes
+        the pool's shape.  Returns (shape tuple, ms per launch)."""
+        sh = Shape()
+        _chk(lib().csv_autotune(*self._args(ids, out, lods, lod, out_offsets, stream), reps, ctypes.byref(sh)),
+             "csv_autotune")
+        return sh.as_tuple(), sh.ms
+
+    def graph(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None):
+        """Capture this decode into a replayable HIP graph."""
+        return Graph(self, self._args(ids, out, lods, lod, out_offsets, stream))
 
     def last_error(self):
         code = ctypes.c_int()
         bid = ctypes.c_uint32()
         _chk(lib().csv_pool_last_error(self._p, ctypes.byref(code), ctypes.byref(bid)), "csv_pool_last_error")
         return code.value, bid.value
+
+
+class Graph:
+    """A decode captured once and replayed with csv_graph_launch."""
+
+    def __init__(self, pool, args):
+        self._g = ctypes.c_void_p()
+        self._pool = pool  # keep the pool alive
+        _chk(lib().csv_graph_create(*args, ctypes.byref(self._g)), "csv_graph_create")
+
+    def launch(self, stream=None):
+        _chk(lib().csv_graph_launch(self._g, _stream_handle(stream)), "csv_graph_launch")
+
+    def close(self):
+        if self._g:
+            lib().csv_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def now_ns() -> int:
+    return int(lib().csv_now_ns())
+
+
+class Server:
+    """Serving loop over a pool: submit requests, poll completions."""
+
+    def __init__(self, pool, cache_bytes=1 << 30, inflight_bytes=256 << 20, max_batch=4096, streams=4):
+        o = ServerOpts(cache_bytes, inflight_bytes, max_batch, streams)
+        self._s = ctypes.c_void_p()
+        self._pool = pool
+        _chk(lib().csv_server_create(pool._p, ctypes.byref(o), ctypes.byref(self._s)), "csv_server_create")
+
+    @staticmethod
+    def requests(brick_ids, lods, tags=None, t_arrival_ns=None) -> np.ndarray:
+        n = len(brick_ids)
+        r = np.zeros(n, dtype=REQUEST_DTYPE)
+        r["brick_id"] = brick_ids
+        r["lod"] = lods
+        r["tag"] = np.arange(n) if tags is None else tags
+        r["t_arrival_ns"] = now_ns() if t_arrival_ns is None else t_arrival_ns
+        return r
+
+    def submit(self, reqs: np.ndarray):
+        reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        _chk(lib().csv_server_submit(self._s, _np_ptr(reqs), len(reqs)), "csv_server_submit")
+
+    def poll(self, cap: int = 65536) -> np.ndarray:
+        buf = np.zeros(cap, dtype=COMPLETION_DTYPE)
+        got = ctypes.c_uint32()
+        _chk(lib().csv_server_poll(self._s, _np_ptr(buf), cap, ctypes.byref(got)), "csv_server_poll")
+        return buf[:got.value]
+
+    def read(self, completion) -> np.ndarray:
+        """The decoded brick of one completion (valid until the next poll)."""
+        c = np.ascontiguousarray(np.asarray(completion, dtype=COMPLETION_DTYPE).reshape(1))
+        out = np.zeros(int(c["elems"][0]), dtype=np.uint32)
+        _chk(lib().csv_server_read(self._s, _np_ptr(c), _np_ptr(out)), "csv_server_read")
+        return out
+
+    def run_trace(self, reqs: np.ndarray, collect: bool = False, timeout_s: float = 10.0):
+        reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        done = np.zeros(len(reqs), dtype=COMPLETION_DTYPE) if collect else None
+        got = ctypes.c_uint32()
+        rc = lib().csv_server_run_trace(self._s, _np_ptr(reqs), len(reqs),
+                                        _np_ptr(done) if collect else ctypes.c_void_p(0), int(timeout_s * 1e9),
+                                        ctypes.byref(got))
+        if rc not in (CSV_OK, CSV_EBUSY):
+            _chk(rc, "csv_server_run_trace")
+        return (done[:got.value] if collect else None), got.value
+
+    def stats(self) -> dict:
+        st = Stats()
+        _chk(lib().csv_server_stats(self._s, ctypes.byref(st)), "csv_server_stats")
+        return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+    def reset_stats(self):
+        _chk(lib().csv_server_reset_stats(self._s), "csv_server_reset_stats")
+
+    def close(self):
+        if self._s:
+            lib().csv_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("csv_decode.hip", "csv_encode.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("csv_decode.hip", "csv_encode.cpp", "csv_server.cpp")]
 LIB = os.path.join(HERE, "libcsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -15,11 +15,13 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-I", os.path.join(ROOT, "include"), "-pthread"]
 
 
-def build() -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call([HIPCC] + FLAGS + SRC + ["-o", tmp])
-    os.replace(tmp, LIB)
-    return LIB
+def build(out: str = LIB, extra=()) -> str:
+    """Compile the library; `extra` adds flags (e.g. -DCSV_PHASE_TIMING for
+    the per-phase clock build)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC] + FLAGS + list(extra) + SRC + ["-o", tmp])
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -1,0 +1,592 @@
+// Serving loop: brick requests arrive as a renderer issues them (Sec. 4: a
+// frame's raymarcher requests missing (brick, LOD) pairs, the GPU decodes
+// them into a cache, the next frame uses them; Sec. 4.1: the cache).  Here a
+// worker thread takes requests continuously:
+//   - a hit in the decoded-brick cache (HBM) completes at once;
+//   - a request for a brick that is being decoded joins that decode;
+//   - a miss is admitted while the decoded bytes in flight stay within the
+//     budget and the cache can give it a slot (LRU eviction within its LOD
+//     class; when nothing of that class can be evicted and the cache is
+//     full, the cache is rebuilt, as the paper's cache does on
+//     fragmentation), then joins the batch being formed;
+//   - a batch is launched as soon as a device stream is free, so batches
+//     formed while others run overlap on the GPU (continuous batching).
+// Completion time is when the worker sees the batch's event complete.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/csv.h"
+
+namespace {
+
+constexpr int kClasses = 6;  // LOD 0..5: (32 >> t)^3 uint32
+constexpr uint64_t kPage = 32 * 32 * 32 * 4;
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+uint64_t class_bytes(int t) {
+    const uint64_t g = 32u >> t;
+    return g * g * g * 4;
+}
+
+enum State : uint8_t { kFree = 0, kDecoding = 1, kValid = 2 };
+
+struct Entry {
+    uint32_t brick = 0;
+    uint8_t lod = 0;
+    State state = kFree;
+    uint32_t pins = 0;               // completions not yet released by the next poll
+    uint64_t slot = 0;               // byte offset in the cache
+    std::list<uint32_t>::iterator lru;
+    bool in_lru = false;
+    std::vector<uint32_t> waiters;   // indices into the request table
+};
+
+struct Pending {
+    csv_request r;
+    uint32_t idx;  // request slot
+};
+
+struct Batch {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint32_t *h_ids = nullptr;
+    uint8_t *h_lods = nullptr;
+    uint64_t *h_off = nullptr;
+    uint32_t *d_ids = nullptr;
+    uint8_t *d_lods = nullptr;
+    uint64_t *d_off = nullptr;
+    std::vector<uint32_t> entries;  // entry ids decoded by this batch
+    uint64_t bytes = 0;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct csv_server {
+    csv_pool *pool = nullptr;
+    csv_server_opts opts{};
+    int device = 0;
+    uint32_t n_bricks = 0;
+    uint8_t *d_cache = nullptr;
+    // cache allocator: pages carved per LOD class, free stacks, per-class LRU
+    uint64_t top = 0;
+    std::vector<uint64_t> free_slots[kClasses];
+    std::list<uint32_t> lru[kClasses];  // front = most recent
+    std::vector<Entry> entries;
+    std::vector<uint32_t> free_entries;
+    std::vector<int32_t> index;  // brick * 6 + lod -> entry id or -1
+    // requests
+    std::mutex in_mu;
+    std::vector<csv_request> inbox;
+    std::deque<Pending> pending;
+    std::vector<csv_request> reqs;   // request table (worker)
+    std::vector<uint32_t> free_reqs;
+    std::mutex out_mu;
+    std::vector<csv_completion> outbox;
+    std::vector<int32_t> outbox_entry;  // cache entry each completion points into (-1: none)
+    std::vector<uint32_t> delivered;    // entries of the completions handed out by the last poll
+    std::vector<uint32_t> to_unpin;     // entries whose completions the client has released
+    // batches
+    std::vector<Batch> batches;
+    Batch *forming = nullptr;
+    uint64_t inflight = 0;
+    // stats
+    std::mutex st_mu;
+    std::vector<float> lat_all, lat_miss;
+    uint64_t n_req = 0, n_hit = 0, n_miss = 0, n_join = 0, n_batches = 0, n_evict = 0, n_rebuild = 0,
+             decoded_bytes = 0, n_launch_err = 0;
+    std::atomic<uint64_t> submitted{0}, completed{0};
+    std::atomic<bool> stop{false};
+    std::thread worker;
+    int error = CSV_OK;
+};
+
+namespace {
+
+void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint64_t t) {
+    const csv_request &r = s->reqs[ridx];
+    csv_completion c;
+    std::memset(&c, 0, sizeof(c));
+    c.tag = r.tag;
+    c.brick_id = r.brick_id;
+    c.lod = r.lod;
+    c.status = status;
+    c.hit = hit ? 1u : 0u;
+    c.t_arrival_ns = r.t_arrival_ns;
+    c.t_done_ns = t;
+    if (e && status == CSV_OK) {
+        c.data = reinterpret_cast<const uint32_t *>(s->d_cache + e->slot);
+        c.elems = (uint32_t)(class_bytes(e->lod) / 4);
+        s->entries[(size_t)(e - s->entries.data())].pins++;  // until the client releases it
+    }
+    const float us = (float)((double)(t - r.t_arrival_ns) * 1e-3);
+    {
+        std::lock_guard<std::mutex> lk(s->st_mu);
+        s->lat_all.push_back(us);
+        if (!hit) s->lat_miss.push_back(us);
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->out_mu);
+        s->outbox.push_back(c);
+        s->outbox_entry.push_back((e && status == CSV_OK) ? (int32_t)(e - s->entries.data()) : -1);
+    }
+    s->free_reqs.push_back(ridx);
+    s->completed.fetch_add(1, std::memory_order_relaxed);
+}
+
+void lru_touch(csv_server *s, uint32_t id) {
+    Entry &e = s->entries[id];
+    auto &L = s->lru[e.lod];
+    if (e.in_lru) L.erase(e.lru);
+    L.push_front(id);
+    e.lru = L.begin();
+    e.in_lru = true;
+}
+
+void drop_entry(csv_server *s, uint32_t id) {
+    Entry &e = s->entries[id];
+    if (e.in_lru) s->lru[e.lod].erase(e.lru);
+    e.in_lru = false;
+    s->index[(size_t)e.brick * kClasses + e.lod] = -1;
+    e.state = kFree;
+    e.waiters.clear();
+    s->free_entries.push_back(id);
+}
+
+// a cache slot for LOD class t, or false
+bool alloc_slot(csv_server *s, int t, uint64_t *slot) {
+    auto &fs = s->free_slots[t];
+    if (!fs.empty()) {
+        *slot = fs.back();
+        fs.pop_back();
+        return true;
+    }
+    if (s->top + kPage <= s->opts.cache_bytes) {
+        const uint64_t sz = class_bytes(t);
+        for (uint64_t o = kPage; o >= 2 * sz; o -= sz) fs.push_back(s->top + o - sz);
+        *slot = s->top;
+        s->top += kPage;
+        return true;
+    }
+    // evict the least recently used unpinned entry of the same class
+    auto &L = s->lru[t];
+    for (auto it = L.rbegin(); it != L.rend(); ++it) {
+        Entry &e = s->entries[*it];
+        if (e.pins == 0 && e.state == kValid) {
+            *slot = e.slot;
+            drop_entry(s, *it);
+            s->n_evict++;
+            return true;
+        }
+    }
+    return false;
+}
+
+// drop every valid unpinned entry and start the allocator afresh; only when
+// nothing is in flight or pinned
+bool rebuild(csv_server *s) {
+    if (s->inflight || (s->forming && !s->forming->entries.empty())) return false;
+    for (uint32_t id = 0; id < s->entries.size(); id++)
+        if (s->entries[id].state != kFree && s->entries[id].pins) return false;
+    for (uint32_t id = 0; id < s->entries.size(); id++)
+        if (s->entries[id].state == kValid) drop_entry(s, id);
+    for (auto &f : s->free_slots) f.clear();
+    s->top = 0;
+    s->n_rebuild++;
+    return true;
+}
+
+Batch *free_batch(csv_server *s) {
+    for (auto &b : s->batches)
+        if (!b.busy && &b != s->forming) return &b;
+    return nullptr;
+}
+
+void launch_batch(csv_server *s, Batch *b) {
+    const uint32_t n = (uint32_t)b->entries.size();
+    for (uint32_t i = 0; i < n; i++) {
+        const Entry &e = s->entries[b->entries[i]];
+        b->h_ids[i] = e.brick;
+        b->h_lods[i] = e.lod;
+        b->h_off[i] = e.slot / 4;
+    }
+    int rc = CSV_OK;
+    if (hipMemcpyAsync(b->d_ids, b->h_ids, 4ull * n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->d_lods, b->h_lods, n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->d_off, b->h_off, 8ull * n, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        rc = CSV_EHIP;
+    if (!rc)
+        rc = csv_decode_bricks(s->pool, b->d_ids, b->d_lods, 0, b->d_off, n,
+                               reinterpret_cast<uint32_t *>(s->d_cache), b->stream);
+    if (!rc && hipEventRecord(b->done, b->stream) != hipSuccess) rc = CSV_EHIP;
+    if (rc) {
+        s->n_launch_err++;
+        s->error = rc;
+    }
+    b->busy = true;
+    s->n_batches++;
+}
+
+void retire(csv_server *s, Batch &b, uint64_t t) {
+    for (uint32_t id : b.entries) {
+        Entry &e = s->entries[id];
+        e.state = kValid;
+        lru_touch(s, id);
+        std::vector<uint32_t> ws;
+        ws.swap(e.waiters);
+        for (uint32_t w : ws) complete(s, w, &s->entries[id], s->error ? s->error : CSV_OK, false, t);
+    }
+    s->decoded_bytes += b.bytes;
+    s->inflight -= b.bytes;
+    b.entries.clear();
+    b.bytes = 0;
+    b.busy = false;
+}
+
+// one request: true if handled (completed, joined or admitted), false if it must wait
+bool admit(csv_server *s, const Pending &p) {
+    const csv_request &r = p.r;
+    if (r.brick_id >= s->n_bricks || r.lod > 5) {
+        complete(s, p.idx, nullptr, CSV_ERANGE, false, now_ns());
+        return true;
+    }
+    const size_t key = (size_t)r.brick_id * kClasses + r.lod;
+    int32_t id = s->index[key];
+    if (id >= 0) {
+        Entry &e = s->entries[id];
+        if (e.state == kValid) {
+            lru_touch(s, (uint32_t)id);
+            complete(s, p.idx, &e, CSV_OK, true, now_ns());
+            std::lock_guard<std::mutex> lk(s->st_mu);
+            s->n_hit++;
+        } else {
+            e.waiters.push_back(p.idx);
+            std::lock_guard<std::mutex> lk(s->st_mu);
+            s->n_join++;
+        }
+        return true;
+    }
+    const uint64_t bytes = class_bytes(r.lod);
+    if (s->inflight + bytes > s->opts.inflight_bytes && s->inflight > 0) return false;
+    if (!s->forming) s->forming = free_batch(s);
+    if (!s->forming) return false;
+    uint64_t slot;
+    if (!alloc_slot(s, r.lod, &slot)) {
+        if (!rebuild(s) || !alloc_slot(s, r.lod, &slot)) return false;
+    }
+    uint32_t nid;
+    if (!s->free_entries.empty()) {
+        nid = s->free_entries.back();
+        s->free_entries.pop_back();
+    } else {
+        nid = (uint32_t)s->entries.size();
+        s->entries.emplace_back();
+    }
+    Entry &e = s->entries[nid];
+    e.brick = r.brick_id;
+    e.lod = r.lod;
+    e.state = kDecoding;
+    e.pins = 0;
+    e.slot = slot;
+    e.in_lru = false;
+    e.waiters.assign(1, p.idx);
+    s->index[key] = (int32_t)nid;
+    s->forming->entries.push_back(nid);
+    s->forming->bytes += bytes;
+    s->inflight += bytes;
+    {
+        std::lock_guard<std::mutex> lk(s->st_mu);
+        s->n_miss++;
+    }
+    if (s->forming->entries.size() >= s->opts.max_batch) {
+        launch_batch(s, s->forming);
+        s->forming = nullptr;
+    }
+    return true;
+}
+
+void worker_main(csv_server *s) {
+    (void)hipSetDevice(s->device);
+    std::vector<csv_request> take;
+    uint32_t idle = 0;
+    while (!s->stop.load(std::memory_order_acquire)) {
+        bool work = false;
+        {
+            std::lock_guard<std::mutex> lk(s->in_mu);
+            take.swap(s->inbox);
+        }
+        for (const csv_request &r : take) {
+            uint32_t idx;
+            if (!s->free_reqs.empty()) {
+                idx = s->free_reqs.back();
+                s->free_reqs.pop_back();
+                s->reqs[idx] = r;
+            } else {
+                idx = (uint32_t)s->reqs.size();
+                s->reqs.push_back(r);
+            }
+            s->pending.push_back(Pending{r, idx});
+            std::lock_guard<std::mutex> lk(s->st_mu);
+            s->n_req++;
+        }
+        work |= !take.empty();
+        take.clear();
+        // completed batches
+        for (auto &b : s->batches) {
+            if (b.busy && hipEventQuery(b.done) == hipSuccess) {
+                retire(s, b, now_ns());
+                work = true;
+            }
+        }
+        // entries pinned by completions the client has released
+        {
+            std::vector<uint32_t> rel;
+            {
+                std::lock_guard<std::mutex> lk(s->out_mu);
+                rel.swap(s->to_unpin);
+            }
+            for (uint32_t id : rel)
+                if (s->entries[id].pins) s->entries[id].pins--;
+        }
+        // admission, in arrival order
+        while (!s->pending.empty()) {
+            if (!admit(s, s->pending.front())) break;
+            s->pending.pop_front();
+            work = true;
+        }
+        // continuous batching: launch what has formed as soon as a stream is free
+        if (s->forming && !s->forming->entries.empty()) {
+            launch_batch(s, s->forming);
+            s->forming = nullptr;
+            work = true;
+        }
+        if (work) {
+            idle = 0;
+        } else if (++idle > 2000) {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        } else {
+            std::this_thread::yield();
+        }
+    }
+}
+
+double pct(std::vector<float> v, double q) {
+    if (v.empty()) return 0.0;
+    const size_t k = std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + (long)k, v.end());
+    return v[k];
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t csv_now_ns(void) { return now_ns(); }
+
+void csv_server_opts_default(csv_server_opts *o) {
+    if (!o) return;
+    o->cache_bytes = 1ull << 30;
+    o->inflight_bytes = 256ull << 20;
+    o->max_batch = 4096;
+    o->streams = 4;
+}
+
+int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out) {
+    if (!pool || !out) return CSV_EINVAL;
+    csv_server_opts opts;
+    csv_server_opts_default(&opts);
+    if (o) opts = *o;
+    if (opts.cache_bytes < kPage || opts.max_batch < 1 || opts.streams < 1 || opts.streams > 16 ||
+        opts.inflight_bytes < kPage)
+        return CSV_EINVAL;
+    csv_pool_info info;
+    int rc = csv_pool_info_get(pool, &info);
+    if (rc) return rc;
+    if (info.n_bricks == 0) return CSV_EINVAL;
+    csv_server *s = new (std::nothrow) csv_server;
+    if (!s) return CSV_ENOMEM;
+    s->pool = pool;
+    s->opts = opts;
+    s->opts.cache_bytes = opts.cache_bytes / kPage * kPage;
+    s->device = info.device;
+    s->n_bricks = info.n_bricks;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    rc = CSV_OK;
+    try {
+        s->index.assign((size_t)info.n_bricks * kClasses, -1);
+    } catch (const std::bad_alloc &) {
+        rc = CSV_ENOMEM;
+    }
+    if (!rc && hipMalloc(reinterpret_cast<void **>(&s->d_cache), s->opts.cache_bytes) != hipSuccess) rc = CSV_ENOMEM;
+    s->batches.resize(opts.streams + 1);  // one more than streams: a batch can form while all run
+    for (auto &b : s->batches) {
+        if (rc) break;
+        const size_t n = opts.max_batch;
+        if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&b.h_ids), 4 * n, 0) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&b.h_lods), n, 0) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&b.h_off), 8 * n, 0) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&b.d_ids), 4 * n) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&b.d_lods), n) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&b.d_off), 8 * n) != hipSuccess)
+            rc = CSV_ENOMEM;
+    }
+    (void)hipSetDevice(prev);
+    if (rc) {
+        csv_server_destroy(s);
+        return rc;
+    }
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return CSV_OK;
+}
+
+int csv_server_submit(csv_server *s, const csv_request *r, uint32_t n) {
+    if (!s || (n && !r)) return CSV_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->in_mu);
+        s->inbox.insert(s->inbox.end(), r, r + n);
+    }
+    s->submitted.fetch_add(n, std::memory_order_relaxed);
+    return CSV_OK;
+}
+
+int csv_server_poll(csv_server *s, csv_completion *c, uint32_t cap, uint32_t *got) {
+    if (!s || !got || (cap && !c)) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(s->out_mu);
+    // the completions handed out by the previous poll are released now
+    s->to_unpin.insert(s->to_unpin.end(), s->delivered.begin(), s->delivered.end());
+    s->delivered.clear();
+    const uint32_t k = (uint32_t)std::min<size_t>(cap, s->outbox.size());
+    std::copy(s->outbox.begin(), s->outbox.begin() + k, c);
+    for (uint32_t i = 0; i < k; i++)
+        if (s->outbox_entry[i] >= 0) s->delivered.push_back((uint32_t)s->outbox_entry[i]);
+    s->outbox.erase(s->outbox.begin(), s->outbox.begin() + k);
+    s->outbox_entry.erase(s->outbox_entry.begin(), s->outbox_entry.begin() + k);
+    *got = k;
+    return CSV_OK;
+}
+
+int csv_server_stats(csv_server *s, csv_stats *st) {
+    if (!s || !st) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(s->st_mu);
+    std::memset(st, 0, sizeof(*st));
+    st->requests = s->n_req;
+    st->hits = s->n_hit;
+    st->misses = s->n_miss;
+    st->joined = s->n_join;
+    st->completed = s->completed.load();
+    st->batches = s->n_batches;
+    st->evictions = s->n_evict;
+    st->rebuilds = s->n_rebuild;
+    st->decoded_bytes = s->decoded_bytes;
+    st->cache_bytes_used = s->top;
+    st->p50_us = pct(s->lat_all, 0.50);
+    st->p99_us = pct(s->lat_all, 0.99);
+    st->p50_miss_us = pct(s->lat_miss, 0.50);
+    st->p99_miss_us = pct(s->lat_miss, 0.99);
+    st->max_us = s->lat_all.empty() ? 0.0 : *std::max_element(s->lat_all.begin(), s->lat_all.end());
+    st->error = s->error;
+    return CSV_OK;
+}
+
+int csv_server_reset_stats(csv_server *s) {
+    if (!s) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(s->st_mu);
+    s->lat_all.clear();
+    s->lat_miss.clear();
+    s->n_req = s->n_hit = s->n_miss = s->n_join = s->n_batches = s->n_evict = s->n_rebuild = 0;
+    s->decoded_bytes = 0;
+    return CSV_OK;
+}
+
+void csv_server_destroy(csv_server *s) {
+    if (!s) return;
+    s->stop.store(true, std::memory_order_release);
+    if (s->worker.joinable()) s->worker.join();
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    for (auto &b : s->batches) {
+        if (b.stream) (void)hipStreamSynchronize(b.stream);
+        if (b.done) (void)hipEventDestroy(b.done);
+        if (b.stream) (void)hipStreamDestroy(b.stream);
+        (void)hipHostFree(b.h_ids);
+        (void)hipHostFree(b.h_lods);
+        (void)hipHostFree(b.h_off);
+        (void)hipFree(b.d_ids);
+        (void)hipFree(b.d_lods);
+        (void)hipFree(b.d_off);
+    }
+    (void)hipFree(s->d_cache);
+    (void)hipSetDevice(prev);
+    delete s;
+}
+
+int csv_server_read(csv_server *s, const csv_completion *c, uint32_t *host_dst) {
+    if (!s || !c || !host_dst || !c->data) return CSV_EINVAL;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    const hipError_t e = hipMemcpy(host_dst, c->data, 4ull * c->elems, hipMemcpyDeviceToHost);
+    (void)hipSetDevice(prev);
+    return e == hipSuccess ? CSV_OK : CSV_EHIP;
+}
+
+/*
+ * Replay a request trace in real time from the calling thread: request i
+ * is submitted once csv_now_ns() reaches start + reqs[i].t_arrival_ns (its
+ * arrival time is then set to that absolute time), completions are drained
+ * as they come (and copied to `done` when not NULL), until all n requests
+ * completed or timeout_ns passed since the last request arrived.
+ */
+int csv_server_run_trace(csv_server *s, const csv_request *reqs, uint32_t n, csv_completion *done,
+                         uint64_t timeout_ns, uint32_t *n_done) {
+    if (!s || (n && !reqs)) return CSV_EINVAL;
+    std::vector<csv_request> batch;
+    std::vector<csv_completion> buf(4096);
+    const uint64_t t0 = now_ns();
+    uint32_t next = 0, got_total = 0;
+    uint64_t last_arrival = t0;
+    while (got_total < n) {
+        const uint64_t t = now_ns();
+        batch.clear();
+        while (next < n && t0 + reqs[next].t_arrival_ns <= t) {
+            csv_request r = reqs[next++];
+            r.t_arrival_ns += t0;
+            last_arrival = r.t_arrival_ns;
+            batch.push_back(r);
+        }
+        if (!batch.empty()) csv_server_submit(s, batch.data(), (uint32_t)batch.size());
+        uint32_t got = 0;
+        csv_server_poll(s, buf.data(), (uint32_t)buf.size(), &got);
+        if (done && got) std::copy(buf.begin(), buf.begin() + got, done + got_total);
+        got_total += got;
+        if (next == n && t - last_arrival > timeout_ns) break;
+        if (!got && batch.empty()) std::this_thread::yield();
+    }
+    uint32_t got = 0;
+    csv_server_poll(s, buf.data(), 0, &got);  // release the last completions
+    if (n_done) *n_done = got_total;
+    return got_total == n ? CSV_OK : CSV_EBUSY;
+}
+
+}  // extern "C"

@@ -186,3 +186,90 @@ def test_config2_lower_lods(csvlib, orc, cfg2, lod):
     log("cfg2 lod %d" % lod)
     got = gpu_decode_uniform(pool, np.arange(4096), lod)
     np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(4096), [lod] * 4096))
+
+
+@pytest.mark.parametrize("shape", [(4, 1, 1), (5, 1, 0), (6, 1, 1), (8, 1, 1), (8, 2, 0)])
+def test_launch_shapes_agree(csvlib, orc, cfg2, shape):
+    # every launch shape decodes the same bytes; 8 waves per group leave an
+    # LDS arena too small for the densest bricks, which then take the
+    # global-memory arena path
+    torch = torch_cuda()
+    vol, blob = cfg2
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    ids = np.arange(0, 4096, 3, dtype=np.uint32)
+    log("cfg2 shape %s" % (shape,))
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    out = torch.full((len(ids) * 32768,), -1, dtype=torch.int32, device="cuda")
+    pool.decode(d_ids, out, lod=0, shape=shape)
+    torch.cuda.synchronize()
+    assert pool.last_error() == (0, 0)
+    want = orc.decode_bricks(blob, ids, [0] * len(ids))
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
+
+
+def mixed_requests(seed, n, n_bricks):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, n_bricks, n).astype(np.uint32), rng.integers(0, 3, n).astype(np.uint8)
+
+
+def test_longest_first_order_and_autotune(csvlib, orc, cfg1, cfg2):
+    # mixed LODs over two volumes: the longest-first order and every tuned
+    # shape give the oracle's bytes
+    torch = torch_cuda()
+    pool = csvlib.Pool()
+    pool.add_volume(cfg1[1])
+    pool.add_volume(cfg2[1])
+    ids, lods = mixed_requests(11, 3000, 8 + 4096)
+    off, tot = csvlib.output_offsets(lods)
+    want = np.concatenate([orc.decode_brick(cfg1[1], int(i), int(t)).ravel() if i < 8 else
+                           orc.decode_brick(cfg2[1], int(i) - 8, int(t)).ravel() for i, t in zip(ids, lods)])
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    d_lods = torch.from_numpy(lods.copy()).cuda()
+    d_off = torch.from_numpy(off.view(np.int64)).cuda()
+    out = torch.full((tot,), -1, dtype=torch.int32, device="cuda")
+    log("lpt order")
+    pool.decode(d_ids, out, lods=d_lods, out_offsets=d_off, shape=(5, 1, 1, 1))
+    torch.cuda.synchronize()
+    assert pool.last_error() == (0, 0)
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
+    log("autotune")
+    out.fill_(-1)
+    shape, ms = pool.autotune(d_ids, out, lods=d_lods, out_offsets=d_off, reps=2)
+    assert pool.get_shape() == shape and ms > 0
+    out.fill_(-1)
+    pool.decode(d_ids, out, lods=d_lods, out_offsets=d_off)
+    torch.cuda.synchronize()
+    assert pool.last_error() == (0, 0)
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
+
+
+@pytest.mark.parametrize("shape", [(5, 1, 1, 0), (6, 1, 1, 1)])
+def test_graph_replays(csvlib, orc, cfg2, shape):
+    # a captured decode replayed several times, with eager work and
+    # synchronisation in between; every replay must match
+    torch = torch_cuda()
+    vol, blob = cfg2
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    pool.set_shape(shape)
+    ids, lods = mixed_requests(5, 1500, 4096)
+    off, tot = csvlib.output_offsets(lods)
+    want = orc.decode_bricks(blob, ids, lods)
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    d_lods = torch.from_numpy(lods.copy()).cuda()
+    d_off = torch.from_numpy(off.view(np.int64)).cuda()
+    out = torch.full((tot,), -1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    log("graph capture %s" % (shape,))
+    g = pool.graph(d_ids, out, lods=d_lods, out_offsets=d_off, stream=s)
+    for rep in range(4):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        assert pool.last_error() == (0, 0)
+        np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want, err_msg="replay %d" % rep)
+        pool.decode(d_ids[:7].contiguous(), torch.empty(7 * 32768, dtype=torch.int32, device="cuda"), lod=0)
+        torch.cuda.synchronize()
+    g.close()

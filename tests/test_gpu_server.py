@@ -1,0 +1,109 @@
+"""GPU tests of the serving loop: every completed brick equals the oracle's
+decode of that brick alone, whatever else was in flight."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print("[gpu-test] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup(orc):
+    torch_cuda()
+    import paper_2308_16619_amd as csv
+    csv.lib()
+    v1 = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+    v2 = synth.cells(n=256, grid=19, seed=7)
+    b1 = orc.encode_volume(v1, scale_bits=10, lane_k=64)
+    b2 = orc.encode_volume(v2, scale_bits=10, lane_k=64)
+    return csv, b1, b2
+
+
+def wait_all(server, n, timeout=60.0):
+    out, t0 = [], time.time()
+    while sum(len(o) for o in out) < n:
+        c = server.poll()
+        if len(c):
+            out.append(c.copy())
+            yield c
+        elif time.time() - t0 > timeout:
+            raise TimeoutError("server completed %d of %d" % (sum(len(o) for o in out), n))
+        else:
+            time.sleep(0.0005)
+
+
+def oracle_brick(orc, b1, b2, bid, lod):
+    return (orc.decode_brick(b1, int(bid), int(lod)) if bid < 8 else orc.decode_brick(b2, int(bid) - 8, int(lod))).ravel()
+
+
+@pytest.mark.parametrize("cache_mb,streams", [(256, 4), (2, 2)])
+def test_alone_equals_mix(setup, orc, cache_mb, streams):
+    csv, b1, b2 = setup
+    pool = csv.Pool()
+    pool.add_volume(b1)
+    pool.add_volume(b2)
+    n_b = 8 + 512
+    rng = np.random.default_rng(cache_mb)
+    n = 3000
+    ids = rng.integers(0, n_b, n).astype(np.uint32)
+    lods = rng.choice([0, 1, 2, 3, 5], n).astype(np.uint32)
+    srv = csv.Server(pool, cache_bytes=cache_mb << 20, inflight_bytes=1 << 20, max_batch=256, streams=streams)
+    log("server cache %d MiB, %d requests" % (cache_mb, n))
+    seen = 0
+    # submit in bursts so that requests arrive while others are on the GPU
+    for k in range(0, n, 500):
+        srv.submit(srv.requests(ids[k:k + 500], lods[k:k + 500], tags=np.arange(k, min(n, k + 500))))
+    for comp in wait_all(srv, n):
+        for c in comp:
+            assert c["status"] == 0
+            got = srv.read(c)
+            np.testing.assert_array_equal(got, oracle_brick(orc, b1, b2, c["brick_id"], c["lod"]))
+            assert c["brick_id"] == ids[c["tag"]] and c["lod"] == lods[c["tag"]]
+            seen += 1
+    assert seen == n
+    st = srv.stats()
+    log("stats %s" % {k: st[k] for k in ("hits", "misses", "joined", "evictions", "rebuilds", "p50_us", "p99_us")})
+    assert st["completed"] == n and st["hits"] + st["misses"] + st["joined"] == n
+    if cache_mb == 2:
+        assert st["evictions"] + st["rebuilds"] > 0
+    srv.close()
+
+
+def test_bad_requests(setup):
+    csv, b1, b2 = setup
+    pool = csv.Pool()
+    pool.add_volume(b1)
+    srv = csv.Server(pool, cache_bytes=16 << 20)
+    srv.submit(srv.requests([3, 99, 2], [0, 0, 6], tags=[0, 1, 2]))
+    got = {}
+    for comp in wait_all(srv, 3):
+        for c in comp:
+            got[int(c["tag"])] = int(c["status"])
+    assert got == {0: 0, 1: csv.CSV_ERANGE, 2: csv.CSV_ERANGE}
+    srv.close()
+
+
+def test_trace_replay(setup, orc):
+    csv, b1, b2 = setup
+    pool = csv.Pool()
+    pool.add_volume(b2)
+    rng = np.random.default_rng(3)
+    n = 20000
+    reqs = csv.Server.requests(rng.integers(0, 512, n), rng.integers(0, 3, n),
+                               t_arrival_ns=np.sort(rng.uniform(0, 0.05e9, n)).astype(np.uint64))
+    srv = csv.Server(pool, cache_bytes=512 << 20, max_batch=1024, streams=4)
+    log("trace replay %d requests" % n)
+    done, got = srv.run_trace(reqs, collect=True, timeout_s=20)
+    assert got == n and (done["status"] == 0).all()
+    st = srv.stats()
+    log("trace p50 %.1f us p99 %.1f us" % (st["p50_us"], st["p99_us"]))
+    srv.close()
