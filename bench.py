@@ -111,7 +111,7 @@ def main():
     assert code == 0, ("decode error", code, who)
 
     # launch-shape sweep (logged): waves per workgroup x work queue
-    for shape in [(4, 1, 1), (5, 1, 1), (6, 1, 1), (8, 1, 1), (5, 1, 0), (5, 1, 1, 1)]:
+    for shape in [(16, 4, 1), (8, 4, 1), (4, 4, 1), (16, 3, 1), (16, 2, 1), (16, 4, 0), (16, 4, 1, 1)]:
         pool.decode(ids, out, lod=lod, shape=shape)
         torch.cuda.synchronize()
         ev0.record(stream)

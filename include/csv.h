@@ -135,9 +135,16 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
  *                i is written at i * (32 >> lod_scalar)^3 (requires lods NULL)
  *   out          device, uint32 destination of the decoded blocks
  * Decodes every brick bit-exactly: the result is level L_lod of the brick's
- * resolution pyramid.  One launch: a workgroup per compute unit whose
- * wavefronts each take the next request from a device work counter and
- * decode that brick alone.
+ * resolution pyramid.  Two persistent launches that take requests from
+ * device work counters: an entropy decoder (a wavefront per brick, many per
+ * compute unit; Sec. 3.3) that leaves each brick's symbols as packed
+ * nibbles in a pool buffer, then the replay (a 4-wavefront workgroup per
+ * brick; Sec. 3.2, Alg. 1) that writes the level-of-detail block.
+ * Each stream has its own intermediate buffers (up to 16 streams per pool
+ * at once; a 17th waits for all work on the device), so decodes on
+ * different streams may overlap; decodes on one stream run in order.  The
+ * buffers grow on demand, which synchronises the stream, and cannot grow
+ * inside a stream capture (CSV_EBUSY): capture with csv_graph_create.
  * Argument errors are returned synchronously.  Errors found on the device
  * (bad brick id or level, malformed record) are recorded in the pool's
  * error word (first error wins, read with csv_pool_last_error after the
@@ -146,30 +153,31 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                       const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
-/* Baseline: the same kernel with one launch per brick (grid of one
- * workgroup, n launches on `stream`).  Same arguments and results. */
+/* Baseline: the same two kernels launched once per brick (grids of one
+ * wavefront and one workgroup, 2n launches on `stream`).  Same arguments
+ * and results. */
 int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                             const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
 /* Launch shape of a batched decode.  Every shape gives the same bytes. */
 typedef struct {
-    int waves_per_group;    /* wavefronts per workgroup: 4, 5, 6 or 8; each wave decodes its own
-                               bricks in an equal share of the LDS left after the decode tables */
-    uint32_t groups_per_cu; /* workgroups per compute unit in the grid (1..16) */
+    int waves_per_group;    /* entropy decoder: wavefronts per workgroup, 4, 8 or 16 (each decodes its
+                               own bricks; the grid fills a CU's 32 wavefront slots) */
+    uint32_t groups_per_cu; /* replay: 4-wavefront workgroups per compute unit, 1..8; each holds
+                               160 KiB / groups_per_cu of LDS (bricks whose arrays do not fit take
+                               a slower path through a global-memory arena) */
     int use_queue;          /* 1: waves take requests from a device work counter; 0: static round robin */
     int lpt_order;          /* 1: requests are first ordered longest-first (binned by log2 of their
                                symbols + output voxels / 8; three small kernels before the decode) */
     float ms;               /* csv_autotune: the measured time per launch of this shape */
 } csv_shape;
 
-/* csv_decode_bricks with an explicit launch shape.  Errors as csv_decode_bricks;
- * CSV_EBUSY if lpt_order is requested inside a stream capture before the
- * pool's order buffer was sized for n requests by an uncaptured call. */
+/* csv_decode_bricks with an explicit launch shape.  Errors as csv_decode_bricks. */
 int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
                              uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
                              void *stream, const csv_shape *shape);
 
-/* The shape csv_decode_bricks uses (default {5, 1, 1, 0}). */
+/* The shape csv_decode_bricks uses (default {16, 4, 1, 0}). */
 int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape);
 int csv_pool_get_shape(const csv_pool *pool, csv_shape *shape);
 
@@ -184,9 +192,13 @@ int csv_autotune(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
 
 /* A decode captured once into a HIP graph and replayed.  The graph holds
  * the pointers and n given here and the pool's shape at creation; replays
- * decode the current contents of those buffers.  Replays of one graph must
- * not overlap each other (they share one work counter).  `stream` is the
- * capture stream (NULL: a private stream); launch on any stream. */
+ * decode the current contents of those buffers.  The graph owns its
+ * intermediate buffers, sized for the pool's bricks at creation (a brick
+ * added later with more symbols is reported as CSV_EINVAL).  Replays of one
+ * graph must not overlap each other (they share one work counter).
+ * `stream` is the capture stream (NULL: a private stream); launch on any
+ * stream.  csv_graph_launch returns CSV_EBUSY once a volume has been added
+ * to the pool after the capture (the pool's tables moved): create it again. */
 typedef struct csv_graph csv_graph;
 int csv_graph_create(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                      const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream, csv_graph **graph);

@@ -188,7 +188,7 @@ def test_config2_lower_lods(csvlib, orc, cfg2, lod):
     np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(4096), [lod] * 4096))
 
 
-@pytest.mark.parametrize("shape", [(4, 1, 1), (5, 1, 0), (6, 1, 1), (8, 1, 1), (8, 2, 0)])
+@pytest.mark.parametrize("shape", [(4, 1, 1), (8, 3, 0), (16, 4, 1), (16, 8, 1), (4, 2, 0)])
 def test_launch_shapes_agree(csvlib, orc, cfg2, shape):
     # every launch shape decodes the same bytes; 8 waves per group leave an
     # LDS arena too small for the densest bricks, which then take the
@@ -229,7 +229,7 @@ def test_longest_first_order_and_autotune(csvlib, orc, cfg1, cfg2):
     d_off = torch.from_numpy(off.view(np.int64)).cuda()
     out = torch.full((tot,), -1, dtype=torch.int32, device="cuda")
     log("lpt order")
-    pool.decode(d_ids, out, lods=d_lods, out_offsets=d_off, shape=(5, 1, 1, 1))
+    pool.decode(d_ids, out, lods=d_lods, out_offsets=d_off, shape=(8, 4, 1, 1))
     torch.cuda.synchronize()
     assert pool.last_error() == (0, 0)
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
@@ -244,7 +244,7 @@ def test_longest_first_order_and_autotune(csvlib, orc, cfg1, cfg2):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
 
 
-@pytest.mark.parametrize("shape", [(5, 1, 1, 0), (6, 1, 1, 1)])
+@pytest.mark.parametrize("shape", [(16, 4, 1, 0), (8, 5, 1, 1)])
 def test_graph_replays(csvlib, orc, cfg2, shape):
     # a captured decode replayed several times, with eager work and
     # synchronisation in between; every replay must match
