@@ -41,6 +41,9 @@ def _load():
         lib.synth_blobs.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64]
         lib.synth_neurite.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        d, u64, u32, vp = ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+        lib.synth_camera_trace.argtypes = [u32, u32, u32, d, d, d, u64, u64, d, d, d, d, u32, u32, u64, vp, vp, vp,
+                                           ctypes.POINTER(u64)]
         _lib = lib
     return _lib
 
@@ -102,3 +105,29 @@ def random_brick(b: int, n_labels: int, seed: int, smooth: int = 0) -> np.ndarra
         take = rng.random(a.shape) < 0.6
         a = np.where(take, sh, a).astype(np.uint32)
     return a
+
+
+
+def camera_trace(nx: int, ny: int, nz: int, rate: float, duration_s: float, seed: int = 6, path_seed: int = 7,
+                 period_s: float = 20.0, cone_deg: float = 60.0, d_max: float = 3000.0, d0: float = 1663.0,
+                 brick: int = 32, max_lod: int = 2, t0_s: float = 0.0):
+    """Brick requests of a camera fly-through, as a renderer issues them:
+    Poisson arrivals at `rate` per second over [t0_s, t0_s + duration_s), a
+    camera on a closed Catmull-Rom path (one lap per period_s) looking along
+    its tangent, each request a point in the view cone with distance density
+    proportional to d^2 up to d_max, at level of detail 0 below d0 and
+    floor(log2(d / d0)) + 1 (at most max_lod) beyond.  Returns (brick ids
+    u32 with x fastest, lods u8, arrival times in ns relative to t0_s)."""
+    cap = int(rate * duration_s * 1.2) + 1024
+    ids = np.empty(cap, np.uint32)
+    lods = np.empty(cap, np.uint8)
+    t = np.empty(cap, np.uint64)
+    n = ctypes.c_uint64()
+    lib = _load()
+    rc = lib.synth_camera_trace(nx, ny, nz, float(rate), float(duration_s), float(t0_s), seed, path_seed,
+                                float(period_s), float(cone_deg), float(d_max), float(d0), brick, max_lod, cap,
+                                ids.ctypes.data_as(ctypes.c_void_p), lods.ctypes.data_as(ctypes.c_void_p),
+                                t.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n))
+    assert rc == 0, rc
+    k = n.value
+    return ids[:k].copy(), lods[:k].copy(), t[:k].copy()

@@ -349,3 +349,92 @@ int synth_neurite(uint32_t *out, uint32_t nx, uint32_t ny, uint32_t nz, uint32_t
     free(pts); free(nsteps); free(rad); free(first); free(perm);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Brick requests of a camera fly-through (the serving workload).
+ *
+ * Camera: closed uniform Catmull-Rom path through 8 control points drawn
+ * uniformly (stream path_seed) at least 15 % of each extent inside the
+ * volume, one lap per `period` seconds, looking along the path's tangent.
+ * Requests: Poisson arrivals at `rate` per second over [t0, t0 + duration)
+ * (stream seed).  Each picks a direction uniform in the view cone (full
+ * angle cone_deg) and a distance with density proportional to d^2 up to
+ * d_max, redrawn until the point lies inside the volume (after 1000 misses
+ * the camera's own position is used); its brick (x fastest) is requested at
+ * level 0 below d0, else at clamp(floor(log2(d / d0)) + 1, 0, max_lod).
+ * Writes at most cap requests; *n_out receives the count.  Times in ns
+ * relative to t0.
+ * ------------------------------------------------------------------------ */
+static void catmull_rom3(const double (*c)[3], int n, double u, double pos[3], double tan[3]) {
+    double s = u * n;
+    long i = (long)floor(s);
+    double f = s - (double)i;
+    i %= n;
+    const double *p0 = c[(i + n - 1) % n], *p1 = c[i], *p2 = c[(i + 1) % n], *p3 = c[(i + 2) % n];
+    for (int k = 0; k < 3; k++) {
+        double a = -p0[k] + p2[k], b = 2 * p0[k] - 5 * p1[k] + 4 * p2[k] - p3[k];
+        double cc = -p0[k] + 3 * p1[k] - 3 * p2[k] + p3[k];
+        pos[k] = 0.5 * (2 * p1[k] + a * f + b * f * f + cc * f * f * f);
+        tan[k] = 0.5 * (a + 2 * b * f + 3 * cc * f * f);
+    }
+}
+
+int synth_camera_trace(uint32_t nx, uint32_t ny, uint32_t nz, double rate, double duration, double t0, uint64_t seed,
+                       uint64_t path_seed, double period, double cone_deg, double d_max, double d0, uint32_t brick,
+                       uint32_t max_lod, uint64_t cap, uint32_t *ids, uint8_t *lods, uint64_t *t_ns, uint64_t *n_out) {
+    if (!ids || !lods || !t_ns || !n_out || rate <= 0 || brick == 0 || nx < brick || ny < brick || nz < brick) return 1;
+    double ctrl[8][3];
+    uint64_t ps = path_seed;
+    const double ext[3] = {nx, ny, nz};
+    for (int i = 0; i < 8; i++)
+        for (int k = 0; k < 3; k++) ctrl[i][k] = ext[k] * (0.15 + 0.7 * rnd(&ps));
+    uint64_t s = seed;
+    const double cos_half = cos(cone_deg * 0.5 * 3.14159265358979323846 / 180.0);
+    const uint32_t nbx = nx / brick, nby = ny / brick;
+    double t = 0;
+    uint64_t n = 0;
+    for (;;) {
+        t += -log(1.0 - rnd(&s)) / rate;
+        if (t >= duration || n >= cap) break;
+        double pos[3], tan[3], fw[3], e1[3], e2[3];
+        double u = fmod((t + t0) / period, 1.0);
+        catmull_rom3((const double(*)[3])ctrl, 8, u, pos, tan);
+        double ln = sqrt(tan[0] * tan[0] + tan[1] * tan[1] + tan[2] * tan[2]);
+        if (ln < 1e-9) ln = 1e-9;
+        for (int k = 0; k < 3; k++) fw[k] = tan[k] / ln;
+        double h[3] = {0, 0, 1};
+        if (fabs(fw[2]) >= 0.9) { h[0] = 1; h[2] = 0; }
+        e1[0] = fw[1] * h[2] - fw[2] * h[1];
+        e1[1] = fw[2] * h[0] - fw[0] * h[2];
+        e1[2] = fw[0] * h[1] - fw[1] * h[0];
+        double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        for (int k = 0; k < 3; k++) e1[k] /= l1;
+        e2[0] = fw[1] * e1[2] - fw[2] * e1[1];
+        e2[1] = fw[2] * e1[0] - fw[0] * e1[2];
+        e2[2] = fw[0] * e1[1] - fw[1] * e1[0];
+        double p[3] = {pos[0], pos[1], pos[2]}, d = 0;
+        int found = 0;
+        for (int tries = 0; tries < 1000 && !found; tries++) {
+            double ct = cos_half + (1.0 - cos_half) * rnd(&s);
+            double st = sqrt(1.0 - ct * ct), ph = 2 * 3.14159265358979323846 * rnd(&s);
+            d = d_max * cbrt(rnd(&s));
+            for (int k = 0; k < 3; k++) p[k] = pos[k] + d * (ct * fw[k] + st * (cos(ph) * e1[k] + sin(ph) * e2[k]));
+            found = p[0] >= 0 && p[1] >= 0 && p[2] >= 0 && p[0] < nx && p[1] < ny && p[2] < nz;
+        }
+        if (!found) {
+            for (int k = 0; k < 3; k++) {
+                p[k] = pos[k] < 0 ? 0 : pos[k];
+                if (p[k] > ext[k] - 1) p[k] = ext[k] - 1;
+            }
+            d = 0;
+        }
+        uint32_t bx = (uint32_t)(p[0] / brick), by = (uint32_t)(p[1] / brick), bz = (uint32_t)(p[2] / brick);
+        ids[n] = bx + nbx * (by + nby * bz);
+        int lod = d < d0 ? 0 : (int)floor(log2(d / d0)) + 1;
+        lods[n] = (uint8_t)(lod < 0 ? 0 : (lod > (int)max_lod ? (int)max_lod : lod));
+        t_ns[n] = (uint64_t)(t * 1e9);
+        n++;
+    }
+    *n_out = n;
+    return 0;
+}
