@@ -153,9 +153,9 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                       const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
-/* Baseline: the same two kernels launched once per brick (grids of one
- * wavefront and one workgroup, 2n launches on `stream`).  Same arguments
- * and results. */
+/* Baseline: the same kernels launched once per brick (a counter reset, a
+ * grid of one wavefront, a grid of one workgroup: 3n launches on `stream`).
+ * Same arguments and results. */
 int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                             const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
@@ -177,7 +177,7 @@ int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *brick_ids, co
                              uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
                              void *stream, const csv_shape *shape);
 
-/* The shape csv_decode_bricks uses (default {16, 4, 1, 0}). */
+/* The shape csv_decode_bricks uses (default {16, 3, 1, 0}). */
 int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape);
 int csv_pool_get_shape(const csv_pool *pool, csv_shape *shape);
 

@@ -3,32 +3,32 @@
 // A decode of n requests (brick, level of detail t; Sec. 3.4, Alg. 1) is
 // two persistent launches that take requests from device work counters:
 //
-// A. entropy decode (Sec. 3.3).  One wavefront per brick, many per CU (the
-//    only LDS is the decode tables and a 2 KB word ring per wave, so the
-//    serial rANS chains of many bricks hide each other's latency).  The W
-//    interleaved states run in lockstep, one per lane; a renormalising lane
-//    takes its 16-bit word at the stream cursor plus the number of lower
-//    lanes that renormalise too (wave ballot + mbcnt).  Eight lanes' 4-bit
-//    symbols are OR-ed into one dword with DPP row shifts and stored to a
-//    per-request nibble buffer in global memory (it stays in L2 / MALL).
-//
-// B. operation replay and output (Sec. 3.2, Alg. 1).  One 4-wave workgroup
-//    per brick, several per CU, level by level in Morton order as palette
-//    indices in LDS (u8 when the palette has at most 253 entries):
-//      - one lane per expanded parent, in stream order; SWAR on its 8
-//        (op, stop) nibbles counts P_a, P_delta and expanded children; wave
-//        prefix sums plus the totals of the lower waves give every child its
-//        palette position, delta slot and the next level's expanded list;
-//      - a neighbour reference to a later node reads the parent level; one to
-//        an earlier node of the same level always lands on a child with one
-//        more coordinate bit set, so three passes of decreasing child
-//        popcount resolve every chain;
-//      - leaf values are kept only for the expanded L_1 nodes, found by a
-//        popcount rank over the expansion bitmask;
-//      - the level-t block goes through the palette to HBM as dense rows of
-//        16-byte stores (a wave's store covers eight whole 128-byte rows).
-//    Bricks whose arrays do not fit the LDS arena use the same code with
-//    u16 indices and an arena in global memory.
+// A. front kernel: one wavefront per brick, 16 per CU, 8 KB of LDS each.
+//    - Entropy decode (Sec. 3.3).  The W interleaved states run in
+//      lockstep, one per lane; a renormalising lane takes its 16-bit word at
+//      the stream cursor plus the number of lower lanes that renormalise too
+//      (wave ballot + mbcnt) from a 2 KB ring of the word stream.  Eight
+//      lanes' 4-bit symbols are OR-ed into one dword with DPP row shifts and
+//      stored to the request's slot in global memory (it stays in L2 / MALL).
+//    - Replay of levels 4 .. max(t, 1) (Sec. 3.2, Alg. 1) by the same wave,
+//      level by level in Morton order as palette indices in its LDS (u8 when
+//      the palette has at most 253 entries, else u16 in the slot): one lane
+//      per expanded parent in stream order, SWAR on its 8 (op, stop)
+//      nibbles, a wave prefix sum for palette positions, delta slots and the
+//      next level's expanded list.  A neighbour reference to a later node
+//      reads the parent level; one to an earlier node of the same level
+//      lands on a child with one more coordinate bit set, so every chain has
+//      at most three links and is followed to its end.
+//    - t >= 1: the level-t block goes through the palette to the output.
+//      t = 0: L_1, its expansion bits and the list of expanded L_1 nodes go
+//      to the slot and the request joins the leaf list.
+// B. leaf kernel: one 4-wave workgroup per brick of the leaf list, several
+//    per CU: L_1, the leaf nibbles and the palette staged in LDS; leaf values
+//    kept only for the expanded L_1 nodes (found by a popcount rank over the
+//    expansion bitmask); chains resolved in three independent rounds; the
+//    32^3 block written through the palette as dense rows of 16-byte stores.
+//    Bricks whose arrays do not fit the LDS arena use the same code on an
+//    arena in global memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +37,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/csv.h"
@@ -49,15 +50,15 @@ constexpr int kLutMaxBits = 11;          // largest supported table precision
 constexpr uint32_t kMaxSym = 2 * 37448;  // every node an operation plus a delta nibble
 constexpr uint32_t kLdsBytes = 160 * 1024;
 constexpr uint32_t kLutLdsCap = 24 * 1024;  // decode tables kept in LDS when they fit
-constexpr uint32_t kPalFast = 253;       // u8 path: palette indices 0..252, 253..255 mark open references
-constexpr uint32_t kRingWords = 1024;    // per-wave word ring of the entropy decoder
+constexpr uint32_t kPalFast = 252;       // u8 indices 0..251; 252 marks an invalid reference, 253..255 open ones
+constexpr uint32_t kRingWords = 1024;    // word ring of the entropy decoder
 #ifndef CSV_WAVES_B
 #define CSV_WAVES_B 4
 #endif
-constexpr int kWavesB = CSV_WAVES_B;     // waves of a replay workgroup
+constexpr int kWavesB = CSV_WAVES_B;     // waves of a leaf workgroup
 constexpr uint32_t kThreadsB = 64 * kWavesB;
-#ifndef CSV_REPLAY_ATTR
-#define CSV_REPLAY_ATTR
+#ifndef CSV_LEAF_ATTR
+#define CSV_LEAF_ATTR
 #endif
 
 // level m (1..4) offsets (entries) inside the Morton-ordered level arrays
@@ -66,6 +67,19 @@ __device__ constexpr uint32_t kLvOff[5] = {0, 0, 4096, 4608, 4672};
 __device__ constexpr uint32_t kBmOff[5] = {0, 0, 512, 576, 584};
 // lists of expanded nodes (u16 entries) for levels 2..4; level 1 has its own
 __device__ constexpr uint32_t kLstOff[5] = {0, 0, 72, 8, 0};
+
+// LDS of one front-kernel wave: the word ring (2 KB) and 512 symbol bytes
+// during the entropy decode, then the upper levels (u8), their expansion
+// bits and lists, the palette
+constexpr uint32_t kWaveLds = 8192;
+constexpr uint32_t kWLv = 0, kWBm = 4688, kWLst = 5280, kWPal = 6448;
+
+// Per-request slot in global memory: the packed nibbles (slot_dw dwords),
+// then the levels (u16 levels 1..4 for big palettes; else u8 L_1 only, in
+// Morton order), the expansion bits of levels 1..4 (L_1 first) and
+// {E_1, P_a operations above L_0}.
+constexpr uint32_t kSlotLv = 9376, kSlotBm = 608, kSlotMeta = 16;
+constexpr uint32_t kSlotExtra = kSlotLv + kSlotBm + kSlotMeta;
 
 struct DecodeArgs {
     const uint64_t *rec_ptr;
@@ -84,29 +98,28 @@ struct DecodeArgs {
     int *err;  // [0] first error code, [1] brick id (or request index)
 };
 
-// per-request status written by the entropy decoder for the replay
-enum : uint8_t { kStOk = 0, kStFail = 1, kStNone = 2 };
-
 struct LaunchA {
     uint32_t lut_lds_words;  // decode-table words in LDS (0: tables read from global memory)
     uint32_t *queue;         // work counter (nullptr: static round robin)
     const uint32_t *order;   // processing order of requests (nullptr: identity)
-    uint32_t *nib;           // slot_dw dwords of packed nibbles per request
-    uint32_t slot_dw;
-    uint8_t *status;
+    uint8_t *slots;          // slot_bytes per request
+    uint32_t slot_bytes;
+    uint32_t slot_dw;        // nibble dwords at the start of a slot
+    uint32_t *leaf_list;     // requests left for the leaf kernel
+    uint32_t *leaf_count;
     uint32_t base;           // first request index
 };
 
 struct LaunchB {
     uint32_t arena_bytes;    // LDS arena per workgroup
-    uint32_t *queue;
-    const uint32_t *order;
-    const uint32_t *nib;
-    uint32_t slot_dw;
-    const uint8_t *status;
-    uint8_t *scratch;        // global arena per workgroup for bricks that do not fit LDS
+    uint32_t *queue;         // work counter over the leaf list
+    const uint32_t *leaf_list;
+    const uint32_t *leaf_count;
+    const uint8_t *slots;
     uint32_t slot_bytes;
-    uint32_t base;
+    uint32_t slot_dw;
+    uint8_t *scratch;        // global arena per workgroup for bricks that do not fit LDS
+    uint32_t scratch_bytes;
 };
 
 // ---------------------------------------------------------------------------
@@ -153,7 +166,7 @@ __device__ __forceinline__ void report(int *err, int code, uint32_t who) {
 #ifdef CSV_PHASE_TIMING
 __device__ uint64_t *g_phase = nullptr;
 __device__ __forceinline__ void phase_mark(uint32_t rq, int i) {
-    if (g_phase && __lane_id() == 0 && (i < 2 || threadIdx.x == 0)) g_phase[16 * (size_t)rq + i] = __builtin_amdgcn_s_memtime();
+    if (g_phase && __lane_id() == 0 && (i < 3 || i >= 9 || threadIdx.x == 0)) g_phase[16 * (size_t)rq + i] = __builtin_amdgcn_s_memtime();
 }
 #else
 __device__ __forceinline__ void phase_mark(uint32_t, int) {}
@@ -210,7 +223,7 @@ template <> struct Vec8<uint16_t> {
     static __device__ __forceinline__ T splat(uint32_t x) { x *= 0x00010001u; return make_uint4(x, x, x, x); }
 };
 
-__host__ __device__ inline uint32_t align16(uint32_t b) { return (b + 15u) & ~15u; }
+__host__ __device__ constexpr uint32_t align16(uint32_t b) { return (b + 15u) & ~15u; }
 
 // Pointers into global memory.  Going through the global address space lets
 // the compiler emit global (not flat) loads: a flat load also waits for LDS
@@ -277,204 +290,9 @@ __device__ __forceinline__ ReqKind load_request(const DecodeArgs &a, uint32_t rq
 }
 
 // ===========================================================================
-// A. entropy decode
+// shared replay pieces
 // ===========================================================================
-// kLutLds: the decode tables of every volume are copied to LDS (else read
-// from global memory)
-template <int WPG, bool kLutLds>
-__global__ __launch_bounds__(WPG * 64) void rans_kernel(DecodeArgs a, LaunchA l) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint32_t *slut = reinterpret_cast<uint32_t *>(smem);
-    if (kLutLds)
-        for (uint32_t e = threadIdx.x; e < l.lut_lds_words; e += blockDim.x) slut[e] = a.luts[e];
-    __syncthreads();
-    const uint32_t L = lane(), wave = threadIdx.x >> 6;
-    uint32_t *ring32 = reinterpret_cast<uint32_t *>(smem + align16(4 * l.lut_lds_words) + wave * kRingWords * 2);
-    const uint16_t *ring = reinterpret_cast<const uint16_t *>(ring32);
-    const uint32_t wid = blockIdx.x * WPG + wave;
-    const uint32_t hdr = csv::record_header_words(kLog2);
-    for (uint32_t k = 0;; k++) {
-        uint32_t req;
-        if (l.queue) {
-            uint32_t v = 0;
-            if (L == 0) v = atomicAdd(l.queue, 1u);
-            req = uniform(v) + l.base;
-        } else {
-            req = l.base + wid + k * gridDim.x * WPG;
-        }
-        if (req >= a.n) break;
-        const uint32_t rq = l.order ? l.order[req] : req;
-        phase_mark(rq, 0);
-        Hdr h;
-        uint32_t *dst, count, fill;
-        const ReqKind kind = load_request(a, rq, h, dst, count, fill);
-        uint8_t st = kStOk;
-        if (kind == kReqBadLod) {
-            if (L == 0) report(a.err, CSV_ERANGE, rq);
-            st = kStNone;
-        } else if (kind == kReqBadId) {
-            if (L == 0) report(a.err, CSV_ERANGE, rq);
-            st = kStFail;
-        } else if (kind == kReqCorrupt) {
-            if (L == 0) report(a.err, CSV_ECORRUPT, h.id);
-            st = kStFail;
-        } else if (kind == kReqDecode) {
-            const uint32_t n = h.c(h.t);
-            uint32_t *out = glob(l.nib) + (size_t)rq * l.slot_dw;
-            if (n + 16 > 8 * l.slot_dw) {  // the buffers are sized for the pool's largest brick
-                if (L == 0) report(a.err, CSV_EINVAL, h.id);
-                st = kStFail;
-            } else {
-                const uint32_t sbits = a.vol_bits[h.vol], lutn = 1u << sbits, mask = lutn - 1u;
-                const uint32_t *lut = (kLutLds ? (const uint32_t *)slut : glob(a.luts)) + a.lut_off[h.vol];
-                const uint32_t W = h.W, lw = 31u - (uint32_t)__builtin_clz(W), leaf = h.c1;
-                const uint32_t *wg = h.rec + hdr + h.P + W;
-                const uint32_t ndw = (h.nw + 1) / 2;  // word dwords in the record (the last one padded)
-                uint32_t x = L < W ? h.rec[hdr + h.P + L] : 0u;
-                // the ring holds words [ring_lo, ring_lo + 1024); pf holds the next 512
-                uint32_t ring_lo = 0;
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const uint32_t d = L + 64 * q;
-                    ring32[d] = d < ndw ? wg[d] : 0u;
-                }
-                uint32_t pf[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const uint32_t d = 512 + L + 64 * q;
-                    pf[q] = d < ndw ? wg[d] : 0u;
-                }
-                wsync();
-                uint32_t cursor = 0, acc = 0;
-                bool bad = false;
-                const uint32_t steps = (n + W - 1) >> lw;
-                uint32_t s = 0;
-                if (W == 64) {
-                    // steps with all 64 lanes busy: no per-lane conditions; every
-                    // lane reads a ring word and keeps it if it renormalises
-                    for (const uint32_t full = n >> 6; s < full; s++) {
-                        const uint32_t i = (s << 6) + L;
-                        const uint32_t e = lut[(i >= leaf ? lutn : 0u) + (x & mask)];
-                        const uint32_t sym = e & 15u;
-                        x = (e >> 16) * (x >> sbits) + ((e >> 4) & 0xFFFu);
-                        const bool need = x < csv::kRansLower;
-                        const uint64_t bal = __ballot(need);
-                        const uint32_t wd = ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
-                        x = need ? ((x << 16) | wd) : x;
-                        cursor += (uint32_t)__popcll(bal);
-                        const uint32_t g = row_or<3>(sym << (4 * (L & 7u)));
-                        if ((L & 7u) == 7u) out[(i - 7) >> 3] = g;
-                        if (cursor >= ring_lo + 512) {  // the oldest half is consumed: refill it
-                            const uint32_t hh = (ring_lo >> 9) & 1u;
-                            wsync();
-#pragma unroll
-                            for (int q = 0; q < 4; q++) ring32[hh * 256 + L + 64 * q] = pf[q];
-                            ring_lo += 512;
-                            const uint32_t d0 = (ring_lo + 1024) >> 1;
-#pragma unroll
-                            for (int q = 0; q < 4; q++) {
-                                const uint32_t d = d0 + L + 64 * q;
-                                pf[q] = d < ndw ? wg[d] : 0u;
-                            }
-                            wsync();
-                        }
-                    }
-                    // words past the end of the stream came from stale ring entries
-                    bad = cursor > h.nw;
-                    if (bad) s = steps;
-                }
-                for (; s < steps; s++) {
-                    const uint32_t i = (s << lw) + L;
-                    const bool act = L < W && i < n;
-                    uint32_t sym = 0;
-                    bool need = false;
-                    if (act) {
-                        const uint32_t e = lut[(i >= leaf ? lutn : 0u) + (x & mask)];
-                        sym = e & 15u;
-                        x = (e >> 16) * (x >> sbits) + ((e >> 4) & 0xFFFu);
-                        need = x < csv::kRansLower;
-                    }
-                    const uint64_t bal = __ballot(need);
-                    const uint32_t cnt = (uint32_t)__popcll(bal);
-                    if (cursor + cnt > h.nw) {
-                        bad = true;
-                        break;
-                    }
-                    if (need) x = (x << 16) | (uint32_t)ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
-                    cursor += cnt;
-                    // 8 consecutive symbols -> one dword of the nibble buffer
-                    const uint32_t v = sym << (4 * (i & 7));
-                    if (W >= 8) {
-                        const uint32_t g = row_or<3>(v);
-                        if ((L & 7) == 7 && L < W && i - 7 < n) out[(i - 7) >> 3] = g;
-                    } else {
-                        const uint32_t g = W == 4 ? row_or<2>(v) : (W == 2 ? row_or<1>(v) : v);
-                        acc |= g;
-                        const bool full = (((s + 1) << lw) & 7) == 0;
-                        if (L == W - 1 && (full || s + 1 == steps)) out[(s << lw) >> 3] = acc;
-                        if (full) acc = 0;
-                    }
-                    if (cursor >= ring_lo + 512) {  // the oldest half is consumed: refill it
-                        const uint32_t hh = (ring_lo >> 9) & 1u;
-                        wsync();
-#pragma unroll
-                        for (int q = 0; q < 4; q++) ring32[hh * 256 + L + 64 * q] = pf[q];
-                        ring_lo += 512;
-                        const uint32_t d0 = (ring_lo + 1024) >> 1;
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            const uint32_t d = d0 + L + 64 * q;
-                            pf[q] = d < ndw ? wg[d] : 0u;
-                        }
-                        wsync();
-                    }
-                }
-                // a complete decode ends in the encoder's initial states with every word read
-                if (!bad && h.t == 0) bad = (__ballot(L < W && x != csv::kRansLower) != 0) || cursor != h.nw;
-                if (bad) {
-                    if (L == 0) report(a.err, CSV_ECORRUPT, h.id);
-                    st = kStFail;
-                }
-            }
-        }
-        if (L == 0) l.status[rq] = st;
-        phase_mark(rq, 1);
-    }
-}
-
-// ===========================================================================
-// B. operation replay and output
-// ===========================================================================
-struct SmallB {
-    uint32_t req;
-    int err;
-    uint32_t wt[kWavesB][3];  // per-wave totals of P_a, P_delta, expanded children
-};
-
-struct LayoutB {
-    uint32_t pal, nib, nib_dw, lv, bm, bpre, lst, list1, l0x, total;
-};
-// stage: the P palette entries and nib_dw dwords of packed nibbles are
-// copied to the arena; S0 leaf-segment symbols (0 unless decoding to LOD 0);
-// idx bytes per palette index
-__host__ __device__ inline LayoutB make_layout_b(bool stage, uint32_t P, uint32_t S0, uint32_t idx, uint32_t nib_dw) {
-    LayoutB L;
-    uint32_t o = 0;
-    const uint32_t e1 = S0 / 8 < 4096 ? S0 / 8 : 4096;
-    L.pal = o; o += stage ? align16(4 * P) : 0;
-    L.nib = o; o += stage ? align16(4 * nib_dw) : 0;
-    L.nib_dw = stage ? nib_dw : 0;
-    L.lv = o; o += align16(4680 * idx);
-    L.bm = o; o += 592;
-    L.bpre = o; o += 160;
-    L.lst = o; o += align16(2 * (8 + 64 + 512));
-    L.list1 = o; o += align16(2 * e1);
-    L.l0x = o; o += align16(8 * e1 * idx);
-    L.total = o;
-    return L;
-}
-
-// children of one expanded parent from its 8 (op, stop) nibbles w: pv parent
+// Children of one expanded parent from its 8 (op, stop) nibbles w: pv parent
 // index; nb[a] the parent-level neighbour at +1 along axis a (valid if bit a
 // of nbok); lowok bit a: the parent is not on the low face of axis a; ipb
 // palette position before the first child; pam8/pdm8 children with P_a /
@@ -522,6 +340,86 @@ __device__ __forceinline__ typename Vec8<IdxT>::T replay_children(uint32_t w, ui
     return out;
 }
 
+// nibbles 0..3 of x -> bytes 0..3
+__device__ __forceinline__ uint32_t nib_to_bytes(uint32_t x) {
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    return (x | (x << 4)) & 0x0F0F0F0Fu;
+}
+// any byte of x equal to 0
+__device__ __forceinline__ bool has_zero_byte(uint32_t x) { return ((x - 0x01010101u) & ~x & 0x80808080u) != 0; }
+// byte selector of child k per operation code (v_perm_b32 codes over the
+// candidates below): R_p -> the parent (4); R_a -> the parent level's +1
+// neighbour (5 + a) if bit a of k is set, else the same-level mark (a);
+// P_0, P_delta, P_a and the unused code 7 -> zero (12)
+__host__ __device__ constexpr uint32_t child_selectors(int k) {
+    return 4u | ((k & 1 ? 5u : 0u) << 4) | ((k & 2 ? 6u : 1u) << 8) | ((k & 4 ? 7u : 2u) << 12) | (12u << 16) |
+           (12u << 20) | (12u << 24) | (12u << 28);
+}
+
+// replay_children for u8 indices, all 8 children at once in two dwords:
+// each child's copy or reference is one byte select (v_perm_b32) out of
+// {marks, parent, neighbours}; the P operations add their palette position
+// (ipb plus an exclusive byte-wise prefix count of the P_a children, +1 for
+// P_a, -1 - delta for P_delta).  A reference that the parent's position
+// does not allow selects 252, which no valid index reaches.
+__device__ __forceinline__ uint2 replay_children_u8(uint32_t w, uint32_t pv, const uint32_t nb[3], uint32_t nbok,
+                                                    uint32_t lowok, uint32_t ipb, const uint32_t *dnib, uint32_t db,
+                                                    uint32_t P, bool leaf, bool &bad) {
+    constexpr uint32_t kInv = 252u;
+    const uint32_t cand_lo = ((lowok & 1u) ? 253u : kInv) | (((lowok & 2u) ? 254u : kInv) << 8) |
+                             (((lowok & 4u) ? 255u : kInv) << 16) | (kInv << 24);
+    const uint32_t cand_hi = pv | (((nbok & 1u) ? nb[0] : kInv) << 8) | (((nbok & 2u) ? nb[1] : kInv) << 16) |
+                             (((nbok & 4u) ? nb[2] : kInv) << 24);
+    uint32_t sel_lo = 0, sel_hi = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const uint32_t o4 = ((w >> (4 * k)) & 7u) << 2;
+        const uint32_t sk = (child_selectors(k) >> o4) & 15u;
+        if (k < 4) sel_lo |= sk << (8 * k);
+        else sel_hi |= sk << (8 * (k - 4));
+    }
+    uint32_t lo = __builtin_amdgcn_perm(cand_hi, cand_lo, sel_lo);
+    uint32_t hi = __builtin_amdgcn_perm(cand_hi, cand_lo, sel_hi);
+    const uint32_t y = w & 0x77777777u;
+    const uint32_t pam = zero_nibbles(y ^ 0x66666666u);
+    const uint32_t pa_lo = nib_to_bytes(pam), pa_hi = nib_to_bytes(pam >> 16);
+    const uint32_t ip_lo = ipb * 0x01010101u + (pa_lo << 8) + (pa_lo << 16) + (pa_lo << 24);
+    const uint32_t ip_hi = (ipb + (uint32_t)__builtin_popcount(pam & 0xFFFFu)) * 0x01010101u + (pa_hi << 8) +
+                           (pa_hi << 16) + (pa_hi << 24);
+    const uint32_t wp = (y >> 2) & 0x11111111u;  // bit 4k: operation code >= 4
+    const uint32_t pb_lo = nib_to_bytes(wp), pb_hi = nib_to_bytes(wp >> 16);
+    lo += (ip_lo & ((pb_lo << 8) - pb_lo)) + pa_lo;
+    hi += (ip_hi & ((pb_hi << 8) - pb_hi)) + pa_hi;
+    uint32_t pd = compact_nibble_bits(zero_nibbles(y ^ 0x55555555u));
+    for (uint32_t j = 0; pd; j++) {
+        const uint32_t k = (uint32_t)__builtin_ctz(pd);
+        pd &= pd - 1;
+        const uint32_t d = nib1(dnib, db + j), sh = 8 * (k & 3u);
+        const uint32_t ipk = ((k < 4 ? ip_lo : ip_hi) >> sh) & 0xFFu;
+        bad |= ipk < d + 1;
+        if (k < 4) lo -= (d + 1) << sh;
+        else hi -= (d + 1) << sh;
+    }
+    bad |= ipb + (uint32_t)__builtin_popcount(pam) >= P;  // the last P_a child's new entry
+    bad |= zero_nibbles(y ^ 0x77777777u) != 0;
+    bad |= leaf && (w & 0x88888888u) != 0;
+    bad |= has_zero_byte(lo ^ 0xFCFCFCFCu) || has_zero_byte(hi ^ 0xFCFCFCFCu);
+    return make_uint2(lo, hi);
+}
+
+// both index widths through one name
+template <class IdxT>
+__device__ __forceinline__ typename Vec8<IdxT>::T replay8(uint32_t w, uint32_t pv, const uint32_t nb[3],
+                                                         uint32_t nbok, uint32_t lowok, uint32_t ipb, uint32_t pam8,
+                                                         uint32_t pdm8, const uint32_t *dnib, uint32_t db, uint32_t P,
+                                                         bool leaf, bool &bad) {
+    if constexpr (sizeof(IdxT) == 1)
+        return replay_children_u8(w, pv, nb, nbok, lowok, ipb, dnib, db, P, leaf, bad);
+    else
+        return replay_children<IdxT>(w, pv, nb, nbok, lowok, ipb, pam8, pdm8, dnib, db, P, leaf, bad);
+}
+
 // palette lookup; indices are checked while decoding, the clamp only keeps a
 // malformed record from reading past a palette held in global memory
 template <bool kG>
@@ -543,12 +441,14 @@ __device__ __forceinline__ void store4(uint32_t *dst, const uint4 &o, bool al16)
     }
 }
 
-__device__ __forceinline__ void wg_fill(uint32_t *dst, uint32_t count, uint32_t v) {
+// count labels of value v, by kThreads threads (tid: this thread's index)
+template <uint32_t kThreads>
+__device__ __forceinline__ void fill_labels(uint32_t *dst, uint32_t count, uint32_t v, uint32_t tid) {
     if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0 && (count & 3) == 0) {
         const uint4 q = make_uint4(v, v, v, v);
-        for (uint32_t e = 4 * threadIdx.x; e < count; e += 4 * kThreadsB) *reinterpret_cast<uint4 *>(dst + e) = q;
+        for (uint32_t e = 4 * tid; e < count; e += 4 * kThreads) *reinterpret_cast<uint4 *>(dst + e) = q;
     } else {
-        for (uint32_t e = threadIdx.x; e < count; e += kThreadsB) dst[e] = v;
+        for (uint32_t e = tid; e < count; e += kThreads) dst[e] = v;
     }
 }
 
@@ -562,37 +462,173 @@ __device__ __forceinline__ void nibble_counts(uint32_t w, bool act, uint32_t &pa
     cnt = __builtin_popcount(pam) | (__builtin_popcount(pdm) << 10) | (__builtin_popcount(exm) << 20);
 }
 
-// the replay of one brick by one workgroup; false on a malformed stream
+// ordering between the lanes of one wave: LDS (wsync) or also global memory
+template <bool kG>
+__device__ __forceinline__ void wave_sync() {
+    if (kG) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        wsync();
+    }
+}
+
+// ===========================================================================
+// A. front kernel
+// ===========================================================================
+// Entropy decode of the first n symbols of a brick (the prefix for its
+// level of detail) into packed nibbles at out (global); ring32: this wave's
+// 2 KB of LDS.  False on a malformed stream.
+template <bool kLutLds>
+__device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h, const uint32_t *slut,
+                                               uint32_t *ring32, uint32_t *out, uint32_t n) {
+    const uint32_t L = lane();
+    const uint32_t hdr = csv::record_header_words(kLog2);
+    const uint16_t *ring = reinterpret_cast<const uint16_t *>(ring32);
+    const uint32_t sbits = a.vol_bits[h.vol], lutn = 1u << sbits, mask = lutn - 1u;
+    const uint32_t *lut = (kLutLds ? slut : glob(a.luts)) + a.lut_off[h.vol];
+    const uint32_t W = h.W, lw = 31u - (uint32_t)__builtin_clz(W), leaf = h.c1;
+    const uint32_t *wg = h.rec + hdr + h.P + W;
+    const uint32_t ndw = (h.nw + 1) / 2;  // word dwords in the record (the last one padded)
+    uint32_t x = L < W ? h.rec[hdr + h.P + L] : 0u;
+    // the ring holds words [ring_lo, ring_lo + 1024); pf holds the next 512
+    uint32_t ring_lo = 0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const uint32_t d = L + 64 * q;
+        ring32[d] = d < ndw ? wg[d] : 0u;
+    }
+    uint32_t pf[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t d = 512 + L + 64 * q;
+        pf[q] = d < ndw ? wg[d] : 0u;
+    }
+    wsync();
+    uint32_t cursor = 0, acc = 0;
+    bool bad = false;
+    // the oldest half of the ring is consumed: refill it from pf, fetch the next
+    auto refill = [&]() {
+        const uint32_t hh = (ring_lo >> 9) & 1u;
+        wsync();
+#pragma unroll
+        for (int q = 0; q < 4; q++) ring32[hh * 256 + L + 64 * q] = pf[q];
+        ring_lo += 512;
+        const uint32_t d0 = (ring_lo + 1024) >> 1;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t d = d0 + L + 64 * q;
+            pf[q] = d < ndw ? wg[d] : 0u;
+        }
+        wsync();
+    };
+    const uint32_t steps = (n + W - 1) >> lw;
+    uint32_t s = 0;
+    if (W == 64) {
+        // steps with all 64 lanes busy: no per-lane conditions; every lane
+        // reads a ring word and keeps it if it renormalises.  Steps wholly
+        // before the leaf segment use the interior table without a select.
+        auto step = [&](auto leaf_select) {
+            const uint32_t i = (s << 6) + L;
+            const uint32_t tb = decltype(leaf_select)::value ? (i >= leaf ? lutn : 0u) : 0u;
+            const uint32_t e = lut[tb + (x & mask)];
+            const uint32_t sym = e & 15u;
+            x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
+            const bool need = x < csv::kRansLower;
+            const uint64_t bal = __ballot(need);
+            const uint32_t wd = ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
+            x = need ? ((x << 16) | wd) : x;
+            cursor += (uint32_t)__popcll(bal);
+            const uint32_t g = row_or<3>(sym << (4 * (L & 7u)));
+            if ((L & 7u) == 7u) out[(i - 7) >> 3] = g;
+            if (cursor >= ring_lo + 512) refill();
+        };
+        // blocks of 8 steps: each lane writes its symbol as a byte to LDS
+        // (no address arithmetic: immediate offsets), then lane L packs the
+        // block's symbols 8L .. 8L + 7 into one nibble dword
+        uint8_t *sb = reinterpret_cast<uint8_t *>(ring32) + 2 * kRingWords;
+        auto block8 = [&](auto leaf_select) {
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t i = ((s + (uint32_t)j) << 6) + L;
+                const uint32_t tb = decltype(leaf_select)::value ? (i >= leaf ? lutn : 0u) : 0u;
+                const uint32_t e = lut[tb + (x & mask)];
+                x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
+                const bool need = x < csv::kRansLower;
+                const uint64_t bal = __ballot(need);
+                const uint32_t wd = ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
+                x = need ? ((x << 16) | wd) : x;
+                cursor += (uint32_t)__popcll(bal);
+                sb[64 * j + L] = (uint8_t)(e & 15u);
+                if (cursor >= ring_lo + 512) refill();
+            }
+            wsync();
+            const uint2 b = *reinterpret_cast<const uint2 *>(sb + 8 * L);
+            const uint32_t lo = (b.x | (b.x >> 4)) & 0x00FF00FFu, hi = (b.y | (b.y >> 4)) & 0x00FF00FFu;
+            out[(s << 3) + L] = ((lo | (lo >> 8)) & 0xFFFFu) | (((hi | (hi >> 8)) & 0xFFFFu) << 16);
+            wsync();
+            s += 8;
+        };
+        const uint32_t full = n >> 6, s_int = min(leaf >> 6, full);
+        while (s + 8 <= s_int) block8(std::false_type{});
+        while (s + 8 <= full) block8(std::true_type{});
+        for (; s < full; s++) step(std::true_type{});
+        // words past the end of the stream came from stale ring entries
+        bad = cursor > h.nw;
+        if (bad) s = steps;
+    }
+    for (; s < steps; s++) {
+        const uint32_t i = (s << lw) + L;
+        const bool act = L < W && i < n;
+        uint32_t sym = 0;
+        bool need = false;
+        if (act) {
+            const uint32_t e = lut[(i >= leaf ? lutn : 0u) + (x & mask)];
+            sym = e & 15u;
+            x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
+            need = x < csv::kRansLower;
+        }
+        const uint64_t bal = __ballot(need);
+        const uint32_t cnt = (uint32_t)__popcll(bal);
+        if (cursor + cnt > h.nw) {
+            bad = true;
+            break;
+        }
+        if (need) x = (x << 16) | (uint32_t)ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
+        cursor += cnt;
+        // 8 consecutive symbols -> one dword of the nibble buffer
+        const uint32_t v = sym << (4 * (i & 7));
+        if (W >= 8) {
+            const uint32_t g = row_or<3>(v);
+            if ((L & 7) == 7 && L < W && i - 7 < n) out[(i - 7) >> 3] = g;
+        } else {
+            const uint32_t g = W == 4 ? row_or<2>(v) : (W == 2 ? row_or<1>(v) : v);
+            acc |= g;
+            const bool full = (((s + 1) << lw) & 7) == 0;
+            if (L == W - 1 && (full || s + 1 == steps)) out[(s << lw) >> 3] = acc;
+            if (full) acc = 0;
+        }
+        if (cursor >= ring_lo + 512) refill();
+    }
+    // a complete decode ends in the encoder's initial states with every word read
+    if (!bad && h.t == 0) bad = (__ballot(L < W && x != csv::kRansLower) != 0) || cursor != h.nw;
+    return !bad;
+}
+
+// Replay of levels 4 .. max(t, 1) by one wave (Alg. 1).  lv: the level
+// arrays (LDS, or the slot when kG); bm, lst: expansion bits and lists of
+// levels 2..4 in LDS; nib: the brick's nibbles (global).  On return E and
+// ipl hold the number of expanded L_1 nodes and the P_a operations so far.
+// False on a malformed stream.
 template <class IdxT, bool kG>
-__device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib, uint8_t *ar, const LayoutB &lay,
-                                             SmallB *sm, uint32_t *dst) {
+__device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, IdxT *lv, uint8_t *bm, uint16_t *lst,
+                                             uint32_t &E_out, uint32_t &ipl_out) {
     using V = Vec8<IdxT>;
     using VT = typename V::T;
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
-    const uint32_t tid = threadIdx.x, L = lane(), w = tid >> 6;
-    const uint32_t t = h.t, P = h.P;
-    const uint32_t hdr = csv::record_header_words(kLog2);
-    const uint32_t *pal = kG ? h.rec + hdr : reinterpret_cast<const uint32_t *>(ar + lay.pal);
-    IdxT *lv = reinterpret_cast<IdxT *>(ar + lay.lv);
-    uint8_t *bm = ar + lay.bm;
-    uint16_t *bpre = reinterpret_cast<uint16_t *>(ar + lay.bpre);
-    uint16_t *lst = reinterpret_cast<uint16_t *>(ar + lay.lst);
-    uint16_t *list1 = reinterpret_cast<uint16_t *>(ar + lay.list1);
-    const uint32_t tl = t > 1 ? t : 1u;  // finest upper level replayed
-    const uint32_t S0 = t == 0 ? h.c0 - h.c1 : 0u;
-    const uint32_t e1cap = S0 / 8 < 4096 ? S0 / 8 : 4096u;
-    const uint32_t *nib = gnib;
-    if (!kG) {  // stage the palette and the brick's nibbles (16-byte aligned at both ends)
-        for (uint32_t e = tid; e < P; e += kThreadsB) reinterpret_cast<uint32_t *>(ar + lay.pal)[e] = h.rec[hdr + e];
-        uint4 *ln = reinterpret_cast<uint4 *>(ar + lay.nib);
-        const uint4 *src = reinterpret_cast<const uint4 *>(gnib);
-        for (uint32_t e = tid; e < (lay.nib_dw + 3) / 4; e += kThreadsB) ln[e] = src[e];
-        nib = reinterpret_cast<const uint32_t *>(ar + lay.nib);
-    }
-    if (tid == 0) sm->err = 0;
-    __syncthreads();
-    phase_mark(h.rq, 8);
-
+    const uint32_t L = lane(), t = h.t, P = h.P;
+    const uint32_t tl = t > 1 ? t : 1u;  // finest level replayed here
     uint32_t E = 1;    // expanded parents of the level being built (the root)
     uint32_t ipl = 0;  // P_a operations so far
     for (int m = kLog2 - 1; m >= (int)tl; m--) {
@@ -603,57 +639,23 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
         uint8_t *cbm = bm + kBmOff[m];
         const uint8_t *pbm = (m + 1 <= 4) ? bm + kBmOff[m + 1] : nullptr;
         const uint16_t *plist = (m + 1 <= 4) ? lst + kLstOff[m + 1] : nullptr;
-        const bool want_list = (m >= 2) || t == 0;
-        uint16_t *clist = (m >= 2) ? lst + kLstOff[m] : list1;
-        const uint32_t list_cap = (m >= 2) ? (1u << (3 * (kLog2 - m))) : e1cap;
+        const bool want_list = m >= 2;  // L_1's list is rebuilt from its bits by the leaf kernel
+        uint16_t *clist = lst + kLstOff[m];
+        const uint32_t list_cap = 1u << (3 * (kLog2 - m));
         // children of parents that are not expanded inherit the parent's index
-        for (uint32_t q = tid; q < np; q += kThreadsB) {
+        for (uint32_t q = L; q < np; q += 64) {
             const bool ex = pbm ? ((pbm[q >> 3] >> (q & 7)) & 1u) : true;
             cbm[q] = 0;
             if (!ex) *reinterpret_cast<VT *>(cur + 8 * q) = V::splat(up ? (uint32_t)up[q] : 0u);
         }
+        wave_sync<kG>();
         const uint32_t seg = (m == kLog2 - 1) ? 0u : h.c((uint32_t)m + 1), seg_end = h.c((uint32_t)m);
         if ((uint64_t)seg + 8ull * E > seg_end) return false;
         const uint32_t D = seg_end - seg - 8 * E, ops0 = seg + D;  // deltas precede the operations
-        const uint32_t nch = (E + 63) / 64, cpw = (nch + kWavesB - 1) / kWavesB;
-        const uint32_t cb = min(w * cpw, nch), ce = min(cb + cpw, nch);  // this wave's chunks
-        // pass 1: this wave's totals
-        uint32_t tpa = 0, tpd = 0, tex = 0;
-        for (uint32_t c = cb; c < ce; c++) {
-            const uint32_t r = 64 * c + L;
-            const bool act = r < E;
-            const uint32_t wd = act ? nib8(nib, ops0 + 8 * r) : 0u;
-            uint32_t pam, pdm, exm, cnt;
-            nibble_counts(wd, act, pam, pdm, exm, cnt);
-            const uint32_t tot = uniform(__builtin_amdgcn_readlane(wave_incl_scan(cnt), 63));
-            tpa += tot & 1023u;
-            tpd += (tot >> 10) & 1023u;
-            tex += tot >> 20;
-        }
-        if (L == 0) {
-            sm->wt[w][0] = tpa;
-            sm->wt[w][1] = tpd;
-            sm->wt[w][2] = tex;
-        }
-        __syncthreads();
-        uint32_t bpa = 0, bpd = 0, bex = 0, PAtot = 0, PDtot = 0, EXtot = 0;
-#pragma unroll
-        for (int v = 0; v < kWavesB; v++) {
-            const uint32_t a0 = sm->wt[v][0], a1 = sm->wt[v][1], a2 = sm->wt[v][2];
-            if ((uint32_t)v < w) {
-                bpa += a0;
-                bpd += a1;
-                bex += a2;
-            }
-            PAtot += a0;
-            PDtot += a1;
-            EXtot += a2;
-        }
-        if (PDtot != D || (want_list && EXtot > list_cap)) return false;
-        // pass 2: children
-        bool bad = false;
         const uint32_t pmask0 = axis_mask(0, Bp), pmask1 = axis_mask(1, Bp), pmask2 = axis_mask(2, Bp);
-        for (uint32_t c = cb; c < ce; c++) {
+        uint32_t bpa = 0, bpd = 0, bex = 0;
+        bool bad = false;
+        for (uint32_t c = 0; c < (E + 63) / 64; c++) {
             const uint32_t r = 64 * c + L;
             const bool act = r < E;
             const uint32_t q = (act && plist) ? (uint32_t)plist[r] : 0u;
@@ -673,7 +675,7 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
                     nbok |= hi ? (1u << a) : 0u;
                     lowok |= (q & am) ? (1u << a) : 0u;
                 }
-                const VT vals = replay_children<IdxT>(wd, pv, nb, nbok, lowok, ipl + bpa + (exc & 1023u),
+                const VT vals = replay8<IdxT>(wd, pv, nb, nbok, lowok, ipl + bpa + (exc & 1023u),
                                                       compact_nibble_bits(pam), compact_nibble_bits(pdm), nib,
                                                       seg + bpd + ((exc >> 10) & 1023u), P, false, bad);
                 *reinterpret_cast<VT *>(cur + 8 * q) = vals;
@@ -693,15 +695,14 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
             bpd += (tot >> 10) & 1023u;
             bex += tot >> 20;
         }
-        if (__ballot(bad) && L == 0) atomicOr(&sm->err, 1);
-        __syncthreads();
-        if (sm->err) return false;
+        if (__ballot(bad) || bpd != D || (want_list && bex > list_cap)) return false;
+        wave_sync<kG>();
         // neighbour references into this level: a reference to child k of
         // the -1 neighbour along a lands on child k | 1 << a, so a chain has
-        // at most three links; a chain is followed to its end while other
-        // lanes resolve in place (a reader sees either the reference or its
-        // final value, and both lead to the same value)
-        for (uint32_t r = tid; r < E; r += kThreadsB) {
+        // at most three links; it is followed to its end while other lanes
+        // resolve in place (a reader sees the reference or its final value,
+        // and both lead to the same value)
+        for (uint32_t r = L; r < E; r += 64) {
             const uint32_t q = plist ? (uint32_t)plist[r] : 0u;
             VT vals = *reinterpret_cast<const VT *>(cur + 8 * q);
             bool dirty = false;
@@ -722,50 +723,266 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
             }
             if (dirty) *reinterpret_cast<VT *>(cur + 8 * q) = vals;
         }
-        __syncthreads();
+        wave_sync<kG>();
         phase_mark(h.rq, 13 - m);
-        ipl += PAtot;
-        E = EXtot;
+        ipl += bpa;
+        E = bex;
     }
-    phase_mark(h.rq, 2);
+    E_out = E;
+    ipl_out = ipl;
+    return true;
+}
 
-    const uint32_t G = 32u >> t;
+// the level-t block (t >= 1) through the palette to dst, by one wave
+template <class IdxT, bool kG>
+__device__ __forceinline__ void upper_output(const IdxT *lv, uint32_t t, const uint32_t *pal, uint32_t P,
+                                             uint32_t *dst) {
+    const uint32_t L = lane(), G = 32u >> t;
+    const IdxT *res = lv + kLvOff[t];
+    if (t == 4) {
+        if (L < 8) dst[L] = pal_at<kG>(pal, res[L], P);  // Morton order equals dense order on 2^3
+        return;
+    }
     const bool al16 = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
-    if (t >= 1) {
-        // ---- output of an upper level -------------------------------------------
-        const IdxT *res = lv + kLvOff[t];
-        if (t == 4) {
-            if (tid < 8) dst[tid] = pal_at<kG>(pal, res[tid], P);  // Morton order equals dense order on 2^3
-        } else {
-            const uint32_t lg = (uint32_t)(kLog2 - t);
-            for (uint32_t e = 4 * tid; e < G * G * G; e += 4 * kThreadsB) {
-                const uint32_t x0 = e & (G - 1), yy = (e >> lg) & (G - 1), zz = e >> (2 * lg);
-                const uint32_t m0 = spread4(x0) | (spread4(yy) << 1) | (spread4(zz) << 2);
-                uint4 o;
-                o.x = pal_at<kG>(pal, res[m0], P);
-                o.y = pal_at<kG>(pal, res[m0 | 1u], P);
-                o.z = pal_at<kG>(pal, res[m0 | 8u], P);
-                o.w = pal_at<kG>(pal, res[m0 | 9u], P);
-                store4(dst + e, o, al16);
-            }
+    const uint32_t lg = (uint32_t)(kLog2 - t);
+    for (uint32_t e = 4 * L; e < G * G * G; e += 256) {
+        const uint32_t x0 = e & (G - 1), yy = (e >> lg) & (G - 1), zz = e >> (2 * lg);
+        const uint32_t m0 = spread4(x0) | (spread4(yy) << 1) | (spread4(zz) << 2);
+        uint4 o;
+        o.x = pal_at<kG>(pal, res[m0], P);
+        o.y = pal_at<kG>(pal, res[m0 | 1u], P);
+        o.z = pal_at<kG>(pal, res[m0 | 8u], P);
+        o.w = pal_at<kG>(pal, res[m0 | 9u], P);
+        store4(dst + e, o, al16);
+    }
+}
+
+// one brick of the front kernel after its entropy decode; false on a
+// malformed stream
+template <class IdxT, bool kG>
+__device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, const uint32_t *nib, uint8_t *slot,
+                                             uint8_t *wl, uint32_t *dst) {
+    const uint32_t L = lane();
+    const uint32_t hdr = csv::record_header_words(kLog2);
+    uint8_t *slv = slot + 4 * l.slot_dw;
+    uint8_t *sbm = slv + kSlotLv;
+    uint32_t *smeta = reinterpret_cast<uint32_t *>(sbm + kSlotBm);
+    IdxT *lv = kG ? reinterpret_cast<IdxT *>(slv) : reinterpret_cast<IdxT *>(wl + kWLv);
+    uint8_t *bm = wl + kWBm;
+    uint16_t *lst = reinterpret_cast<uint16_t *>(wl + kWLst);
+    uint32_t E1 = 0, ipl = 0;
+    if (!upper_replay<IdxT, kG>(h, nib, lv, bm, lst, E1, ipl)) return false;
+    if (h.t >= 1) {
+        const uint32_t *pal = h.rec + hdr;
+        if (!kG) {  // stage the palette next to the levels
+            uint32_t *sp = reinterpret_cast<uint32_t *>(wl + kWPal);
+            for (uint32_t e = L; e < h.P; e += 64) sp[e] = pal[e];
+            wsync();
+            pal = sp;
         }
-        phase_mark(h.rq, 5);
+        upper_output<IdxT, kG>(lv, h.t, pal, h.P, dst);
         return true;
     }
+    // t = 0: hand L_1 to the leaf kernel
+    if (!kG) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(lv);
+#pragma unroll
+        for (int q = 0; q < 4; q++) reinterpret_cast<uint4 *>(slv)[L + 64 * q] = src[L + 64 * q];
+    }
+    if (L < 32) reinterpret_cast<uint4 *>(sbm)[L] = reinterpret_cast<const uint4 *>(bm)[L];
+    if (L == 0) *reinterpret_cast<uint4 *>(smeta) = make_uint4(E1, ipl, 0u, 0u);
+    if (L == 0) {
+        const uint32_t at = atomicAdd(l.leaf_count, 1u);
+        l.leaf_list[at] = h.rq;
+    }
+    return true;
+}
 
-    // ---- leaf level ------------------------------------------------------------
-    const uint32_t E1 = E;
-    const IdxT *l1 = lv + kLvOff[1];
-    const uint8_t *bm1 = bm + kBmOff[1];
-    const uint64_t *bm1w = reinterpret_cast<const uint64_t *>(bm1);
-    IdxT *l0x = reinterpret_cast<IdxT *>(ar + lay.l0x);
-    if (w == 0) {  // rank prefix of the expanded L_1 bits, per 64-bit word
+// kLutLds: the decode tables of every volume are copied to LDS (else read
+// from global memory)
+template <int WPG, bool kLutLds>
+// 16 waves per CU at most (LDS); registers for 4 per SIMD
+__global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) void front_kernel(DecodeArgs a, LaunchA l) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *slut = reinterpret_cast<uint32_t *>(smem);
+    if (kLutLds)
+        for (uint32_t e = threadIdx.x; e < l.lut_lds_words; e += blockDim.x) slut[e] = a.luts[e];
+    __syncthreads();
+    const uint32_t L = lane(), wave = threadIdx.x >> 6;
+    uint8_t *wl = smem + align16(4 * l.lut_lds_words) + wave * kWaveLds;
+    const uint32_t wid = blockIdx.x * WPG + wave;
+    for (uint32_t k = 0;; k++) {
+        uint32_t req;
+        if (l.queue) {
+            uint32_t v = 0;
+            if (L == 0) v = atomicAdd(l.queue, 1u);
+            req = uniform(v) + l.base;
+        } else {
+            req = l.base + wid + k * gridDim.x * WPG;
+        }
+        if (req >= a.n) break;
+        const uint32_t rq = l.order ? l.order[req] : req;
+        phase_mark(rq, 0);
+        Hdr h;
+        uint32_t *dst, count, fill;
+        const ReqKind kind = load_request(a, rq, h, dst, count, fill);
+        if (kind == kReqBadLod) {
+            if (L == 0) report(a.err, CSV_ERANGE, rq);
+            continue;
+        }
+        if (kind != kReqDecode) {
+            if (kind != kReqFill && L == 0) report(a.err, kind == kReqBadId ? CSV_ERANGE : CSV_ECORRUPT,
+                                                   kind == kReqBadId ? rq : h.id);
+            fill_labels<64>(dst, count, kind == kReqFill ? fill : 0u, L);
+            continue;
+        }
+        const uint32_t n = h.c(h.t);
+        uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
+        uint32_t *nib = reinterpret_cast<uint32_t *>(slot);
+        if (n + 16 > 8 * l.slot_dw) {  // the slots are sized for the pool's largest brick
+            if (L == 0) report(a.err, CSV_EINVAL, h.id);
+            fill_labels<64>(dst, count, 0u, L);
+            continue;
+        }
+        bool ok = entropy_decode<kLutLds>(a, h, slut, reinterpret_cast<uint32_t *>(wl), nib, n);
+        phase_mark(rq, 1);
+        // this wave's nibble stores before its own loads of them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        wsync();  // the ring is reused for the levels
+        if (ok) ok = h.P <= kPalFast ? front_replay<uint8_t, false>(h, l, nib, slot, wl, dst)
+                                     : front_replay<uint16_t, true>(h, l, nib, slot, wl, dst);
+        if (!ok) {
+            if (L == 0) report(a.err, CSV_ECORRUPT, h.id);
+            fill_labels<64>(dst, count, 0u, L);
+        }
+        phase_mark(rq, 2);
+    }
+}
+
+// ===========================================================================
+// B. leaf kernel
+// ===========================================================================
+struct SmallB {
+    uint32_t req;
+    int err;
+    uint32_t wt[kWavesB][2];  // per-wave totals of P_a, P_delta
+};
+
+// Arena of a leaf brick: palette (P entries) and nib4 16-byte groups of
+// nibbles (staged only in LDS), L_1 as a dense 16^3 array, its expansion
+// bits (Morton order) and their rank prefix, the expanded L_1 nodes (dense
+// coordinates X | Y << 4 | Z << 8, stream order; list_cap entries) and the
+// dense 32^3 leaf level
+struct LayoutL {
+    uint32_t pal, nib, l1, bm1, bpre, list1, leaf, total;
+};
+__host__ __device__ constexpr LayoutL make_layout_l(bool stage, uint32_t P, uint32_t nib4, uint32_t list_cap,
+                                                    uint32_t idx) {
+    LayoutL L{};
+    uint32_t o = 0;
+    L.pal = o; o += stage ? align16(4 * P) : 0;
+    L.nib = o; o += stage ? 16 * nib4 : 0;
+    L.l1 = o; o += 4096 * idx;
+    L.bm1 = o; o += 512;
+    L.bpre = o; o += 128;
+    L.list1 = o; o += align16(2 * list_cap);
+    L.leaf = o; o += 32768 * idx;
+    L.total = o;
+    return L;
+}
+
+// global arena of a leaf brick that does not fit LDS
+constexpr uint32_t kArenaBytes = make_layout_l(false, 0, 0, 4096, 2).total;
+
+// coordinates of a 12-bit Morton index (x in bits 0, 3, 6, 9)
+__device__ __forceinline__ uint32_t morton_coord(uint32_t p) {
+    return (p & 1u) | ((p >> 2) & 2u) | ((p >> 4) & 4u) | ((p >> 6) & 8u);
+}
+
+// follow a chain of same-level references in the dense leaf level: value v
+// at voxel i, a reference to the voxel at -1 along axis v - kMark
+template <class IdxT>
+__device__ __forceinline__ uint32_t chase(const IdxT *D, uint32_t i, uint32_t v) {
+    constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
+    while (v >= kMark) {
+        const uint32_t a = v - kMark;
+        i -= a == 0 ? 1u : (a == 1 ? 32u : 1024u);
+        v = D[i];
+    }
+    return v;
+}
+
+// The leaf level L_0 of one brick by one workgroup, and its 32^3 output.
+// nib holds the nibbles from position nib0 on; l1m (Morton order) and bm1
+// come from the front kernel; pal is the palette; ar the arena.  False on a
+// malformed stream.
+template <class IdxT, bool kG>
+__device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t ipl, const uint32_t *nib,
+                                            uint32_t nib0, const IdxT *l1m, const uint64_t *bm1w,
+                                            const uint32_t *pal, uint8_t *ar, const LayoutL &lay, SmallB *sm,
+                                            uint32_t *dst) {
+    using V = Vec8<IdxT>;
+    using VT = typename V::T;
+    const uint32_t tid = threadIdx.x, L = lane(), w = tid >> 6;
+    const uint32_t P = h.P;
+    IdxT *l1 = reinterpret_cast<IdxT *>(ar + lay.l1);             // X + 16 Y + 256 Z
+    uint16_t *bpre = reinterpret_cast<uint16_t *>(ar + lay.bpre);
+    uint16_t *list1 = reinterpret_cast<uint16_t *>(ar + lay.list1);
+    IdxT *D = reinterpret_cast<IdxT *>(ar + lay.leaf);            // x + 32 y + 1024 z
+    const uint32_t seg = h.c1, seg_end = h.c0;
+    if ((uint64_t)seg + 8ull * E1 > seg_end || E1 > 4096) return false;
+    // L_1 to dense order: Morton indices 16t .. 16t + 15 share bits 4.. of t
+    for (uint32_t t = tid; t < 256; t += kThreadsB) {
+        const uint32_t base = (((t >> 2) & 1u) << 2 | ((t >> 5) & 1u) << 3) +
+                              16 * (((t & 1u) << 1) | (((t >> 3) & 1u) << 2) | (((t >> 6) & 1u) << 3)) +
+                              256 * ((((t >> 1) & 1u) << 1) | (((t >> 4) & 1u) << 2) | (((t >> 7) & 1u) << 3));
+        IdxT v[16];
+        if constexpr (sizeof(IdxT) == 1) {
+            const uint4 q = reinterpret_cast<const uint4 *>(l1m)[t];
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 16; j++) v[j] = (IdxT)((qq[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+        } else {
+            const uint4 q0 = reinterpret_cast<const uint4 *>(l1m)[2 * t], q1 = reinterpret_cast<const uint4 *>(l1m)[2 * t + 1];
+            const uint32_t qq[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int j = 0; j < 16; j++) v[j] = (IdxT)((qq[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            l1[base + (j & 1) + 2 * ((j >> 3) & 1) + 16 * ((j >> 1) & 1) + 256 * ((j >> 2) & 1)] = v[j];
+    }
+    if (w == 0) {  // rank prefix of the expansion bits, per 64-bit word
         const uint32_t c = (uint32_t)__popcll(bm1w[L]);
         bpre[L] = (uint16_t)(wave_incl_scan(c) - c);
     }
-    const uint32_t seg = h.c1, seg_end = h.c0;
-    if ((uint64_t)seg + 8ull * E1 > seg_end) return false;
-    const uint32_t D0 = seg_end - seg - 8 * E1, ops0 = seg + D0;
+    __syncthreads();
+    // every voxel takes its L_1 node's value (expanded nodes are overwritten
+    // below); pass 1: this wave's P_a and P_delta totals
+    for (uint32_t e = tid; e < 2048; e += kThreadsB) {  // half rows of 16 voxels
+        const uint32_t hx = e & 1u, y = (e >> 1) & 31u, z = e >> 6;
+        const IdxT *src = l1 + 8 * hx + 16 * (y >> 1) + 256 * (z >> 1);
+        IdxT *o = D + 16 * hx + 32 * y + 1024 * z;
+        if constexpr (sizeof(IdxT) == 1) {
+            const uint2 q = *reinterpret_cast<const uint2 *>(src);
+            *reinterpret_cast<uint4 *>(o) =
+                make_uint4(__builtin_amdgcn_perm(q.y, q.x, 0x01010000u), __builtin_amdgcn_perm(q.y, q.x, 0x03030202u),
+                           __builtin_amdgcn_perm(q.y, q.x, 0x05050404u), __builtin_amdgcn_perm(q.y, q.x, 0x07070606u));
+        } else {
+            const uint4 q = *reinterpret_cast<const uint4 *>(src);
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+            uint32_t r[8];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                r[2 * j] = __builtin_amdgcn_perm(qq[j], qq[j], 0x01000100u);
+                r[2 * j + 1] = __builtin_amdgcn_perm(qq[j], qq[j], 0x03020302u);
+            }
+            reinterpret_cast<uint4 *>(o)[0] = make_uint4(r[0], r[1], r[2], r[3]);
+            reinterpret_cast<uint4 *>(o)[1] = make_uint4(r[4], r[5], r[6], r[7]);
+        }
+    }
+    const uint32_t D0 = seg_end - seg - 8 * E1, ops0 = seg + D0 - nib0;
     const uint32_t nch = (E1 + 63) / 64, cpw = (nch + kWavesB - 1) / kWavesB;
     const uint32_t cb = min(w * cpw, nch), ce = min(cb + cpw, nch);
     uint32_t tpa = 0, tpd = 0;
@@ -784,6 +1001,19 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
         sm->wt[w][1] = tpd;
     }
     __syncthreads();
+    // the expanded L_1 nodes in Morton (= stream) order, from the bitmask
+    for (uint32_t t = tid; t < 256; t += kThreadsB) {
+        const uint32_t wd = t >> 2, q = t & 3u;
+        const uint64_t word = bm1w[wd];
+        uint32_t bits = (uint32_t)(word >> (16 * q)) & 0xFFFFu;
+        uint32_t pos = bpre[wd] + (uint32_t)__popcll(word & ((1ull << (16 * q)) - 1ull));
+        while (bits) {
+            const uint32_t p = 64 * wd + 16 * q + (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1;
+            if (pos < E1) list1[pos] = (uint16_t)(morton_coord(p) | (morton_coord(p >> 1) << 4) | (morton_coord(p >> 2) << 8));
+            pos++;
+        }
+    }
     uint32_t bpa = 0, bpd = 0, PDtot = 0;
 #pragma unroll
     for (int v = 0; v < kWavesB; v++) {
@@ -794,34 +1024,45 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
         }
         PDtot += a1;
     }
+    __syncthreads();
     if (PDtot != D0) return false;
+    phase_mark(h.rq, 3);
+    // pass 2: the children of every expanded L_1 node into the dense level
     bool bad = false;
-    const uint32_t m0 = axis_mask(0, 4), m1 = axis_mask(1, 4), m2 = axis_mask(2, 4);
     for (uint32_t c = cb; c < ce; c++) {
         const uint32_t r = 64 * c + L;
         const bool act = r < E1;
         const uint32_t wd = act ? nib8(nib, ops0 + 8 * r) : 0u;
-        const uint32_t p = act ? (uint32_t)list1[r] : 0u;
+        const uint32_t cc = act ? (uint32_t)list1[r] : 0u;
         uint32_t pam, pdm, exm, cnt;
         nibble_counts(wd, act, pam, pdm, exm, cnt);
         cnt &= 0xFFFFFu;
         const uint32_t inc = wave_incl_scan(cnt), exc = inc - cnt;
         const uint32_t tot = uniform(__builtin_amdgcn_readlane(inc, 63));
         if (act) {
-            const uint32_t pv = l1[p];
-            uint32_t nbv[3], nbok = 0, lowok = 0;
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-                const uint32_t am = a == 0 ? m0 : (a == 1 ? m1 : m2);
-                const bool hi = (p & am) != am;
-                nbv[a] = hi ? (uint32_t)l1[morton_inc(p, am)] : 0u;
-                nbok |= hi ? (1u << a) : 0u;
-                lowok |= (p & am) ? (1u << a) : 0u;
+            const uint32_t X = cc & 15u, Y = (cc >> 4) & 15u, Z = (cc >> 8) & 15u;
+            const uint32_t i = X + 16 * Y + 256 * Z;
+            const uint32_t pv = l1[i];
+            const uint32_t nbv[3] = {X < 15 ? (uint32_t)l1[i + 1] : 0u, Y < 15 ? (uint32_t)l1[i + 16] : 0u,
+                                     Z < 15 ? (uint32_t)l1[i + 256] : 0u};
+            const uint32_t nbok = (X < 15 ? 1u : 0u) | (Y < 15 ? 2u : 0u) | (Z < 15 ? 4u : 0u);
+            const uint32_t lowok = (X > 0 ? 1u : 0u) | (Y > 0 ? 2u : 0u) | (Z > 0 ? 4u : 0u);
+            const VT vals = replay8<IdxT>(wd, pv, nbv, nbok, lowok, ipl + bpa + (exc & 1023u),
+                                          compact_nibble_bits(pam), compact_nibble_bits(pdm), nib,
+                                          seg - nib0 + bpd + ((exc >> 10) & 1023u), P, true, bad);
+            // child k = kx | ky << 1 | kz << 2 at voxel (2X + kx, 2Y + ky, 2Z + kz): x pairs
+            const uint32_t v0 = 2 * X + 64 * Y + 2048 * Z;
+            if constexpr (sizeof(IdxT) == 1) {
+                *reinterpret_cast<uint16_t *>(D + v0) = (uint16_t)(vals.x & 0xFFFFu);
+                *reinterpret_cast<uint16_t *>(D + v0 + 32) = (uint16_t)(vals.x >> 16);
+                *reinterpret_cast<uint16_t *>(D + v0 + 1024) = (uint16_t)(vals.y & 0xFFFFu);
+                *reinterpret_cast<uint16_t *>(D + v0 + 1056) = (uint16_t)(vals.y >> 16);
+            } else {
+                *reinterpret_cast<uint32_t *>(D + v0) = vals.x;
+                *reinterpret_cast<uint32_t *>(D + v0 + 32) = vals.y;
+                *reinterpret_cast<uint32_t *>(D + v0 + 1024) = vals.z;
+                *reinterpret_cast<uint32_t *>(D + v0 + 1056) = vals.w;
             }
-            const VT vals = replay_children<IdxT>(wd, pv, nbv, nbok, lowok, ipl + bpa + (exc & 1023u),
-                                                  compact_nibble_bits(pam), compact_nibble_bits(pdm), nib,
-                                                  seg + bpd + ((exc >> 10) & 1023u), P, true, bad);
-            *reinterpret_cast<VT *>(l0x + 8 * r) = vals;
         }
         bpa += tot & 1023u;
         bpd += (tot >> 10) & 1023u;
@@ -829,110 +1070,107 @@ __device__ __forceinline__ bool replay_brick(const Hdr &h, const uint32_t *gnib,
     if (__ballot(bad) && L == 0) atomicOr(&sm->err, 1);
     __syncthreads();
     if (sm->err) return false;
-    phase_mark(h.rq, 3);
-    // leaf neighbour references, resolved as on the upper levels; a chain
-    // ends at a non-expanded L_1 node, whose value is final
-    for (uint32_t r = tid; r < E1; r += kThreadsB) {
-        VT vals = *reinterpret_cast<const VT *>(l0x + 8 * r);
-        bool dirty = false;
-        uint32_t p = 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 0; k < 7; k++) {
-            uint32_t v = V::get(vals, k);
-            if (v >= kMark) {
-                if (p == 0xFFFFFFFFu) p = list1[r];
-                uint32_t pp = p, kk = (uint32_t)k;
-                do {
-                    const int a = (int)(v - kMark);
-                    pp = morton_dec(pp, a == 0 ? m0 : (a == 1 ? m1 : m2));
-                    kk |= 1u << a;
-                    if ((bm1[pp >> 3] >> (pp & 7)) & 1u) {
-                        const uint32_t rk = bpre[pp >> 6] + (uint32_t)__popcll(bm1w[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
-                        v = l0x[8 * rk + kk];
-                    } else {
-                        v = l1[pp];
-                    }
-                } while (v >= kMark);
-                V::set(vals, k, v);
-                dirty = true;
-            }
-        }
-        if (dirty) *reinterpret_cast<VT *>(l0x + 8 * r) = vals;
-    }
-    __syncthreads();
     phase_mark(h.rq, 4);
-
-    // ---- leaf output: a lane covers two x-adjacent L_1 nodes, 4 rows of 16 bytes ----
-    for (uint32_t it = w; it < 32; it += kWavesB) {
-        const uint32_t xp = L & 7u, Y = (L >> 3) | ((it & 1u) << 3), Z = it >> 1;
-        const uint32_t p0 = spread4(2 * xp) | (spread4(Y) << 1) | (spread4(Z) << 2);
-        VT v8[2];
+    // output: a wave writes 8 whole rows of a z slice per store; lane L
+    // covers voxels 4 (L & 7) .. + 3 of rows (L >> 3) + 8c; references are
+    // followed along the dense level (at most three links)
+    constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
+    const bool al16 = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+    for (uint32_t zz = w; zz < 32; zz += kWavesB) {
 #pragma unroll
-        for (int b = 0; b < 2; b++) {
-            const uint32_t p = p0 | (uint32_t)b;
-            if ((bm1[p >> 3] >> (p & 7)) & 1u) {
-                const uint32_t rk = bpre[p >> 6] + (uint32_t)__popcll(bm1w[p >> 6] & ((1ull << (p & 63)) - 1ull));
-                v8[b] = *reinterpret_cast<const VT *>(l0x + 8 * rk);
+        for (int c = 0; c < 4; c++) {
+            const uint32_t v0 = 4 * (L & 7u) + 32 * ((L >> 3) + 8 * (uint32_t)c) + 1024 * zz;
+            uint32_t idx[4];
+            if constexpr (sizeof(IdxT) == 1) {
+                const uint32_t q = *reinterpret_cast<const uint32_t *>(D + v0);
+#pragma unroll
+                for (int b = 0; b < 4; b++) idx[b] = (q >> (8 * b)) & 0xFFu;
+                // bytes >= 252: a reference (252 never survives the checks)
+                const uint32_t t = ~q & 0xFCFCFCFCu;
+                if (((t - 0x01010101u) & ~t & 0x80808080u) != 0) {
+#pragma unroll
+                    for (int b = 0; b < 4; b++)
+                        if (idx[b] >= kMark) idx[b] = chase<IdxT>(D, v0 + (uint32_t)b, idx[b]);
+                }
             } else {
-                v8[b] = V::splat(l1[p]);
-            }
-        }
+                const uint2 q = *reinterpret_cast<const uint2 *>(D + v0);
+                idx[0] = q.x & 0xFFFFu;
+                idx[1] = q.x >> 16;
+                idx[2] = q.y & 0xFFFFu;
+                idx[3] = q.y >> 16;
 #pragma unroll
-        for (int c = 0; c < 4; c++) {  // c = cy | cz << 1
-            const int k0 = ((c & 1) << 1) | ((c >> 1) << 2);
+                for (int b = 0; b < 4; b++)
+                    if (idx[b] >= kMark) idx[b] = chase<IdxT>(D, v0 + (uint32_t)b, idx[b]);
+            }
             uint4 o;
-            o.x = pal_at<kG>(pal, V::get(v8[0], k0), P);
-            o.y = pal_at<kG>(pal, V::get(v8[0], k0 | 1), P);
-            o.z = pal_at<kG>(pal, V::get(v8[1], k0), P);
-            o.w = pal_at<kG>(pal, V::get(v8[1], k0 | 1), P);
-            const uint32_t yy = 2 * Y + (uint32_t)(c & 1), zz = 2 * Z + (uint32_t)(c >> 1);
-            store4(dst + 4 * xp + 32 * (yy + 32 * zz), o, al16);
+            o.x = pal_at<kG>(pal, idx[0], P);
+            o.y = pal_at<kG>(pal, idx[1], P);
+            o.z = pal_at<kG>(pal, idx[2], P);
+            o.w = pal_at<kG>(pal, idx[3], P);
+            store4(dst + v0, o, al16);
         }
     }
     phase_mark(h.rq, 5);
     return true;
 }
 
-__global__ __launch_bounds__(kThreadsB) CSV_REPLAY_ATTR void replay_kernel(DecodeArgs a, LaunchB l) {
+__global__ __launch_bounds__(kThreadsB) CSV_LEAF_ATTR void leaf_kernel(DecodeArgs a, LaunchB l) {
     extern __shared__ __align__(16) uint8_t smem[];
     SmallB *sm = reinterpret_cast<SmallB *>(smem);
     uint8_t *arena = smem + align16(sizeof(SmallB));
-    uint8_t *gslot = l.scratch ? l.scratch + (size_t)blockIdx.x * l.slot_bytes : nullptr;
+    uint8_t *gslot = l.scratch ? glob(l.scratch) + (size_t)blockIdx.x * l.scratch_bytes : nullptr;
     const uint32_t tid = threadIdx.x;
+    const uint32_t hdr = csv::record_header_words(kLog2);
+    const uint32_t n_leaf = *glob(l.leaf_count);
     for (uint32_t k = 0;; k++) {
-        if (tid == 0) sm->req = l.queue ? atomicAdd(l.queue, 1u) + l.base : l.base + blockIdx.x + k * gridDim.x;
+        if (tid == 0) sm->req = l.queue ? atomicAdd(l.queue, 1u) : blockIdx.x + k * gridDim.x;
         __syncthreads();
-        const uint32_t req = sm->req;
-        if (req >= a.n) break;
-        const uint32_t rq = l.order ? l.order[req] : req;
+        const uint32_t item = sm->req;
+        if (item >= n_leaf) break;
+        const uint32_t rq = l.leaf_list[item];
         Hdr h;
         uint32_t *dst, count, fill;
-        const ReqKind kind = load_request(a, rq, h, dst, count, fill);
-        const uint8_t st = l.status[rq];
-        if (kind == kReqBadLod || st == kStNone) {
-            // nothing to write (reported by the entropy decoder)
-        } else if (kind != kReqDecode || st == kStFail) {
-            wg_fill(dst, count, (kind == kReqFill && st == kStOk) ? fill : 0u);
-        } else {
-            const uint32_t *nib = glob(l.nib) + (size_t)rq * l.slot_dw;
-            const uint32_t S0 = h.t == 0 ? h.c0 - h.c1 : 0u;
-            const LayoutB fast = make_layout_b(true, h.P, S0, 1, (h.c(h.t) + 7) / 8 + 2);
-            const bool fits = h.P <= kPalFast && fast.total <= l.arena_bytes;
-            bool ok;
-            phase_mark(rq, 6);
-            if (fits) {
-                ok = replay_brick<uint8_t, false>(h, nib, arena, fast, sm, dst);
-            } else if (gslot) {
-                phase_mark(rq, 7);
-                ok = replay_brick<uint16_t, true>(h, nib, gslot, make_layout_b(false, h.P, S0, 2, 0), sm, dst);
-            } else {
-                ok = false;
-            }
+        (void)load_request(a, rq, h, dst, count, fill);  // a decode at t = 0: checked by the front kernel
+        phase_mark(rq, 6);
+        const uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
+        const uint32_t *gnib = reinterpret_cast<const uint32_t *>(slot);
+        const uint8_t *slv = slot + 4 * l.slot_dw;
+        const uint8_t *sbm = slv + kSlotLv;
+        const uint4 meta = *reinterpret_cast<const uint4 *>(sbm + kSlotBm);
+        const uint32_t E1 = uniform(meta.x), ipl = uniform(meta.y);
+        const uint32_t E1c = E1 < 4096 ? E1 : 4096u;
+        // nibbles from the delta segment of L_0 on, from a 16-byte boundary
+        const uint32_t nb0 = (h.c1 >> 5) << 2, nib4 = (((h.c0 + 7) >> 3) + 2 - nb0 + 3) / 4;
+        const LayoutL fast = make_layout_l(true, h.P, nib4, E1c, 1);
+        const bool fits = h.P <= kPalFast && fast.total <= l.arena_bytes;
+        if (tid == 0) sm->err = 0;
+        bool ok;
+        if (fits) {
+            for (uint32_t e = tid; e < h.P; e += kThreadsB) reinterpret_cast<uint32_t *>(arena + fast.pal)[e] = h.rec[hdr + e];
+            for (uint32_t e = tid; e < nib4; e += kThreadsB)
+                reinterpret_cast<uint4 *>(arena + fast.nib)[e] = reinterpret_cast<const uint4 *>(gnib + nb0)[e];
+            if (tid < 32) reinterpret_cast<uint4 *>(arena + fast.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
             __syncthreads();
-            if (!ok) {
-                if (tid == 0) report(a.err, (fits || gslot) ? CSV_ECORRUPT : CSV_EINVAL, h.id);
-                wg_fill(dst, count, 0);
-            }
+            ok = leaf_replay<uint8_t, false>(h, E1, ipl, reinterpret_cast<const uint32_t *>(arena + fast.nib), 8 * nb0,
+                                             slv, reinterpret_cast<const uint64_t *>(arena + fast.bm1),
+                                             reinterpret_cast<const uint32_t *>(arena + fast.pal), arena, fast, sm, dst);
+        } else if (gslot) {
+            phase_mark(rq, 7);
+            __syncthreads();
+            const uint64_t *gbm = reinterpret_cast<const uint64_t *>(sbm);
+            if (h.P <= kPalFast)
+                ok = leaf_replay<uint8_t, true>(h, E1, ipl, gnib, 0, slv, gbm, h.rec + hdr, gslot,
+                                                make_layout_l(false, 0, 0, 4096, 1), sm, dst);
+            else
+                ok = leaf_replay<uint16_t, true>(h, E1, ipl, gnib, 0, reinterpret_cast<const uint16_t *>(slv), gbm,
+                                                 h.rec + hdr, gslot, make_layout_l(false, 0, 0, 4096, 2), sm, dst);
+        } else {
+            ok = false;
+        }
+        __syncthreads();
+        if (!ok) {
+            if (tid == 0) report(a.err, fits || gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
+            fill_labels<kThreadsB>(dst, count, 0u, tid);
         }
         __syncthreads();
     }
@@ -981,40 +1219,41 @@ __global__ void zero_words(uint32_t *p, uint32_t n) {
 struct LaunchBufs {
     hipStream_t stream = nullptr;
     uint64_t last_use = 0;
-    uint32_t *nib = nullptr;
-    uint8_t *status = nullptr;
-    uint32_t *order = nullptr;
-    uint32_t *small = nullptr;  // [0, 64): order bins; [64, 66): work counters
+    uint8_t *slots = nullptr;      // slot_bytes per request
+    uint32_t *order = nullptr;     // longest-first order
+    uint32_t *leaf_list = nullptr; // requests for the leaf kernel
+    uint32_t *small = nullptr;     // [0, 64): order bins; 64, 65: work counters; 66: leaf count
     uint32_t slot_dw = 0;
     uint32_t cap_n = 0;
+    uint32_t slot_bytes() const { return 4 * slot_dw + kSlotExtra; }
     void release() {
-        (void)hipFree(nib);
-        (void)hipFree(status);
+        (void)hipFree(slots);
         (void)hipFree(order);
+        (void)hipFree(leaf_list);
         (void)hipFree(small);
-        nib = nullptr;
-        status = nullptr;
+        slots = nullptr;
         order = nullptr;
+        leaf_list = nullptr;
         small = nullptr;
         cap_n = 0;
     }
-    // room for n requests of slot_dw nibble dwords each
+    // room for n requests with slot_dw nibble dwords each
     int reserve(uint32_t n, uint32_t dw) {
-        if (nib && n <= cap_n && dw == slot_dw) return CSV_OK;
+        if (slots && n <= cap_n && dw == slot_dw) return CSV_OK;
         release();
         const uint32_t cap = std::max(n, 1024u);
-        if (hipMalloc(reinterpret_cast<void **>(&nib), 4ull * cap * dw + 64) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&status), cap) != hipSuccess ||
+        slot_dw = dw;
+        if (hipMalloc(reinterpret_cast<void **>(&slots), (size_t)cap * slot_bytes()) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&order), 4ull * cap) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&small), 4 * 66) != hipSuccess) {
+            hipMalloc(reinterpret_cast<void **>(&leaf_list), 4ull * cap) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&small), 4 * 68) != hipSuccess) {
             release();
             return CSV_ENOMEM;
         }
         cap_n = cap;
-        slot_dw = dw;
         return CSV_OK;
     }
-    uint64_t bytes() const { return nib ? (4ull * cap_n * slot_dw + 64 + 5ull * cap_n + 4 * 66) : 0; }
+    uint64_t bytes() const { return slots ? ((uint64_t)cap_n * (slot_bytes() + 8) + 4 * 68) : 0; }
 };
 constexpr size_t kMaxStreamBufs = 16;
 
@@ -1046,7 +1285,7 @@ struct csv_pool {
     uint32_t max_fast_bytes = 0;              // largest LDS arena a brick of the pool needs
     bool any_big_palette = false;
     uint32_t generation = 0;                  // bumped when device tables move
-    csv_shape shape{16, 4, 1, 0, 0.f};        // launch shape of csv_decode_bricks
+    csv_shape shape{16, 3, 1, 0, 0.f};        // launch shape of csv_decode_bricks
     uint64_t record_bytes = 0;
     std::mutex mu;
 };
@@ -1087,7 +1326,7 @@ uint32_t lut_lds_words(const csv_pool *p) {
     return (4 * lw <= kLutLdsCap) ? lw : 0u;
 }
 // nibble dwords per request: a multiple of 4, so every request's nibbles start 16-byte aligned
-uint32_t slot_dw(const csv_pool *p) { return ((p->max_c0 + 7) / 8 + 4 + 3) & ~3u; }
+uint32_t slot_dw(const csv_pool *p) { return ((p->max_c0 + 7) / 8 + 8 + 3) & ~3u; }
 constexpr uint32_t kSmallB = (sizeof(SmallB) + 15u) & ~15u;
 constexpr uint32_t kMaxGroupsB = 8;
 // replay arena when `groups` replay workgroups share a CU's LDS
@@ -1115,9 +1354,9 @@ int stream_bufs(csv_pool *pool, hipStream_t s, uint32_t n, LaunchBufs **out) {
     }
     b->last_use = ++pool->use_clock;
     const uint32_t dw = slot_dw(pool);
-    if (!b->nib || n > b->cap_n || dw != b->slot_dw) {
+    if (!b->slots || n > b->cap_n || dw != b->slot_dw) {
         if (cap) return CSV_EBUSY;  // buffers cannot be re-sized inside a capture
-        if (b->nib && hipStreamSynchronize(s) != hipSuccess) return CSV_EHIP;
+        if (b->slots && hipStreamSynchronize(s) != hipSuccess) return CSV_EHIP;
         const int rc = b->reserve(n, dw);
         if (rc) return rc;
     }
@@ -1135,16 +1374,16 @@ template <int WPG>
 void launch_a(const DecodeArgs &a, const LaunchA &l, uint32_t grid, size_t lds, hipStream_t s) {
     static std::once_flag once;
     std::call_once(once, [] {
-        (void)set_lds_attr(rans_kernel<WPG, true>);
-        (void)set_lds_attr(rans_kernel<WPG, false>);
+        (void)set_lds_attr(front_kernel<WPG, true>);
+        (void)set_lds_attr(front_kernel<WPG, false>);
     });
     if (l.lut_lds_words)
-        hipLaunchKernelGGL((rans_kernel<WPG, true>), dim3(grid), dim3(64 * WPG), lds, s, a, l);
+        hipLaunchKernelGGL((front_kernel<WPG, true>), dim3(grid), dim3(64 * WPG), lds, s, a, l);
     else
-        hipLaunchKernelGGL((rans_kernel<WPG, false>), dim3(grid), dim3(64 * WPG), lds, s, a, l);
+        hipLaunchKernelGGL((front_kernel<WPG, false>), dim3(grid), dim3(64 * WPG), lds, s, a, l);
 }
 
-// waves_a: entropy-decoder waves per workgroup; groups_b: replay workgroups
+// waves_a: front-kernel waves per workgroup; groups_b: leaf workgroups
 // per CU; fixed: buffers owned by the caller (a captured graph), else the
 // stream's own set
 int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
@@ -1161,7 +1400,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     static std::once_flag once_b;
     static hipError_t attr_b = hipSuccess;
-    std::call_once(once_b, [] { attr_b = set_lds_attr(replay_kernel); });
+    std::call_once(once_b, [] { attr_b = set_lds_attr(leaf_kernel); });
     if (attr_b != hipSuccess) return CSV_EHIP;
     std::lock_guard<std::mutex> lk(pool->mu);
     LaunchBufs *B = fixed;
@@ -1186,28 +1425,31 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     a.out = out;
     a.n = n;
     a.err = pool->d_err;
+    uint32_t *ctr = B->small + 2 * kBins;  // front counter, leaf counter, leaf list length
     LaunchA la;
     la.lut_lds_words = lut_lds_words(pool);
-    la.queue = nullptr;
+    la.queue = queue ? ctr : nullptr;
     la.order = nullptr;
-    la.nib = B->nib;
+    la.slots = B->slots;
+    la.slot_bytes = B->slot_bytes();
     la.slot_dw = B->slot_dw;
-    la.status = B->status;
+    la.leaf_list = B->leaf_list;
+    la.leaf_count = ctr + 2;
     la.base = 0;
     LaunchB lb;
     lb.arena_bytes = arena_b(groups_b);
-    lb.queue = nullptr;
-    lb.order = nullptr;
-    lb.nib = la.nib;
-    lb.slot_dw = la.slot_dw;
-    lb.status = la.status;
+    lb.queue = (queue || plain) ? ctr + 1 : nullptr;
+    lb.leaf_list = B->leaf_list;
+    lb.leaf_count = ctr + 2;
+    lb.slots = B->slots;
+    lb.slot_bytes = B->slot_bytes();
+    lb.slot_dw = B->slot_dw;
     lb.scratch = pool->d_scratch;
-    lb.slot_bytes = pool->slot_bytes;
-    lb.base = 0;
+    lb.scratch_bytes = kArenaBytes;
     const size_t lds_b = kSmallB + (size_t)lb.arena_bytes;
     const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
-    // entropy decoder: as many workgroups as a CU's LDS and 32 wave slots allow
-    const uint32_t lds_a = align16(4 * la.lut_lds_words) + (uint32_t)waves_a * kRingWords * 2;
+    // front kernel: as many workgroups as a CU's LDS and 32 wave slots allow
+    const uint32_t lds_a = align16(4 * la.lut_lds_words) + (uint32_t)waves_a * kWaveLds;
     const uint32_t fit_a = std::max(1u, std::min(kLdsBytes / lds_a, 32u / (uint32_t)waves_a));
     const uint32_t grid_a = std::max(1u, std::min(cu * fit_a, (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a));
     uint32_t grid_b = std::min(cu * groups_b, n);
@@ -1220,30 +1462,27 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
         }
     };
     if (plain) {
+        // per brick: counter reset, front kernel (one wave), leaf kernel (one workgroup)
         DecodeArgs b = a;
         for (uint32_t i = 0; i < n; i++) {
-            la.base = lb.base = i;
+            la.base = i;
             b.n = i + 1;
+            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 3u);
             go_a(b, la, 1);
-            hipLaunchKernelGGL(replay_kernel, dim3(1), dim3(kThreadsB), lds_b, s, b, lb);
+            hipLaunchKernelGGL(leaf_kernel, dim3(1), dim3(kThreadsB), lds_b, s, b, lb);
         }
     } else {
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 3u);
         if (lpt) {
             const uint32_t gq = std::min<uint32_t>((n + 255) / 256, 1024u);
             hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, B->small, 2u * kBins);
             hipLaunchKernelGGL(order_count, dim3(gq), dim3(256), 0, s, a, B->small);
             hipLaunchKernelGGL(order_scan, dim3(1), dim3(64), 0, s, B->small);
             hipLaunchKernelGGL(order_scatter, dim3(gq), dim3(256), 0, s, a, B->small, B->order);
-            la.order = lb.order = B->order;
-        }
-        if (queue) {
-            uint32_t *q = B->small + 2 * kBins;
-            la.queue = q;
-            lb.queue = q + 1;
-            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, q, 2u);
+            la.order = B->order;
         }
         go_a(a, la, grid_a);
-        hipLaunchKernelGGL(replay_kernel, dim3(grid_b), dim3(kThreadsB), lds_b, s, a, lb);
+        hipLaunchKernelGGL(leaf_kernel, dim3(grid_b), dim3(kThreadsB), lds_b, s, a, lb);
     }
     return hipGetLastError() == hipSuccess ? CSV_OK : CSV_EHIP;
 }
@@ -1322,7 +1561,8 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
         if (c1 > c0 || c0 > kMaxSym) return CSV_ECORRUPT;
         big |= P > kPalFast;
         max_c0 = std::max(max_c0, c0);
-        max_fast = std::max(max_fast, make_layout_b(true, P, c0 - c1, 1, (c0 + 7) / 8 + 2).total);
+        const uint32_t e1 = std::min((c0 - c1) / 8, 4096u), nb0 = (c1 >> 5) << 2;
+        max_fast = std::max(max_fast, make_layout_l(true, P, (((c0 + 7) >> 3) + 2 - nb0 + 3) / 4, e1, 1).total);
     }
     // the kernels run to the end of a record; 64 bytes of slack cover their last vector loads
     void *buf = nullptr;
@@ -1336,7 +1576,7 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     (void)hipDeviceSynchronize();
     // a global replay arena per replay workgroup when some brick may not fit an LDS arena
     if ((big || max_fast > min_arena_b()) && !p->d_scratch) {
-        p->slot_bytes = align16(make_layout_b(false, 0, kMaxSym, 2, 0).total);
+        p->slot_bytes = kArenaBytes;
         if (hipMalloc(reinterpret_cast<void **>(&p->d_scratch), (size_t)p->slot_bytes * p->n_slots) != hipSuccess) {
             (void)hipFree(buf);
             p->slot_bytes = 0;

@@ -20,7 +20,6 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <list>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -49,11 +48,16 @@ struct Entry {
     uint32_t brick = 0;
     uint8_t lod = 0;
     State state = kFree;
+    bool in_lru = false;
     uint32_t pins = 0;               // completions not yet released by the next poll
     uint64_t slot = 0;               // byte offset in the cache
-    std::list<uint32_t>::iterator lru;
-    bool in_lru = false;
-    std::vector<uint32_t> waiters;   // indices into the request table
+    int32_t prev = -1, next = -1;    // LRU neighbours within the LOD class (prev: more recent)
+    int32_t waiters = -1;            // first request waiting for this decode (chained by req_next)
+};
+
+// intrusive LRU list of one LOD class: head most recent
+struct Lru {
+    int32_t head = -1, tail = -1;
 };
 
 struct Pending {
@@ -86,7 +90,7 @@ struct csv_server {
     // cache allocator: pages carved per LOD class, free stacks, per-class LRU
     uint64_t top = 0;
     std::vector<uint64_t> free_slots[kClasses];
-    std::list<uint32_t> lru[kClasses];  // front = most recent
+    Lru lru[kClasses];
     std::vector<Entry> entries;
     std::vector<uint32_t> free_entries;
     std::vector<int32_t> index;  // brick * 6 + lod -> entry id or -1
@@ -95,6 +99,7 @@ struct csv_server {
     std::vector<csv_request> inbox;
     std::deque<Pending> pending;
     std::vector<csv_request> reqs;   // request table (worker)
+    std::vector<int32_t> req_next;   // next waiter of the same decode
     std::vector<uint32_t> free_reqs;
     std::mutex out_mu;
     std::vector<csv_completion> outbox;
@@ -105,6 +110,11 @@ struct csv_server {
     std::vector<Batch> batches;
     Batch *forming = nullptr;
     uint64_t inflight = 0;
+    // worker-local completions and statistics, published once per loop
+    std::vector<csv_completion> c_local;
+    std::vector<int32_t> e_local;
+    std::vector<float> l_all, l_miss;
+    uint64_t d_req = 0, d_hit = 0, d_miss = 0, d_join = 0;
     // stats
     std::mutex st_mu;
     std::vector<float> lat_all, lat_miss;
@@ -129,42 +139,79 @@ void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint
     c.hit = hit ? 1u : 0u;
     c.t_arrival_ns = r.t_arrival_ns;
     c.t_done_ns = t;
+    int32_t eid = -1;
     if (e && status == CSV_OK) {
         c.data = reinterpret_cast<const uint32_t *>(s->d_cache + e->slot);
         c.elems = (uint32_t)(class_bytes(e->lod) / 4);
-        s->entries[(size_t)(e - s->entries.data())].pins++;  // until the client releases it
+        e->pins++;  // until the client releases it
+        eid = (int32_t)(e - s->entries.data());
     }
     const float us = (float)((double)(t - r.t_arrival_ns) * 1e-3);
-    {
-        std::lock_guard<std::mutex> lk(s->st_mu);
-        s->lat_all.push_back(us);
-        if (!hit) s->lat_miss.push_back(us);
-    }
-    {
-        std::lock_guard<std::mutex> lk(s->out_mu);
-        s->outbox.push_back(c);
-        s->outbox_entry.push_back((e && status == CSV_OK) ? (int32_t)(e - s->entries.data()) : -1);
-    }
+    s->l_all.push_back(us);
+    if (!hit) s->l_miss.push_back(us);
+    s->c_local.push_back(c);
+    s->e_local.push_back(eid);
     s->free_reqs.push_back(ridx);
-    s->completed.fetch_add(1, std::memory_order_relaxed);
+}
+
+// hand this loop's statistics, then its completions, to the client side
+// (a completion the client sees is already counted)
+void publish(csv_server *s) {
+    if (!s->l_all.empty() || s->d_req || s->d_hit || s->d_miss || s->d_join) {
+        std::lock_guard<std::mutex> lk(s->st_mu);
+        s->lat_all.insert(s->lat_all.end(), s->l_all.begin(), s->l_all.end());
+        s->lat_miss.insert(s->lat_miss.end(), s->l_miss.begin(), s->l_miss.end());
+        s->n_req += s->d_req;
+        s->n_hit += s->d_hit;
+        s->n_miss += s->d_miss;
+        s->n_join += s->d_join;
+        s->l_all.clear();
+        s->l_miss.clear();
+        s->d_req = s->d_hit = s->d_miss = s->d_join = 0;
+    }
+    if (!s->c_local.empty()) {
+        const size_t k = s->c_local.size();
+        s->completed.fetch_add(k, std::memory_order_relaxed);
+        std::lock_guard<std::mutex> lk(s->out_mu);
+        s->outbox.insert(s->outbox.end(), s->c_local.begin(), s->c_local.end());
+        s->outbox_entry.insert(s->outbox_entry.end(), s->e_local.begin(), s->e_local.end());
+        s->c_local.clear();
+        s->e_local.clear();
+    }
+}
+
+void lru_unlink(csv_server *s, uint32_t id) {
+    Entry &e = s->entries[id];
+    Lru &L = s->lru[e.lod];
+    if (e.prev >= 0) s->entries[e.prev].next = e.next;
+    else L.head = e.next;
+    if (e.next >= 0) s->entries[e.next].prev = e.prev;
+    else L.tail = e.prev;
+    e.prev = e.next = -1;
+    e.in_lru = false;
 }
 
 void lru_touch(csv_server *s, uint32_t id) {
     Entry &e = s->entries[id];
-    auto &L = s->lru[e.lod];
-    if (e.in_lru) L.erase(e.lru);
-    L.push_front(id);
-    e.lru = L.begin();
+    Lru &L = s->lru[e.lod];
+    if (e.in_lru) {
+        if (L.head == (int32_t)id) return;
+        lru_unlink(s, id);
+    }
+    e.prev = -1;
+    e.next = L.head;
+    if (L.head >= 0) s->entries[L.head].prev = (int32_t)id;
+    L.head = (int32_t)id;
+    if (L.tail < 0) L.tail = (int32_t)id;
     e.in_lru = true;
 }
 
 void drop_entry(csv_server *s, uint32_t id) {
+    if (s->entries[id].in_lru) lru_unlink(s, id);
     Entry &e = s->entries[id];
-    if (e.in_lru) s->lru[e.lod].erase(e.lru);
-    e.in_lru = false;
     s->index[(size_t)e.brick * kClasses + e.lod] = -1;
     e.state = kFree;
-    e.waiters.clear();
+    e.waiters = -1;
     s->free_entries.push_back(id);
 }
 
@@ -184,12 +231,11 @@ bool alloc_slot(csv_server *s, int t, uint64_t *slot) {
         return true;
     }
     // evict the least recently used unpinned entry of the same class
-    auto &L = s->lru[t];
-    for (auto it = L.rbegin(); it != L.rend(); ++it) {
-        Entry &e = s->entries[*it];
+    for (int32_t id = s->lru[t].tail; id >= 0; id = s->entries[id].prev) {
+        Entry &e = s->entries[id];
         if (e.pins == 0 && e.state == kValid) {
             *slot = e.slot;
-            drop_entry(s, *it);
+            drop_entry(s, (uint32_t)id);
             s->n_evict++;
             return true;
         }
@@ -206,6 +252,7 @@ bool rebuild(csv_server *s) {
     for (uint32_t id = 0; id < s->entries.size(); id++)
         if (s->entries[id].state == kValid) drop_entry(s, id);
     for (auto &f : s->free_slots) f.clear();
+    for (auto &L : s->lru) L = Lru{};
     s->top = 0;
     s->n_rebuild++;
     return true;
@@ -247,9 +294,13 @@ void retire(csv_server *s, Batch &b, uint64_t t) {
         Entry &e = s->entries[id];
         e.state = kValid;
         lru_touch(s, id);
-        std::vector<uint32_t> ws;
-        ws.swap(e.waiters);
-        for (uint32_t w : ws) complete(s, w, &s->entries[id], s->error ? s->error : CSV_OK, false, t);
+        int32_t w = e.waiters;
+        e.waiters = -1;
+        while (w >= 0) {
+            const int32_t nx = s->req_next[(size_t)w];
+            complete(s, (uint32_t)w, &s->entries[id], s->error ? s->error : CSV_OK, false, t);
+            w = nx;
+        }
     }
     s->decoded_bytes += b.bytes;
     s->inflight -= b.bytes;
@@ -271,13 +322,12 @@ bool admit(csv_server *s, const Pending &p) {
         Entry &e = s->entries[id];
         if (e.state == kValid) {
             lru_touch(s, (uint32_t)id);
-            complete(s, p.idx, &e, CSV_OK, true, now_ns());
-            std::lock_guard<std::mutex> lk(s->st_mu);
-            s->n_hit++;
+            complete(s, p.idx, &s->entries[(size_t)id], CSV_OK, true, now_ns());
+            s->d_hit++;
         } else {
-            e.waiters.push_back(p.idx);
-            std::lock_guard<std::mutex> lk(s->st_mu);
-            s->n_join++;
+            s->req_next[p.idx] = e.waiters;
+            e.waiters = (int32_t)p.idx;
+            s->d_join++;
         }
         return true;
     }
@@ -304,15 +354,14 @@ bool admit(csv_server *s, const Pending &p) {
     e.pins = 0;
     e.slot = slot;
     e.in_lru = false;
-    e.waiters.assign(1, p.idx);
+    e.prev = e.next = -1;
+    e.waiters = (int32_t)p.idx;
+    s->req_next[p.idx] = -1;
     s->index[key] = (int32_t)nid;
     s->forming->entries.push_back(nid);
     s->forming->bytes += bytes;
     s->inflight += bytes;
-    {
-        std::lock_guard<std::mutex> lk(s->st_mu);
-        s->n_miss++;
-    }
+    s->d_miss++;
     if (s->forming->entries.size() >= s->opts.max_batch) {
         launch_batch(s, s->forming);
         s->forming = nullptr;
@@ -339,11 +388,11 @@ void worker_main(csv_server *s) {
             } else {
                 idx = (uint32_t)s->reqs.size();
                 s->reqs.push_back(r);
+                s->req_next.push_back(-1);
             }
             s->pending.push_back(Pending{r, idx});
-            std::lock_guard<std::mutex> lk(s->st_mu);
-            s->n_req++;
         }
+        s->d_req += take.size();
         work |= !take.empty();
         take.clear();
         // completed batches
@@ -375,6 +424,7 @@ void worker_main(csv_server *s) {
             s->forming = nullptr;
             work = true;
         }
+        publish(s);
         if (work) {
             idle = 0;
         } else if (++idle > 2000) {
@@ -562,7 +612,7 @@ int csv_server_run_trace(csv_server *s, const csv_request *reqs, uint32_t n, csv
                          uint64_t timeout_ns, uint32_t *n_done) {
     if (!s || (n && !reqs)) return CSV_EINVAL;
     std::vector<csv_request> batch;
-    std::vector<csv_completion> buf(4096);
+    std::vector<csv_completion> buf(65536);
     const uint64_t t0 = now_ns();
     uint32_t next = 0, got_total = 0;
     uint64_t last_arrival = t0;

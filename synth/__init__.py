@@ -44,6 +44,9 @@ def _load():
         d, u64, u32, vp = ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
         lib.synth_camera_trace.argtypes = [u32, u32, u32, d, d, d, u64, u64, d, d, d, d, u32, u32, u64, vp, vp, vp,
                                            ctypes.POINTER(u64)]
+        lib.synth_camera_path.argtypes = [u32, u32, u32, u64, vp]
+        lib.synth_camera_pose.argtypes = [vp, d, vp, vp]
+        lib.synth_camera_pose.restype = None
         _lib = lib
     return _lib
 
@@ -131,3 +134,23 @@ def camera_trace(nx: int, ny: int, nz: int, rate: float, duration_s: float, seed
     assert rc == 0, rc
     k = n.value
     return ids[:k].copy(), lods[:k].copy(), t[:k].copy()
+
+
+def camera_path(nx: int, ny: int, nz: int, seed: int = 7) -> np.ndarray:
+    """The 8 control points (x, y, z) of camera_trace's path (path_seed)."""
+    c = np.empty((8, 3), np.float64)
+    assert _load().synth_camera_path(nx, ny, nz, seed, c.ctypes.data_as(ctypes.c_void_p)) == 0
+    return c
+
+
+def camera_pose(ctrl: np.ndarray, u):
+    """Camera position and path tangent at parameters u in [0, 1)."""
+    ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+    u = np.atleast_1d(np.asarray(u, dtype=np.float64))
+    pos, tan = np.empty((len(u), 3)), np.empty((len(u), 3))
+    lib, cp = _load(), ctrl.ctypes.data_as(ctypes.c_void_p)
+    p3, t3 = np.empty(3), np.empty(3)
+    for i, x in enumerate(u):
+        lib.synth_camera_pose(cp, float(x), p3.ctypes.data_as(ctypes.c_void_p), t3.ctypes.data_as(ctypes.c_void_p))
+        pos[i], tan[i] = p3, t3
+    return pos, tan

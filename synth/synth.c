@@ -379,15 +379,33 @@ static void catmull_rom3(const double (*c)[3], int n, double u, double pos[3], d
     }
 }
 
+static void camera_ctrl(uint32_t nx, uint32_t ny, uint32_t nz, uint64_t path_seed, double ctrl[8][3]) {
+    uint64_t ps = path_seed;
+    const double ext[3] = {nx, ny, nz};
+    for (int i = 0; i < 8; i++)
+        for (int k = 0; k < 3; k++) ctrl[i][k] = ext[k] * (0.15 + 0.7 * rnd(&ps));
+}
+
+/* the 8 control points (x, y, z) of the camera path, and the camera's
+ * position and tangent at path parameter u in [0, 1) */
+int synth_camera_path(uint32_t nx, uint32_t ny, uint32_t nz, uint64_t path_seed, double *ctrl24) {
+    double c[8][3];
+    camera_ctrl(nx, ny, nz, path_seed, c);
+    memcpy(ctrl24, c, sizeof(c));
+    return 0;
+}
+
+void synth_camera_pose(const double *ctrl24, double u, double *pos3, double *tan3) {
+    catmull_rom3((const double(*)[3])ctrl24, 8, u, pos3, tan3);
+}
+
 int synth_camera_trace(uint32_t nx, uint32_t ny, uint32_t nz, double rate, double duration, double t0, uint64_t seed,
                        uint64_t path_seed, double period, double cone_deg, double d_max, double d0, uint32_t brick,
                        uint32_t max_lod, uint64_t cap, uint32_t *ids, uint8_t *lods, uint64_t *t_ns, uint64_t *n_out) {
     if (!ids || !lods || !t_ns || !n_out || rate <= 0 || brick == 0 || nx < brick || ny < brick || nz < brick) return 1;
     double ctrl[8][3];
-    uint64_t ps = path_seed;
+    camera_ctrl(nx, ny, nz, path_seed, ctrl);
     const double ext[3] = {nx, ny, nz};
-    for (int i = 0; i < 8; i++)
-        for (int k = 0; k < 3; k++) ctrl[i][k] = ext[k] * (0.15 + 0.7 * rnd(&ps));
     uint64_t s = seed;
     const double cos_half = cos(cone_deg * 0.5 * 3.14159265358979323846 / 180.0);
     const uint32_t nbx = nx / brick, nby = ny / brick;
