@@ -12,6 +12,7 @@ decode kernel, the one-launch-per-brick baseline and the CPU oracle.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# HBM bytes of one decode call on this workload (front + leaf kernel), from
+# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
+# counters read for a plain 256 MiB device copy; see
+# profiles/decode_cells512_hbm_traffic.md.  Valid only for the decoder source
+# and launch shape the counters were taken with.
+TRAFFIC = {"decoder_sha256_16": "0bad906bca505b3f", "shape": (16, 3, 1, 0), "bytes": 657029837}
 
 
 def log(msg):
@@ -78,6 +86,8 @@ def serving_leg(csv, synth, seconds):
                  "hit_rate": round(st["hits"] / max(st["requests"], 1), 4),
                  "joined": int(st["joined"]), "evictions": int(st["evictions"]), "rebuilds": int(st["rebuilds"]),
                  "batches": int(st["batches"]), "decoded_gb": round(st["decoded_bytes"] / 1e9, 3),
+                 "worker_busy_frac": round(st["worker_busy_ns"] * 1e-9 / seconds, 3),
+                 "worker_launch_frac": round(st["worker_launch_ns"] * 1e-9 / seconds, 3),
                  "lod_hist": [round(float(x), 4) for x in hist]}
             log("serving %s" % r)
             runs.append(r)
@@ -134,6 +144,11 @@ def main():
     in_bytes = record_bytes(blob, ids_np, lod)
 
     stream = torch.cuda.current_stream()
+    # the launch shape is picked on this request set by the autotuner
+    shape, tune_ms = pool.autotune(ids, out, lod=lod, reps=3)
+    torch.cuda.synchronize()
+    assert pool.last_error()[0] == 0
+    log("autotuned shape %s: %.4f ms" % (shape, tune_ms))
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -168,21 +183,13 @@ def main():
     code, who = pool.last_error()
     assert code == 0, ("decode error", code, who)
 
-    # launch-shape sweep (logged): waves per workgroup x work queue
-    for shape in [(16, 3, 1), (8, 3, 1), (16, 2, 1), (16, 4, 1), (16, 3, 0), (16, 3, 1, 1)]:
-        pool.decode(ids, out, lod=lod, shape=shape)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            pool.decode(ids, out, lod=lod, shape=shape)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        sms = ev0.elapsed_time(ev1) / args.steps
-        log("shape %s: %.4f ms/step, %.1f GB/s" % (shape, sms, out_bytes / (sms * 1e-3) / 1e9))
-    assert pool.last_error()[0] == 0
 
-    # per-launch kernel time: one launch per step, so the event time per step
+    # per-call time: one decode call (front + leaf kernel) per step, so the event time per step
     achieved = (in_bytes + out_bytes) / (ms * 1e-3) / 1e9
+    src = os.path.join(ROOT, "paper_2308_16619_amd", "csrc", "csv_decode.hip")
+    src_hash = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = TRAFFIC["bytes"] if (src_hash == TRAFFIC["decoder_sha256_16"] and
+                                   tuple(shape) == TRAFFIC["shape"]) else None
 
     # baseline: one launch per brick
     nb = min(args.plain_bricks, B)
@@ -239,8 +246,10 @@ def main():
         "voxels_per_s": round(elems / (ms * 1e-3), 1),
         "wall_s": round(t_wall, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "algorithmic_bytes_per_launch": in_bytes + out_bytes, "kernel": "decode_kernel"},
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "traffic_unit": "bytes per decode call", "algorithmic_bytes_per_launch": in_bytes + out_bytes,
+                     "kernel": "csv_decode_bricks = front_kernel + leaf_kernel", "shape": list(shape),
+                     "decoder_sha256_16": src_hash},
         "plain_per_brick_launch": {"value": round(plain_gbs, 3), "unit": "GB/s", "bricks": nb},
         "cpu_baseline": cpu,
         "serving": serving,

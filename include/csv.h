@@ -161,14 +161,16 @@ int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, con
 
 /* Launch shape of a batched decode.  Every shape gives the same bytes. */
 typedef struct {
-    int waves_per_group;    /* entropy decoder: wavefronts per workgroup, 4, 8 or 16 (each decodes its
-                               own bricks; the grid fills a CU's 32 wavefront slots) */
-    uint32_t groups_per_cu; /* replay: 4-wavefront workgroups per compute unit, 1..8; each holds
-                               160 KiB / groups_per_cu of LDS (bricks whose arrays do not fit take
-                               a slower path through a global-memory arena) */
-    int use_queue;          /* 1: waves take requests from a device work counter; 0: static round robin */
+    int waves_per_group;    /* front kernel: wavefronts per workgroup, 4, 8 or 16 (each decodes its
+                               own bricks; 8 KiB of LDS per wavefront) */
+    uint32_t groups_per_cu; /* leaf kernel: 4-wavefront workgroups per compute unit, 1..8; each holds
+                               160 KiB / groups_per_cu of LDS (rounded down to whole KiB; bricks
+                               whose arrays do not fit take a slower path through a global-memory
+                               arena) */
+    int use_queue;          /* 1: waves / workgroups take requests from device work counters;
+                               0: static round robin */
     int lpt_order;          /* 1: requests are first ordered longest-first (binned by log2 of their
-                               symbols + output voxels / 8; three small kernels before the decode) */
+                               symbols + output voxels / 8; one small kernel before the decode) */
     float ms;               /* csv_autotune: the measured time per launch of this shape */
 } csv_shape;
 
@@ -182,7 +184,9 @@ int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape);
 int csv_pool_get_shape(const csv_pool *pool, csv_shape *shape);
 
 /* Autotuner: decodes the given request set (same arguments as
- * csv_decode_bricks; `out` is overwritten) with every candidate shape, one
+ * csv_decode_bricks; `out` is overwritten) with every candidate shape
+ * (front waves {8, 16} x leaf groups {2, 3, 4, 5} x queue {0, 1} x order
+ * {0, 1}), one
  * warm-up and `reps` timed launches each (HIP events on `stream`), makes
  * the fastest the pool's shape and returns it in *best (may be NULL).
  * Synchronous.  Not allowed while `stream` is being captured. */
@@ -219,7 +223,8 @@ typedef struct csv_server csv_server;
 
 typedef struct {
     uint64_t cache_bytes;    /* decoded-brick cache in HBM (LRU per LOD class, 128 KiB pages) */
-    uint64_t inflight_bytes; /* admission budget: decoded bytes of admitted, unfinished requests */
+    uint64_t inflight_bytes; /* admission budget: decoded bytes of admitted, unfinished requests
+                                (at most a quarter of cache_bytes is used) */
     uint32_t max_batch;      /* bricks per launch */
     uint32_t streams;        /* batches that may run on the GPU at once (1..16) */
 } csv_server_opts;
@@ -251,6 +256,11 @@ typedef struct {
     uint64_t decoded_bytes, cache_bytes_used;
     double p50_us, p99_us, p50_miss_us, p99_miss_us, max_us; /* arrival -> completion */
     int32_t error;
+    int32_t pad;
+    uint64_t worker_busy_ns;   /* worker thread time spent on requests and batches */
+    uint64_t worker_launch_ns; /* ... of which launching batches */
+    uint64_t stall_batch, stall_inflight, stall_slot; /* admission rounds stopped by: no free batch,
+                                                         the in-flight budget, no cache slot */
 } csv_stats;
 
 /* Clock of arrival and completion times (steady, nanoseconds). */

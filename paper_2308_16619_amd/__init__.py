@@ -62,7 +62,9 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("requests", "hits", "misses", "joined", "completed", "batches",
                                               "evictions", "rebuilds", "decoded_bytes", "cache_bytes_used")] + [
         (n, ctypes.c_double) for n in ("p50_us", "p99_us", "p50_miss_us", "p99_miss_us", "max_us")] + [
-        ("error", ctypes.c_int32)]
+        ("error", ctypes.c_int32), ("pad", ctypes.c_int32), ("worker_busy_ns", ctypes.c_uint64),
+        ("worker_launch_ns", ctypes.c_uint64), ("stall_batch", ctypes.c_uint64), ("stall_inflight", ctypes.c_uint64),
+        ("stall_slot", ctypes.c_uint64)]
 
 
 class PoolInfo(ctypes.Structure):

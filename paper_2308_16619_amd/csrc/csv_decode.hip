@@ -68,11 +68,12 @@ __device__ constexpr uint32_t kBmOff[5] = {0, 0, 512, 576, 584};
 // lists of expanded nodes (u16 entries) for levels 2..4; level 1 has its own
 __device__ constexpr uint32_t kLstOff[5] = {0, 0, 72, 8, 0};
 
-// LDS of one front-kernel wave: the word ring (2 KB) and 512 symbol bytes
-// during the entropy decode, then the upper levels (u8), their expansion
-// bits and lists, the palette
+// LDS of one front-kernel wave: the word ring (2 KB plus a 128-byte mirror)
+// and 512 symbol bytes during the entropy decode, then the upper levels
+// (u8), their expansion bits and lists, the palette
 constexpr uint32_t kWaveLds = 8192;
 constexpr uint32_t kWLv = 0, kWBm = 4688, kWLst = 5280, kWPal = 6448;
+constexpr uint32_t kWDeltaDw = (kWaveLds - kWPal) / 4;  // the palette area holds a level's deltas during the replay
 
 // Per-request slot in global memory: the packed nibbles (slot_dw dwords),
 // then the levels (u16 levels 1..4 for big palettes; else u8 L_1 only, in
@@ -428,11 +429,19 @@ __device__ __forceinline__ uint32_t pal_at(const uint32_t *pal, uint32_t i, uint
     return pal[i];
 }
 
-// four labels to dst (16-byte aligned when al16; outputs of mixed levels of
-// detail need not be)
-__device__ __forceinline__ void store4(uint32_t *dst, const uint4 &o, bool al16) {
-    if (al16) {
-        *reinterpret_cast<uint4 *>(dst) = o;
+// four labels to dst: one non-temporal 16-byte store when dst is 16-byte
+// aligned (kAl16, a compile-time choice so that the compiler keeps the wide
+// store), else four dword stores (outputs of mixed levels of detail need
+// not be aligned)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt(uint32_t *dst, const uint4 &o) {
+    u32x4 v = {o.x, o.y, o.z, o.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
+}
+template <bool kAl16>
+__device__ __forceinline__ void store4(uint32_t *dst, const uint4 &o) {
+    if constexpr (kAl16) {
+        store_nt(dst, o);
     } else {
         dst[0] = o.x;
         dst[1] = o.y;
@@ -446,7 +455,7 @@ template <uint32_t kThreads>
 __device__ __forceinline__ void fill_labels(uint32_t *dst, uint32_t count, uint32_t v, uint32_t tid) {
     if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0 && (count & 3) == 0) {
         const uint4 q = make_uint4(v, v, v, v);
-        for (uint32_t e = 4 * tid; e < count; e += 4 * kThreads) *reinterpret_cast<uint4 *>(dst + e) = q;
+        for (uint32_t e = 4 * tid; e < count; e += 4 * kThreads) store_nt(dst + e, q);
     } else {
         for (uint32_t e = tid; e < count; e += kThreads) dst[e] = v;
     }
@@ -492,12 +501,16 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
     const uint32_t *wg = h.rec + hdr + h.P + W;
     const uint32_t ndw = (h.nw + 1) / 2;  // word dwords in the record (the last one padded)
     uint32_t x = L < W ? h.rec[hdr + h.P + L] : 0u;
-    // the ring holds words [ring_lo, ring_lo + 1024); pf holds the next 512
+    // the ring holds words [ring_lo, ring_lo + 1024) at positions word & 1023,
+    // and positions 0..63 again after position 1023 (a read of 64 words from
+    // any position needs no wrap-around); pf holds the next 512 words
     uint32_t ring_lo = 0;
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const uint32_t d = L + 64 * q;
-        ring32[d] = d < ndw ? wg[d] : 0u;
+        const uint32_t v = d < ndw ? wg[d] : 0u;
+        ring32[d] = v;
+        if (q == 0 && L < 32) ring32[kRingWords / 2 + L] = v;
     }
     uint32_t pf[4];
 #pragma unroll
@@ -514,6 +527,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
         wsync();
 #pragma unroll
         for (int q = 0; q < 4; q++) ring32[hh * 256 + L + 64 * q] = pf[q];
+        if (hh == 0 && L < 32) ring32[kRingWords / 2 + L] = pf[0];
         ring_lo += 512;
         const uint32_t d0 = (ring_lo + 1024) >> 1;
 #pragma unroll
@@ -547,7 +561,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
         // blocks of 8 steps: each lane writes its symbol as a byte to LDS
         // (no address arithmetic: immediate offsets), then lane L packs the
         // block's symbols 8L .. 8L + 7 into one nibble dword
-        uint8_t *sb = reinterpret_cast<uint8_t *>(ring32) + 2 * kRingWords;
+        uint8_t *sb = reinterpret_cast<uint8_t *>(ring32) + 2 * kRingWords + 128;
         auto block8 = [&](auto leaf_select) {
 #pragma unroll
             for (int j = 0; j < 8; j++) {
@@ -557,7 +571,9 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
                 x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
                 const bool need = x < csv::kRansLower;
                 const uint64_t bal = __ballot(need);
-                const uint32_t wd = ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, cursor & (kRingWords - 1)));
+                const uint32_t wd = ring[pos];
                 x = need ? ((x << 16) | wd) : x;
                 cursor += (uint32_t)__popcll(bal);
                 sb[64 * j + L] = (uint8_t)(e & 15u);
@@ -623,7 +639,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
 // False on a malformed stream.
 template <class IdxT, bool kG>
 __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, IdxT *lv, uint8_t *bm, uint16_t *lst,
-                                             uint32_t &E_out, uint32_t &ipl_out) {
+                                             uint32_t *dstage, uint32_t &E_out, uint32_t &ipl_out) {
     using V = Vec8<IdxT>;
     using VT = typename V::T;
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
@@ -653,6 +669,16 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
         if ((uint64_t)seg + 8ull * E > seg_end) return false;
         const uint32_t D = seg_end - seg - 8 * E, ops0 = seg + D;  // deltas precede the operations
         const uint32_t pmask0 = axis_mask(0, Bp), pmask1 = axis_mask(1, Bp), pmask2 = axis_mask(2, Bp);
+        // the level's delta nibbles in LDS when they fit (read by lanes with P_delta children)
+        const uint32_t d0 = seg >> 3, dn = D ? ((seg + D + 7) >> 3) - d0 + 1 : 0u;
+        const uint32_t *dnib = nib;
+        uint32_t dbase = seg;
+        if (dn <= kWDeltaDw) {
+            for (uint32_t e = L; e < dn; e += 64) dstage[e] = nib[d0 + e];
+            wsync();
+            dnib = dstage;
+            dbase = seg - 8 * d0;
+        }
         uint32_t bpa = 0, bpd = 0, bex = 0;
         bool bad = false;
         for (uint32_t c = 0; c < (E + 63) / 64; c++) {
@@ -676,8 +702,8 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
                     lowok |= (q & am) ? (1u << a) : 0u;
                 }
                 const VT vals = replay8<IdxT>(wd, pv, nb, nbok, lowok, ipl + bpa + (exc & 1023u),
-                                                      compact_nibble_bits(pam), compact_nibble_bits(pdm), nib,
-                                                      seg + bpd + ((exc >> 10) & 1023u), P, false, bad);
+                                                      compact_nibble_bits(pam), compact_nibble_bits(pdm), dnib,
+                                                      dbase + bpd + ((exc >> 10) & 1023u), P, false, bad);
                 *reinterpret_cast<VT *>(cur + 8 * q) = vals;
                 uint32_t ex8 = compact_nibble_bits(exm);
                 cbm[q] = (uint8_t)ex8;
@@ -743,18 +769,21 @@ __device__ __forceinline__ void upper_output(const IdxT *lv, uint32_t t, const u
         if (L < 8) dst[L] = pal_at<kG>(pal, res[L], P);  // Morton order equals dense order on 2^3
         return;
     }
-    const bool al16 = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
     const uint32_t lg = (uint32_t)(kLog2 - t);
-    for (uint32_t e = 4 * L; e < G * G * G; e += 256) {
-        const uint32_t x0 = e & (G - 1), yy = (e >> lg) & (G - 1), zz = e >> (2 * lg);
-        const uint32_t m0 = spread4(x0) | (spread4(yy) << 1) | (spread4(zz) << 2);
-        uint4 o;
-        o.x = pal_at<kG>(pal, res[m0], P);
-        o.y = pal_at<kG>(pal, res[m0 | 1u], P);
-        o.z = pal_at<kG>(pal, res[m0 | 8u], P);
-        o.w = pal_at<kG>(pal, res[m0 | 9u], P);
-        store4(dst + e, o, al16);
-    }
+    auto rows = [&](auto al16) {
+        for (uint32_t e = 4 * L; e < G * G * G; e += 256) {
+            const uint32_t x0 = e & (G - 1), yy = (e >> lg) & (G - 1), zz = e >> (2 * lg);
+            const uint32_t m0 = spread4(x0) | (spread4(yy) << 1) | (spread4(zz) << 2);
+            uint4 o;
+            o.x = pal_at<kG>(pal, res[m0], P);
+            o.y = pal_at<kG>(pal, res[m0 | 1u], P);
+            o.z = pal_at<kG>(pal, res[m0 | 8u], P);
+            o.w = pal_at<kG>(pal, res[m0 | 9u], P);
+            store4<decltype(al16)::value>(dst + e, o);
+        }
+    };
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) rows(std::true_type{});
+    else rows(std::false_type{});
 }
 
 // one brick of the front kernel after its entropy decode; false on a
@@ -771,7 +800,7 @@ __device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, con
     uint8_t *bm = wl + kWBm;
     uint16_t *lst = reinterpret_cast<uint16_t *>(wl + kWLst);
     uint32_t E1 = 0, ipl = 0;
-    if (!upper_replay<IdxT, kG>(h, nib, lv, bm, lst, E1, ipl)) return false;
+    if (!upper_replay<IdxT, kG>(h, nib, lv, bm, lst, reinterpret_cast<uint32_t *>(wl + kWPal), E1, ipl)) return false;
     if (h.t >= 1) {
         const uint32_t *pal = h.rec + hdr;
         if (!kG) {  // stage the palette next to the levels
@@ -1075,41 +1104,44 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     // covers voxels 4 (L & 7) .. + 3 of rows (L >> 3) + 8c; references are
     // followed along the dense level (at most three links)
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
-    const bool al16 = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
-    for (uint32_t zz = w; zz < 32; zz += kWavesB) {
+    auto slices = [&](auto al16) {
+        for (uint32_t zz = w; zz < 32; zz += kWavesB) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-            const uint32_t v0 = 4 * (L & 7u) + 32 * ((L >> 3) + 8 * (uint32_t)c) + 1024 * zz;
-            uint32_t idx[4];
-            if constexpr (sizeof(IdxT) == 1) {
-                const uint32_t q = *reinterpret_cast<const uint32_t *>(D + v0);
+            for (int c = 0; c < 4; c++) {
+                const uint32_t v0 = 4 * (L & 7u) + 32 * ((L >> 3) + 8 * (uint32_t)c) + 1024 * zz;
+                uint32_t idx[4];
+                if constexpr (sizeof(IdxT) == 1) {
+                    const uint32_t q = *reinterpret_cast<const uint32_t *>(D + v0);
 #pragma unroll
-                for (int b = 0; b < 4; b++) idx[b] = (q >> (8 * b)) & 0xFFu;
-                // bytes >= 252: a reference (252 never survives the checks)
-                const uint32_t t = ~q & 0xFCFCFCFCu;
-                if (((t - 0x01010101u) & ~t & 0x80808080u) != 0) {
+                    for (int b = 0; b < 4; b++) idx[b] = (q >> (8 * b)) & 0xFFu;
+                    // bytes >= 252: a reference (252 never survives the checks)
+                    const uint32_t t = ~q & 0xFCFCFCFCu;
+                    if (((t - 0x01010101u) & ~t & 0x80808080u) != 0) {
+#pragma unroll
+                        for (int b = 0; b < 4; b++)
+                            if (idx[b] >= kMark) idx[b] = chase<IdxT>(D, v0 + (uint32_t)b, idx[b]);
+                    }
+                } else {
+                    const uint2 q = *reinterpret_cast<const uint2 *>(D + v0);
+                    idx[0] = q.x & 0xFFFFu;
+                    idx[1] = q.x >> 16;
+                    idx[2] = q.y & 0xFFFFu;
+                    idx[3] = q.y >> 16;
 #pragma unroll
                     for (int b = 0; b < 4; b++)
                         if (idx[b] >= kMark) idx[b] = chase<IdxT>(D, v0 + (uint32_t)b, idx[b]);
                 }
-            } else {
-                const uint2 q = *reinterpret_cast<const uint2 *>(D + v0);
-                idx[0] = q.x & 0xFFFFu;
-                idx[1] = q.x >> 16;
-                idx[2] = q.y & 0xFFFFu;
-                idx[3] = q.y >> 16;
-#pragma unroll
-                for (int b = 0; b < 4; b++)
-                    if (idx[b] >= kMark) idx[b] = chase<IdxT>(D, v0 + (uint32_t)b, idx[b]);
+                uint4 o;
+                o.x = pal_at<kG>(pal, idx[0], P);
+                o.y = pal_at<kG>(pal, idx[1], P);
+                o.z = pal_at<kG>(pal, idx[2], P);
+                o.w = pal_at<kG>(pal, idx[3], P);
+                store4<decltype(al16)::value>(dst + v0, o);
             }
-            uint4 o;
-            o.x = pal_at<kG>(pal, idx[0], P);
-            o.y = pal_at<kG>(pal, idx[1], P);
-            o.z = pal_at<kG>(pal, idx[2], P);
-            o.w = pal_at<kG>(pal, idx[3], P);
-            store4(dst + v0, o, al16);
         }
-    }
+    };
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) slices(std::true_type{});
+    else slices(std::false_type{});
     phase_mark(h.rq, 5);
     return true;
 }
@@ -1178,7 +1210,7 @@ __global__ __launch_bounds__(kThreadsB) CSV_LEAF_ATTR void leaf_kernel(DecodeArg
 
 // Longest-first request order: requests are binned by the log2 of their
 // work (symbols to decode plus output voxels / 8), largest bin first, and
-// laid out bin by bin.  ws: 2 x 32 counters.
+// laid out bin by bin.
 constexpr int kBins = 32;
 __device__ __forceinline__ uint32_t work_bin(const DecodeArgs &a, uint32_t r) {
     const uint32_t id = a.ids[r];
@@ -1190,22 +1222,24 @@ __device__ __forceinline__ uint32_t work_bin(const DecodeArgs &a, uint32_t r) {
     const uint32_t work = n + (g * g * g) / 8 + 1;
     return (uint32_t)__builtin_clz(work);  // 32 - bit length: small for big work
 }
-__global__ void order_count(DecodeArgs a, uint32_t *ws) {
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < a.n; r += gridDim.x * blockDim.x)
-        atomicAdd(&ws[work_bin(a, r)], 1u);
-}
-__global__ void order_scan(uint32_t *ws) {
-    if (threadIdx.x == 0) {
+// one workgroup: bin counts and offsets in LDS, then each request takes
+// the next slot of its bin (the order within a bin is arbitrary)
+__global__ __launch_bounds__(1024) void order_lpt(DecodeArgs a, uint32_t *order) {
+    __shared__ uint32_t cnt[kBins], off[kBins];
+    const uint32_t tid = threadIdx.x;
+    if (tid < kBins) cnt[tid] = 0;
+    __syncthreads();
+    for (uint32_t r = tid; r < a.n; r += blockDim.x) atomicAdd(&cnt[work_bin(a, r)], 1u);
+    __syncthreads();
+    if (tid == 0) {
         uint32_t o = 0;
         for (int b = 0; b < kBins; b++) {
-            ws[kBins + b] = o;
-            o += ws[b];
+            off[b] = o;
+            o += cnt[b];
         }
     }
-}
-__global__ void order_scatter(DecodeArgs a, uint32_t *ws, uint32_t *order) {
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < a.n; r += gridDim.x * blockDim.x)
-        order[atomicAdd(&ws[kBins + work_bin(a, r)], 1u)] = r;
+    __syncthreads();
+    for (uint32_t r = tid; r < a.n; r += blockDim.x) order[atomicAdd(&off[work_bin(a, r)], 1u)] = r;
 }
 __global__ void zero_words(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -1329,8 +1363,10 @@ uint32_t lut_lds_words(const csv_pool *p) {
 uint32_t slot_dw(const csv_pool *p) { return ((p->max_c0 + 7) / 8 + 8 + 3) & ~3u; }
 constexpr uint32_t kSmallB = (sizeof(SmallB) + 15u) & ~15u;
 constexpr uint32_t kMaxGroupsB = 8;
-// replay arena when `groups` replay workgroups share a CU's LDS
-uint32_t arena_b(uint32_t groups) { return ((kLdsBytes / groups) - kSmallB) & ~15u; }
+// leaf arena when `groups` leaf workgroups share a CU's LDS (whole 4 KiB
+// per workgroup: LDS is allocated in granules, and a workgroup that rounds
+// up past its share would leave room for one fewer)
+uint32_t arena_b(uint32_t groups) { return ((kLdsBytes / groups) & ~4095u) - kSmallB; }
 uint32_t min_arena_b() { return arena_b(kMaxGroupsB); }
 
 // the buffers of stream s, sized for n requests (pool->mu held)
@@ -1448,6 +1484,8 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     lb.scratch_bytes = kArenaBytes;
     const size_t lds_b = kSmallB + (size_t)lb.arena_bytes;
     const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
+    // a small batch takes smaller front workgroups, so that its bricks spread over the CUs
+    while (waves_a > 4 && (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a < cu) waves_a /= 2;
     // front kernel: as many workgroups as a CU's LDS and 32 wave slots allow
     const uint32_t lds_a = align16(4 * la.lut_lds_words) + (uint32_t)waves_a * kWaveLds;
     const uint32_t fit_a = std::max(1u, std::min(kLdsBytes / lds_a, 32u / (uint32_t)waves_a));
@@ -1474,11 +1512,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     } else {
         hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 3u);
         if (lpt) {
-            const uint32_t gq = std::min<uint32_t>((n + 255) / 256, 1024u);
-            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, B->small, 2u * kBins);
-            hipLaunchKernelGGL(order_count, dim3(gq), dim3(256), 0, s, a, B->small);
-            hipLaunchKernelGGL(order_scan, dim3(1), dim3(64), 0, s, B->small);
-            hipLaunchKernelGGL(order_scatter, dim3(gq), dim3(256), 0, s, a, B->small, B->order);
+            hipLaunchKernelGGL(order_lpt, dim3(1), dim3(1024), 0, s, a, B->order);
             la.order = B->order;
         }
         go_a(a, la, grid_a);
@@ -1677,23 +1711,24 @@ int csv_autotune(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint3
     if (capturing(s)) return CSV_EINVAL;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CSV_EHIP;
-    const int waves[3] = {4, 8, 16};
-    const uint32_t groups[5] = {3, 4, 5, 6, 8};
+    const int waves[2] = {8, 16};
+    const uint32_t groups[4] = {2, 3, 4, 5};
     csv_shape win{};
     win.ms = 1e30f;
     int rc = CSV_OK;
-    for (int wi = 0; wi < 3 && !rc; wi++)
-        for (int gi = 0; gi < 5 && !rc; gi++)
-            for (int o = 0; o < 2 && !rc; o++) {
-                csv_shape sh{waves[wi], groups[gi], 1, o, 0.f};
+    for (int wi = 0; wi < 2 && !rc; wi++)
+        for (int gi = 0; gi < 4 && !rc; gi++)
+            for (int q = 0; q < 2 && !rc; q++)
+                for (int o = 0; o < 2 && !rc; o++) {
+                csv_shape sh{waves[wi], groups[gi], q, o, 0.f};
                 // one warm-up launch, then reps timed launches
                 rc = launch(pool, ids, lods, lod_scalar, out_off, n, out, stream, false, sh.waves_per_group,
-                            (uint32_t)sh.groups_per_cu, true, o != 0);
+                            (uint32_t)sh.groups_per_cu, q != 0, o != 0);
                 if (rc) break;
                 (void)hipEventRecord(e0, s);
                 for (uint32_t r = 0; r < reps && !rc; r++)
                     rc = launch(pool, ids, lods, lod_scalar, out_off, n, out, stream, false, sh.waves_per_group,
-                                (uint32_t)sh.groups_per_cu, true, o != 0);
+                                (uint32_t)sh.groups_per_cu, q != 0, o != 0);
                 (void)hipEventRecord(e1, s);
                 if (hipEventSynchronize(e1) != hipSuccess) rc = CSV_EHIP;
                 float ms = 0.f;

@@ -49,6 +49,7 @@ struct Entry {
     uint8_t lod = 0;
     State state = kFree;
     bool in_lru = false;
+    uint8_t ref = 0;                 // hit since it last passed the eviction scan (second chance)
     uint32_t pins = 0;               // completions not yet released by the next poll
     uint64_t slot = 0;               // byte offset in the cache
     int32_t prev = -1, next = -1;    // LRU neighbours within the LOD class (prev: more recent)
@@ -68,12 +69,10 @@ struct Pending {
 struct Batch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    uint32_t *h_ids = nullptr;
-    uint8_t *h_lods = nullptr;
-    uint64_t *h_off = nullptr;
-    uint32_t *d_ids = nullptr;
-    uint8_t *d_lods = nullptr;
-    uint64_t *d_off = nullptr;
+    // a batch's requests, u64 offsets[n], u32 ids[n], u8 lods[n], in pinned
+    // host memory that the decode kernels read directly (d_buf: its device address)
+    uint8_t *h_buf = nullptr;
+    uint8_t *d_buf = nullptr;
     std::vector<uint32_t> entries;  // entry ids decoded by this batch
     uint64_t bytes = 0;
     bool busy = false;
@@ -104,6 +103,7 @@ struct csv_server {
     std::mutex out_mu;
     std::vector<csv_completion> outbox;
     std::vector<int32_t> outbox_entry;  // cache entry each completion points into (-1: none)
+    size_t outbox_head = 0;             // completions before it have been handed out
     std::vector<uint32_t> delivered;    // entries of the completions handed out by the last poll
     std::vector<uint32_t> to_unpin;     // entries whose completions the client has released
     // batches
@@ -114,12 +114,14 @@ struct csv_server {
     std::vector<csv_completion> c_local;
     std::vector<int32_t> e_local;
     std::vector<float> l_all, l_miss;
-    uint64_t d_req = 0, d_hit = 0, d_miss = 0, d_join = 0;
+    uint64_t d_req = 0, d_hit = 0, d_miss = 0, d_join = 0, d_busy = 0, d_launch = 0;
     // stats
     std::mutex st_mu;
-    std::vector<float> lat_all, lat_miss;
+    std::deque<float> lat_all, lat_miss;  // a deque grows without copying what it holds
     uint64_t n_req = 0, n_hit = 0, n_miss = 0, n_join = 0, n_batches = 0, n_evict = 0, n_rebuild = 0,
-             decoded_bytes = 0, n_launch_err = 0;
+             decoded_bytes = 0, n_launch_err = 0, busy_ns = 0, launch_ns = 0;
+    uint64_t stall[3] = {0, 0, 0};  // admission stopped: no free batch, in-flight budget, no slot
+
     std::atomic<uint64_t> submitted{0}, completed{0};
     std::atomic<bool> stop{false};
     std::thread worker;
@@ -130,8 +132,7 @@ namespace {
 
 void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint64_t t) {
     const csv_request &r = s->reqs[ridx];
-    csv_completion c;
-    std::memset(&c, 0, sizeof(c));
+    csv_completion c{};
     c.tag = r.tag;
     c.brick_id = r.brick_id;
     c.lod = r.lod;
@@ -157,8 +158,11 @@ void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint
 // hand this loop's statistics, then its completions, to the client side
 // (a completion the client sees is already counted)
 void publish(csv_server *s) {
-    if (!s->l_all.empty() || s->d_req || s->d_hit || s->d_miss || s->d_join) {
+    if (!s->l_all.empty() || s->d_req || s->d_hit || s->d_miss || s->d_join || s->d_busy) {
         std::lock_guard<std::mutex> lk(s->st_mu);
+        s->busy_ns += s->d_busy;
+        s->launch_ns += s->d_launch;
+        s->d_busy = s->d_launch = 0;
         s->lat_all.insert(s->lat_all.end(), s->l_all.begin(), s->l_all.end());
         s->lat_miss.insert(s->lat_miss.end(), s->l_miss.begin(), s->l_miss.end());
         s->n_req += s->d_req;
@@ -215,6 +219,25 @@ void drop_entry(csv_server *s, uint32_t id) {
     s->free_entries.push_back(id);
 }
 
+// the least recently used unpinned valid entry of class t, or -1.  An entry
+// hit since the scan last passed it gets a second chance (its flag is
+// cleared and the scan moves on; a hit itself only sets the flag, which
+// keeps hits cheap).  The scan is bounded; past the bound the first
+// unpinned entry it saw is taken.
+int32_t evictable(csv_server *s, int t) {
+    int32_t id = s->lru[t].tail, first = -1;
+    for (int budget = 32; id >= 0 && budget > 0; budget--) {
+        Entry &e = s->entries[id];
+        if (e.pins == 0 && e.state == kValid) {
+            if (!e.ref) return id;
+            e.ref = 0;
+            if (first < 0) first = id;
+        }
+        id = e.prev;
+    }
+    return first;
+}
+
 // a cache slot for LOD class t, or false
 bool alloc_slot(csv_server *s, int t, uint64_t *slot) {
     auto &fs = s->free_slots[t];
@@ -231,14 +254,22 @@ bool alloc_slot(csv_server *s, int t, uint64_t *slot) {
         return true;
     }
     // evict the least recently used unpinned entry of the same class
-    for (int32_t id = s->lru[t].tail; id >= 0; id = s->entries[id].prev) {
-        Entry &e = s->entries[id];
-        if (e.pins == 0 && e.state == kValid) {
-            *slot = e.slot;
-            drop_entry(s, (uint32_t)id);
-            s->n_evict++;
-            return true;
-        }
+    int32_t id = evictable(s, t);
+    if (id >= 0) {
+        *slot = s->entries[id].slot;
+        drop_entry(s, (uint32_t)id);
+        s->n_evict++;
+        return true;
+    }
+    // a smaller class takes over the page of the least recently used unpinned
+    // full-LOD entry (one page each), so that classes follow the request mix
+    if (t > 0 && (id = evictable(s, 0)) >= 0) {
+        const uint64_t page = s->entries[id].slot, sz = class_bytes(t);
+        drop_entry(s, (uint32_t)id);
+        s->n_evict++;
+        for (uint64_t o = kPage; o >= 2 * sz; o -= sz) fs.push_back(page + o - sz);
+        *slot = page;
+        return true;
     }
     return false;
 }
@@ -265,20 +296,21 @@ Batch *free_batch(csv_server *s) {
 }
 
 void launch_batch(csv_server *s, Batch *b) {
+    const uint64_t t0 = now_ns();
     const uint32_t n = (uint32_t)b->entries.size();
+    uint64_t *h_off = reinterpret_cast<uint64_t *>(b->h_buf);
+    uint32_t *h_ids = reinterpret_cast<uint32_t *>(h_off + n);
+    uint8_t *h_lods = reinterpret_cast<uint8_t *>(h_ids + n);
     for (uint32_t i = 0; i < n; i++) {
         const Entry &e = s->entries[b->entries[i]];
-        b->h_ids[i] = e.brick;
-        b->h_lods[i] = e.lod;
-        b->h_off[i] = e.slot / 4;
+        h_ids[i] = e.brick;
+        h_lods[i] = e.lod;
+        h_off[i] = e.slot / 4;
     }
-    int rc = CSV_OK;
-    if (hipMemcpyAsync(b->d_ids, b->h_ids, 4ull * n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(b->d_lods, b->h_lods, n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(b->d_off, b->h_off, 8ull * n, hipMemcpyHostToDevice, b->stream) != hipSuccess)
-        rc = CSV_EHIP;
-    if (!rc)
-        rc = csv_decode_bricks(s->pool, b->d_ids, b->d_lods, 0, b->d_off, n,
+    const uint64_t *d_off = reinterpret_cast<const uint64_t *>(b->d_buf);
+    const uint32_t *d_ids = reinterpret_cast<const uint32_t *>(d_off + n);
+    const uint8_t *d_lods = reinterpret_cast<const uint8_t *>(d_ids + n);
+    int rc = csv_decode_bricks(s->pool, d_ids, d_lods, 0, d_off, n,
                                reinterpret_cast<uint32_t *>(s->d_cache), b->stream);
     if (!rc && hipEventRecord(b->done, b->stream) != hipSuccess) rc = CSV_EHIP;
     if (rc) {
@@ -287,6 +319,7 @@ void launch_batch(csv_server *s, Batch *b) {
     }
     b->busy = true;
     s->n_batches++;
+    s->d_launch += now_ns() - t0;
 }
 
 void retire(csv_server *s, Batch &b, uint64_t t) {
@@ -309,11 +342,12 @@ void retire(csv_server *s, Batch &b, uint64_t t) {
     b.busy = false;
 }
 
-// one request: true if handled (completed, joined or admitted), false if it must wait
-bool admit(csv_server *s, const Pending &p) {
+// one request: true if handled (completed, joined or admitted), false if it
+// must wait; t_now: the time of this admission round (hits complete at it)
+bool admit(csv_server *s, const Pending &p, uint64_t t_now) {
     const csv_request &r = p.r;
     if (r.brick_id >= s->n_bricks || r.lod > 5) {
-        complete(s, p.idx, nullptr, CSV_ERANGE, false, now_ns());
+        complete(s, p.idx, nullptr, CSV_ERANGE, false, t_now);
         return true;
     }
     const size_t key = (size_t)r.brick_id * kClasses + r.lod;
@@ -321,8 +355,8 @@ bool admit(csv_server *s, const Pending &p) {
     if (id >= 0) {
         Entry &e = s->entries[id];
         if (e.state == kValid) {
-            lru_touch(s, (uint32_t)id);
-            complete(s, p.idx, &s->entries[(size_t)id], CSV_OK, true, now_ns());
+            e.ref = 1;
+            complete(s, p.idx, &s->entries[(size_t)id], CSV_OK, true, t_now);
             s->d_hit++;
         } else {
             s->req_next[p.idx] = e.waiters;
@@ -332,12 +366,23 @@ bool admit(csv_server *s, const Pending &p) {
         return true;
     }
     const uint64_t bytes = class_bytes(r.lod);
-    if (s->inflight + bytes > s->opts.inflight_bytes && s->inflight > 0) return false;
+    // decodes in flight hold cache slots: keep them within a quarter of the cache
+    const uint64_t budget = std::min(s->opts.inflight_bytes, s->opts.cache_bytes / 4);
+    if (s->inflight + bytes > budget && s->inflight > 0) {
+        s->stall[1]++;
+        return false;
+    }
     if (!s->forming) s->forming = free_batch(s);
-    if (!s->forming) return false;
+    if (!s->forming) {
+        s->stall[0]++;
+        return false;
+    }
     uint64_t slot;
     if (!alloc_slot(s, r.lod, &slot)) {
-        if (!rebuild(s) || !alloc_slot(s, r.lod, &slot)) return false;
+        if (!rebuild(s) || !alloc_slot(s, r.lod, &slot)) {
+            s->stall[2]++;
+            return false;
+        }
     }
     uint32_t nid;
     if (!s->free_entries.empty()) {
@@ -354,6 +399,7 @@ bool admit(csv_server *s, const Pending &p) {
     e.pins = 0;
     e.slot = slot;
     e.in_lru = false;
+    e.ref = 0;
     e.prev = e.next = -1;
     e.waiters = (int32_t)p.idx;
     s->req_next[p.idx] = -1;
@@ -375,6 +421,7 @@ void worker_main(csv_server *s) {
     uint32_t idle = 0;
     while (!s->stop.load(std::memory_order_acquire)) {
         bool work = false;
+        const uint64_t t_loop = now_ns();
         {
             std::lock_guard<std::mutex> lk(s->in_mu);
             take.swap(s->inbox);
@@ -413,8 +460,9 @@ void worker_main(csv_server *s) {
                 if (s->entries[id].pins) s->entries[id].pins--;
         }
         // admission, in arrival order
+        const uint64_t t_now = now_ns();
         while (!s->pending.empty()) {
-            if (!admit(s, s->pending.front())) break;
+            if (!admit(s, s->pending.front(), t_now)) break;
             s->pending.pop_front();
             work = true;
         }
@@ -424,6 +472,7 @@ void worker_main(csv_server *s) {
             s->forming = nullptr;
             work = true;
         }
+        if (work) s->d_busy += now_ns() - t_loop;
         publish(s);
         if (work) {
             idle = 0;
@@ -435,7 +484,8 @@ void worker_main(csv_server *s) {
     }
 }
 
-double pct(std::vector<float> v, double q) {
+double pct(const std::deque<float> &d, double q) {
+    std::vector<float> v(d.begin(), d.end());
     if (v.empty()) return 0.0;
     const size_t k = std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5));
     std::nth_element(v.begin(), v.begin() + (long)k, v.end());
@@ -491,12 +541,9 @@ int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out
         const size_t n = opts.max_batch;
         if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&b.h_ids), 4 * n, 0) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&b.h_lods), n, 0) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&b.h_off), 8 * n, 0) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&b.d_ids), 4 * n) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&b.d_lods), n) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&b.d_off), 8 * n) != hipSuccess)
+            hipHostMalloc(reinterpret_cast<void **>(&b.h_buf), 13 * n + 16, hipHostMallocMapped | hipHostMallocCoherent) !=
+                hipSuccess ||
+            hipHostGetDevicePointer(reinterpret_cast<void **>(&b.d_buf), b.h_buf, 0) != hipSuccess)
             rc = CSV_ENOMEM;
     }
     (void)hipSetDevice(prev);
@@ -525,12 +572,21 @@ int csv_server_poll(csv_server *s, csv_completion *c, uint32_t cap, uint32_t *go
     // the completions handed out by the previous poll are released now
     s->to_unpin.insert(s->to_unpin.end(), s->delivered.begin(), s->delivered.end());
     s->delivered.clear();
-    const uint32_t k = (uint32_t)std::min<size_t>(cap, s->outbox.size());
-    std::copy(s->outbox.begin(), s->outbox.begin() + k, c);
+    const size_t h = s->outbox_head;
+    const uint32_t k = (uint32_t)std::min<size_t>(cap, s->outbox.size() - h);
+    std::copy(s->outbox.begin() + (long)h, s->outbox.begin() + (long)(h + k), c);
     for (uint32_t i = 0; i < k; i++)
-        if (s->outbox_entry[i] >= 0) s->delivered.push_back((uint32_t)s->outbox_entry[i]);
-    s->outbox.erase(s->outbox.begin(), s->outbox.begin() + k);
-    s->outbox_entry.erase(s->outbox_entry.begin(), s->outbox_entry.begin() + k);
+        if (s->outbox_entry[h + i] >= 0) s->delivered.push_back((uint32_t)s->outbox_entry[h + i]);
+    s->outbox_head = h + k;
+    if (s->outbox_head == s->outbox.size()) {
+        s->outbox.clear();
+        s->outbox_entry.clear();
+        s->outbox_head = 0;
+    } else if (s->outbox_head > 65536 && 2 * s->outbox_head > s->outbox.size()) {  // compact now and then
+        s->outbox.erase(s->outbox.begin(), s->outbox.begin() + (long)s->outbox_head);
+        s->outbox_entry.erase(s->outbox_entry.begin(), s->outbox_entry.begin() + (long)s->outbox_head);
+        s->outbox_head = 0;
+    }
     *got = k;
     return CSV_OK;
 }
@@ -555,6 +611,11 @@ int csv_server_stats(csv_server *s, csv_stats *st) {
     st->p99_miss_us = pct(s->lat_miss, 0.99);
     st->max_us = s->lat_all.empty() ? 0.0 : *std::max_element(s->lat_all.begin(), s->lat_all.end());
     st->error = s->error;
+    st->worker_busy_ns = s->busy_ns;
+    st->worker_launch_ns = s->launch_ns;
+    st->stall_batch = s->stall[0];
+    st->stall_inflight = s->stall[1];
+    st->stall_slot = s->stall[2];
     return CSV_OK;
 }
 
@@ -565,6 +626,8 @@ int csv_server_reset_stats(csv_server *s) {
     s->lat_miss.clear();
     s->n_req = s->n_hit = s->n_miss = s->n_join = s->n_batches = s->n_evict = s->n_rebuild = 0;
     s->decoded_bytes = 0;
+    s->busy_ns = s->launch_ns = 0;
+    s->stall[0] = s->stall[1] = s->stall[2] = 0;
     return CSV_OK;
 }
 
@@ -579,12 +642,7 @@ void csv_server_destroy(csv_server *s) {
         if (b.stream) (void)hipStreamSynchronize(b.stream);
         if (b.done) (void)hipEventDestroy(b.done);
         if (b.stream) (void)hipStreamDestroy(b.stream);
-        (void)hipHostFree(b.h_ids);
-        (void)hipHostFree(b.h_lods);
-        (void)hipHostFree(b.h_off);
-        (void)hipFree(b.d_ids);
-        (void)hipFree(b.d_lods);
-        (void)hipFree(b.d_off);
+        (void)hipHostFree(b.h_buf);
     }
     (void)hipFree(s->d_cache);
     (void)hipSetDevice(prev);
@@ -612,7 +670,8 @@ int csv_server_run_trace(csv_server *s, const csv_request *reqs, uint32_t n, csv
                          uint64_t timeout_ns, uint32_t *n_done) {
     if (!s || (n && !reqs)) return CSV_EINVAL;
     std::vector<csv_request> batch;
-    std::vector<csv_completion> buf(65536);
+    // modest polls: a poll's completions pin their cache entries until the next poll
+    std::vector<csv_completion> buf(4096);
     const uint64_t t0 = now_ns();
     uint32_t next = 0, got_total = 0;
     uint64_t last_arrival = t0;
