@@ -52,14 +52,8 @@ constexpr uint32_t kLdsBytes = 160 * 1024;
 constexpr uint32_t kLutLdsCap = 24 * 1024;  // decode tables kept in LDS when they fit
 constexpr uint32_t kPalFast = 252;       // u8 indices 0..251; 252 marks an invalid reference, 253..255 open ones
 constexpr uint32_t kRingWords = 1024;    // word ring of the entropy decoder
-#ifndef CSV_WAVES_B
-#define CSV_WAVES_B 4
-#endif
-constexpr int kWavesB = CSV_WAVES_B;     // waves of a leaf workgroup
-constexpr uint32_t kThreadsB = 64 * kWavesB;
-#ifndef CSV_LEAF_ATTR
-#define CSV_LEAF_ATTR
-#endif
+constexpr int kWavesLeaf = 8;            // waves of a leaf workgroup (LDS arena)
+constexpr int kWavesLeafG = 4;           // waves of a leaf workgroup with a global-memory arena
 
 // level m (1..4) offsets (entries) inside the Morton-ordered level arrays
 __device__ constexpr uint32_t kLvOff[5] = {0, 0, 4096, 4608, 4672};
@@ -113,9 +107,12 @@ struct LaunchA {
 
 struct LaunchB {
     uint32_t arena_bytes;    // LDS arena per workgroup
-    uint32_t *queue;         // work counter over the leaf list
+    uint32_t *queue;         // work counter over the leaf list (nullptr: static round robin)
     const uint32_t *leaf_list;
     const uint32_t *leaf_count;
+    uint32_t *slow_list;     // leaf requests that do not fit the LDS arena
+    uint32_t *slow_count;
+    uint32_t *slow_queue;
     const uint8_t *slots;
     uint32_t slot_bytes;
     uint32_t slot_dw;
@@ -895,7 +892,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
 struct SmallB {
     uint32_t req;
     int err;
-    uint32_t wt[kWavesB][2];  // per-wave totals of P_a, P_delta
+    uint32_t wt[kWavesLeaf][2];  // per-wave totals of P_a, P_delta
 };
 
 // Arena of a leaf brick: palette (P entries) and nib4 16-byte groups of
@@ -946,7 +943,7 @@ __device__ __forceinline__ uint32_t chase(const IdxT *D, uint32_t i, uint32_t v)
 // nib holds the nibbles from position nib0 on; l1m (Morton order) and bm1
 // come from the front kernel; pal is the palette; ar the arena.  False on a
 // malformed stream.
-template <class IdxT, bool kG>
+template <class IdxT, bool kG, int NW>
 __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t ipl, const uint32_t *nib,
                                             uint32_t nib0, const IdxT *l1m, const uint64_t *bm1w,
                                             const uint32_t *pal, uint8_t *ar, const LayoutL &lay, SmallB *sm,
@@ -962,7 +959,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     const uint32_t seg = h.c1, seg_end = h.c0;
     if ((uint64_t)seg + 8ull * E1 > seg_end || E1 > 4096) return false;
     // L_1 to dense order: Morton indices 16t .. 16t + 15 share bits 4.. of t
-    for (uint32_t t = tid; t < 256; t += kThreadsB) {
+    for (uint32_t t = tid; t < 256; t += (64 * NW)) {
         const uint32_t base = (((t >> 2) & 1u) << 2 | ((t >> 5) & 1u) << 3) +
                               16 * (((t & 1u) << 1) | (((t >> 3) & 1u) << 2) | (((t >> 6) & 1u) << 3)) +
                               256 * ((((t >> 1) & 1u) << 1) | (((t >> 4) & 1u) << 2) | (((t >> 7) & 1u) << 3));
@@ -989,7 +986,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     __syncthreads();
     // every voxel takes its L_1 node's value (expanded nodes are overwritten
     // below); pass 1: this wave's P_a and P_delta totals
-    for (uint32_t e = tid; e < 2048; e += kThreadsB) {  // half rows of 16 voxels
+    for (uint32_t e = tid; e < 2048; e += (64 * NW)) {  // half rows of 16 voxels
         const uint32_t hx = e & 1u, y = (e >> 1) & 31u, z = e >> 6;
         const IdxT *src = l1 + 8 * hx + 16 * (y >> 1) + 256 * (z >> 1);
         IdxT *o = D + 16 * hx + 32 * y + 1024 * z;
@@ -1012,7 +1009,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
         }
     }
     const uint32_t D0 = seg_end - seg - 8 * E1, ops0 = seg + D0 - nib0;
-    const uint32_t nch = (E1 + 63) / 64, cpw = (nch + kWavesB - 1) / kWavesB;
+    const uint32_t nch = (E1 + 63) / 64, cpw = (nch + NW - 1) / NW;
     const uint32_t cb = min(w * cpw, nch), ce = min(cb + cpw, nch);
     uint32_t tpa = 0, tpd = 0;
     for (uint32_t c = cb; c < ce; c++) {
@@ -1031,7 +1028,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     }
     __syncthreads();
     // the expanded L_1 nodes in Morton (= stream) order, from the bitmask
-    for (uint32_t t = tid; t < 256; t += kThreadsB) {
+    for (uint32_t t = tid; t < 256; t += (64 * NW)) {
         const uint32_t wd = t >> 2, q = t & 3u;
         const uint64_t word = bm1w[wd];
         uint32_t bits = (uint32_t)(word >> (16 * q)) & 0xFFFFu;
@@ -1045,7 +1042,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     }
     uint32_t bpa = 0, bpd = 0, PDtot = 0;
 #pragma unroll
-    for (int v = 0; v < kWavesB; v++) {
+    for (int v = 0; v < NW; v++) {
         const uint32_t a0 = sm->wt[v][0], a1 = sm->wt[v][1];
         if ((uint32_t)v < w) {
             bpa += a0;
@@ -1105,7 +1102,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     // followed along the dense level (at most three links)
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
     auto slices = [&](auto al16) {
-        for (uint32_t zz = w; zz < 32; zz += kWavesB) {
+        for (uint32_t zz = w; zz < 32; zz += NW) {
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const uint32_t v0 = 4 * (L & 7u) + 32 * ((L >> 3) + 8 * (uint32_t)c) + 1024 * zz;
@@ -1146,20 +1143,26 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     return true;
 }
 
-__global__ __launch_bounds__(kThreadsB) CSV_LEAF_ATTR void leaf_kernel(DecodeArgs a, LaunchB l) {
+// kSlow false: bricks whose arrays fit the LDS arena, the others deferred
+// to the slow list; kSlow true: the slow list, on an arena in global memory
+template <int NW, bool kSlow>
+__global__ __launch_bounds__(64 * NW) void leaf_kernel(DecodeArgs a, LaunchB l) {
+    constexpr uint32_t NT = 64 * NW;
     extern __shared__ __align__(16) uint8_t smem[];
     SmallB *sm = reinterpret_cast<SmallB *>(smem);
     uint8_t *arena = smem + align16(sizeof(SmallB));
     uint8_t *gslot = l.scratch ? glob(l.scratch) + (size_t)blockIdx.x * l.scratch_bytes : nullptr;
     const uint32_t tid = threadIdx.x;
     const uint32_t hdr = csv::record_header_words(kLog2);
-    const uint32_t n_leaf = *glob(l.leaf_count);
+    const uint32_t n_items = *glob(kSlow ? l.slow_count : l.leaf_count);
+    const uint32_t *list = kSlow ? l.slow_list : l.leaf_list;
+    uint32_t *queue = kSlow ? l.slow_queue : l.queue;
     for (uint32_t k = 0;; k++) {
-        if (tid == 0) sm->req = l.queue ? atomicAdd(l.queue, 1u) : blockIdx.x + k * gridDim.x;
+        if (tid == 0) sm->req = queue ? atomicAdd(queue, 1u) : blockIdx.x + k * gridDim.x;
         __syncthreads();
         const uint32_t item = sm->req;
-        if (item >= n_leaf) break;
-        const uint32_t rq = l.leaf_list[item];
+        if (item >= n_items) break;
+        const uint32_t rq = list[item];
         Hdr h;
         uint32_t *dst, count, fill;
         (void)load_request(a, rq, h, dst, count, fill);  // a decode at t = 0: checked by the front kernel
@@ -1171,38 +1174,45 @@ __global__ __launch_bounds__(kThreadsB) CSV_LEAF_ATTR void leaf_kernel(DecodeArg
         const uint4 meta = *reinterpret_cast<const uint4 *>(sbm + kSlotBm);
         const uint32_t E1 = uniform(meta.x), ipl = uniform(meta.y);
         const uint32_t E1c = E1 < 4096 ? E1 : 4096u;
-        // nibbles from the delta segment of L_0 on, from a 16-byte boundary
-        const uint32_t nb0 = (h.c1 >> 5) << 2, nib4 = (((h.c0 + 7) >> 3) + 2 - nb0 + 3) / 4;
-        const LayoutL fast = make_layout_l(true, h.P, nib4, E1c, 1);
-        const bool fits = h.P <= kPalFast && fast.total <= l.arena_bytes;
         if (tid == 0) sm->err = 0;
-        bool ok;
-        if (fits) {
-            for (uint32_t e = tid; e < h.P; e += kThreadsB) reinterpret_cast<uint32_t *>(arena + fast.pal)[e] = h.rec[hdr + e];
-            for (uint32_t e = tid; e < nib4; e += kThreadsB)
-                reinterpret_cast<uint4 *>(arena + fast.nib)[e] = reinterpret_cast<const uint4 *>(gnib + nb0)[e];
-            if (tid < 32) reinterpret_cast<uint4 *>(arena + fast.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
-            __syncthreads();
-            ok = leaf_replay<uint8_t, false>(h, E1, ipl, reinterpret_cast<const uint32_t *>(arena + fast.nib), 8 * nb0,
-                                             slv, reinterpret_cast<const uint64_t *>(arena + fast.bm1),
-                                             reinterpret_cast<const uint32_t *>(arena + fast.pal), arena, fast, sm, dst);
-        } else if (gslot) {
+        bool ok = true, done = true;
+        if constexpr (!kSlow) {
+            // nibbles from the delta segment of L_0 on, from a 16-byte boundary
+            const uint32_t nb0 = (h.c1 >> 5) << 2, nib4 = (((h.c0 + 7) >> 3) + 2 - nb0 + 3) / 4;
+            const LayoutL fast = make_layout_l(true, h.P, nib4, E1c, 1);
+            if (h.P <= kPalFast && fast.total <= l.arena_bytes) {
+                for (uint32_t e = tid; e < h.P; e += NT) reinterpret_cast<uint32_t *>(arena + fast.pal)[e] = h.rec[hdr + e];
+                for (uint32_t e = tid; e < nib4; e += NT)
+                    reinterpret_cast<uint4 *>(arena + fast.nib)[e] = reinterpret_cast<const uint4 *>(gnib + nb0)[e];
+                if (tid < 32) reinterpret_cast<uint4 *>(arena + fast.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
+                __syncthreads();
+                ok = leaf_replay<uint8_t, false, NW>(h, E1, ipl, reinterpret_cast<const uint32_t *>(arena + fast.nib),
+                                                     8 * nb0, slv, reinterpret_cast<const uint64_t *>(arena + fast.bm1),
+                                                     reinterpret_cast<const uint32_t *>(arena + fast.pal), arena, fast,
+                                                     sm, dst);
+            } else if (l.slow_list) {  // the slow kernel takes it
+                done = false;
+                if (tid == 0) l.slow_list[atomicAdd(l.slow_count, 1u)] = rq;
+            } else {  // the pool's bounds say every brick fits: a corrupt record
+                ok = false;
+            }
+        } else {
             phase_mark(rq, 7);
             __syncthreads();
             const uint64_t *gbm = reinterpret_cast<const uint64_t *>(sbm);
-            if (h.P <= kPalFast)
-                ok = leaf_replay<uint8_t, true>(h, E1, ipl, gnib, 0, slv, gbm, h.rec + hdr, gslot,
-                                                make_layout_l(false, 0, 0, 4096, 1), sm, dst);
+            if (!gslot)
+                ok = false;
+            else if (h.P <= kPalFast)
+                ok = leaf_replay<uint8_t, true, NW>(h, E1, ipl, gnib, 0, slv, gbm, h.rec + hdr, gslot,
+                                                    make_layout_l(false, 0, 0, 4096, 1), sm, dst);
             else
-                ok = leaf_replay<uint16_t, true>(h, E1, ipl, gnib, 0, reinterpret_cast<const uint16_t *>(slv), gbm,
-                                                 h.rec + hdr, gslot, make_layout_l(false, 0, 0, 4096, 2), sm, dst);
-        } else {
-            ok = false;
+                ok = leaf_replay<uint16_t, true, NW>(h, E1, ipl, gnib, 0, reinterpret_cast<const uint16_t *>(slv), gbm,
+                                                     h.rec + hdr, gslot, make_layout_l(false, 0, 0, 4096, 2), sm, dst);
         }
         __syncthreads();
-        if (!ok) {
-            if (tid == 0) report(a.err, fits || gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
-            fill_labels<kThreadsB>(dst, count, 0u, tid);
+        if (done && !ok) {
+            if (tid == 0) report(a.err, !kSlow || gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
+            fill_labels<NT>(dst, count, 0u, tid);
         }
         __syncthreads();
     }
@@ -1256,7 +1266,9 @@ struct LaunchBufs {
     uint8_t *slots = nullptr;      // slot_bytes per request
     uint32_t *order = nullptr;     // longest-first order
     uint32_t *leaf_list = nullptr; // requests for the leaf kernel
-    uint32_t *small = nullptr;     // [0, 64): order bins; 64, 65: work counters; 66: leaf count
+    uint32_t *slow_list = nullptr; // ... of them for its global-arena variant
+    uint32_t *small = nullptr;     // 64: front counter, 65: leaf counter, 66: leaf count, 67: slow count,
+                                   // 68: slow counter
     uint32_t slot_dw = 0;
     uint32_t cap_n = 0;
     uint32_t slot_bytes() const { return 4 * slot_dw + kSlotExtra; }
@@ -1264,10 +1276,12 @@ struct LaunchBufs {
         (void)hipFree(slots);
         (void)hipFree(order);
         (void)hipFree(leaf_list);
+        (void)hipFree(slow_list);
         (void)hipFree(small);
         slots = nullptr;
         order = nullptr;
         leaf_list = nullptr;
+        slow_list = nullptr;
         small = nullptr;
         cap_n = 0;
     }
@@ -1280,14 +1294,16 @@ struct LaunchBufs {
         if (hipMalloc(reinterpret_cast<void **>(&slots), (size_t)cap * slot_bytes()) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&order), 4ull * cap) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&leaf_list), 4ull * cap) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&small), 4 * 68) != hipSuccess) {
+            hipMalloc(reinterpret_cast<void **>(&slow_list), 4ull * cap) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&small), 4 * 72) != hipSuccess ||
+            hipMemset(small, 0, 4 * 72) != hipSuccess) {
             release();
             return CSV_ENOMEM;
         }
         cap_n = cap;
         return CSV_OK;
     }
-    uint64_t bytes() const { return slots ? ((uint64_t)cap_n * (slot_bytes() + 8) + 4 * 68) : 0; }
+    uint64_t bytes() const { return slots ? ((uint64_t)cap_n * (slot_bytes() + 12) + 4 * 72) : 0; }
 };
 constexpr size_t kMaxStreamBufs = 16;
 
@@ -1436,7 +1452,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     static std::once_flag once_b;
     static hipError_t attr_b = hipSuccess;
-    std::call_once(once_b, [] { attr_b = set_lds_attr(leaf_kernel); });
+    std::call_once(once_b, [] { attr_b = set_lds_attr(leaf_kernel<kWavesLeaf, false>); });
     if (attr_b != hipSuccess) return CSV_EHIP;
     std::lock_guard<std::mutex> lk(pool->mu);
     LaunchBufs *B = fixed;
@@ -1461,7 +1477,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     a.out = out;
     a.n = n;
     a.err = pool->d_err;
-    uint32_t *ctr = B->small + 2 * kBins;  // front counter, leaf counter, leaf list length
+    uint32_t *ctr = B->small + 2 * kBins;  // front counter, leaf counter, leaf count, slow count, slow counter
     LaunchA la;
     la.lut_lds_words = lut_lds_words(pool);
     la.queue = queue ? ctr : nullptr;
@@ -1477,12 +1493,18 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     lb.queue = (queue || plain) ? ctr + 1 : nullptr;
     lb.leaf_list = B->leaf_list;
     lb.leaf_count = ctr + 2;
+    lb.slow_count = ctr + 3;
+    lb.slow_queue = ctr + 4;
     lb.slots = B->slots;
     lb.slot_bytes = B->slot_bytes();
     lb.slot_dw = B->slot_dw;
     lb.scratch = pool->d_scratch;
     lb.scratch_bytes = kArenaBytes;
     const size_t lds_b = kSmallB + (size_t)lb.arena_bytes;
+    // the global-arena variant runs only for pools with bricks that may not fit the LDS arena
+    const bool slow = pool->any_big_palette || pool->max_fast_bytes > lb.arena_bytes;
+    const size_t lds_g = kSmallB;
+    lb.slow_list = slow ? B->slow_list : nullptr;
     const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
     // a small batch takes smaller front workgroups, so that its bricks spread over the CUs
     while (waves_a > 4 && (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a < cu) waves_a /= 2;
@@ -1490,8 +1512,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     const uint32_t lds_a = align16(4 * la.lut_lds_words) + (uint32_t)waves_a * kWaveLds;
     const uint32_t fit_a = std::max(1u, std::min(kLdsBytes / lds_a, 32u / (uint32_t)waves_a));
     const uint32_t grid_a = std::max(1u, std::min(cu * fit_a, (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a));
-    uint32_t grid_b = std::min(cu * groups_b, n);
-    if (pool->d_scratch) grid_b = std::min(grid_b, pool->n_slots);
+    const uint32_t grid_b = std::min(cu * groups_b, n);
     auto go_a = [&](const DecodeArgs &aa, const LaunchA &L, uint32_t grid) {
         switch (waves_a) {
             case 4: launch_a<4>(aa, L, grid, lds_a, s); break;
@@ -1505,18 +1526,23 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
         for (uint32_t i = 0; i < n; i++) {
             la.base = i;
             b.n = i + 1;
-            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 3u);
+            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 5u);
             go_a(b, la, 1);
-            hipLaunchKernelGGL(leaf_kernel, dim3(1), dim3(kThreadsB), lds_b, s, b, lb);
+            hipLaunchKernelGGL((leaf_kernel<kWavesLeaf, false>), dim3(1), dim3(64 * kWavesLeaf), lds_b, s, b, lb);
+            if (slow) hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(1), dim3(64 * kWavesLeafG), lds_g, s, b, lb);
         }
     } else {
-        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 3u);
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 5u);
         if (lpt) {
             hipLaunchKernelGGL(order_lpt, dim3(1), dim3(1024), 0, s, a, B->order);
             la.order = B->order;
         }
         go_a(a, la, grid_a);
-        hipLaunchKernelGGL(leaf_kernel, dim3(grid_b), dim3(kThreadsB), lds_b, s, a, lb);
+        hipLaunchKernelGGL((leaf_kernel<kWavesLeaf, false>), dim3(grid_b), dim3(64 * kWavesLeaf), lds_b, s, a, lb);
+        if (slow) {
+            const uint32_t grid_g = std::min(std::min(cu * 4, n), std::max(pool->n_slots, 1u));
+            hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(grid_g), dim3(64 * kWavesLeafG), lds_g, s, a, lb);
+        }
     }
     return hipGetLastError() == hipSuccess ? CSV_OK : CSV_EHIP;
 }
