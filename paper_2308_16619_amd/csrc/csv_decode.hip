@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -67,7 +68,7 @@ __device__ constexpr uint32_t kLstOff[5] = {0, 0, 72, 8, 0};
 // (u8), their expansion bits and lists, the palette
 constexpr uint32_t kWaveLds = 8192;
 constexpr uint32_t kWLv = 0, kWBm = 4688, kWLst = 5280, kWPal = 6448;
-constexpr uint32_t kWDeltaDw = (kWaveLds - kWPal) / 4;  // the palette area holds a level's deltas during the replay
+constexpr uint32_t kWDeltaDw = (kWaveLds - kWPal) / 4;  // the palette area holds a level's nibbles during the replay
 
 // Per-request slot in global memory: the packed nibbles (slot_dw dwords),
 // then the levels (u16 levels 1..4 for big palettes; else u8 L_1 only, in
@@ -118,6 +119,7 @@ struct LaunchB {
     uint32_t slot_dw;
     uint8_t *scratch;        // global arena per workgroup for bricks that do not fit LDS
     uint32_t scratch_bytes;
+    uint32_t ref_cap;        // longest list of same-level references (LDS room permitting)
 };
 
 // ---------------------------------------------------------------------------
@@ -129,12 +131,14 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
 }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// inclusive prefix sum over the 64 lanes (DPP row shifts, then row broadcasts)
+// inclusive prefix sum over the 64 lanes (DPP row shifts, then row
+// broadcasts); lanes shifted in from outside a row read 0, so that each
+// step is one v_add_u32_dpp
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);  // row_shr:8
     v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
     v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
@@ -570,7 +574,9 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
                 const uint64_t bal = __ballot(need);
                 const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, cursor & (kRingWords - 1)));
-                const uint32_t wd = ring[pos];
+                uint32_t wd = ring[pos];
+                // every lane reads (the read is not worth a branch on the critical path)
+                __asm__ volatile("" : "+v"(wd));
                 x = need ? ((x << 16) | wd) : x;
                 cursor += (uint32_t)__popcll(bal);
                 sb[64 * j + L] = (uint8_t)(e & 15u);
@@ -666,85 +672,102 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
         if ((uint64_t)seg + 8ull * E > seg_end) return false;
         const uint32_t D = seg_end - seg - 8 * E, ops0 = seg + D;  // deltas precede the operations
         const uint32_t pmask0 = axis_mask(0, Bp), pmask1 = axis_mask(1, Bp), pmask2 = axis_mask(2, Bp);
-        // the level's delta nibbles in LDS when they fit (read by lanes with P_delta children)
-        const uint32_t d0 = seg >> 3, dn = D ? ((seg + D + 7) >> 3) - d0 + 1 : 0u;
-        const uint32_t *dnib = nib;
-        uint32_t dbase = seg;
-        if (dn <= kWDeltaDw) {
-            for (uint32_t e = L; e < dn; e += 64) dstage[e] = nib[d0 + e];
-            wsync();
-            dnib = dstage;
-            dbase = seg - 8 * d0;
-        }
+        // the level's nibbles (deltas, then operations) in LDS when they fit:
+        // one round trip to global memory per level instead of one per 64
+        // nodes.  src holds the nibbles from position off on.
         uint32_t bpa = 0, bpd = 0, bex = 0;
         bool bad = false;
-        for (uint32_t c = 0; c < (E + 63) / 64; c++) {
-            const uint32_t r = 64 * c + L;
-            const bool act = r < E;
-            const uint32_t q = (act && plist) ? (uint32_t)plist[r] : 0u;
-            const uint32_t wd = act ? nib8(nib, ops0 + 8 * r) : 0u;
-            uint32_t pam, pdm, exm, cnt;
-            nibble_counts(wd, act, pam, pdm, exm, cnt);
-            const uint32_t inc = wave_incl_scan(cnt), exc = inc - cnt;
-            const uint32_t tot = uniform(__builtin_amdgcn_readlane(inc, 63));
-            if (act) {
-                const uint32_t pv = up ? (uint32_t)up[q] : 0u;
-                uint32_t nb[3], nbok = 0, lowok = 0;
+        auto run = [&](const uint32_t *src, uint32_t off) __attribute__((always_inline)) {
+            for (uint32_t c = 0; c < (E + 63) / 64; c++) {
+                const uint32_t r = 64 * c + L;
+                const bool act = r < E;
+                const uint32_t q = (act && plist) ? (uint32_t)plist[r] : 0u;
+                const uint32_t wd = act ? nib8(src, ops0 - off + 8 * r) : 0u;
+                uint32_t pam, pdm, exm, cnt;
+                nibble_counts(wd, act, pam, pdm, exm, cnt);
+                const uint32_t inc = wave_incl_scan(cnt), exc = inc - cnt;
+                const uint32_t tot = uniform(__builtin_amdgcn_readlane(inc, 63));
+                if (act) {
+                    const uint32_t pv = up ? (uint32_t)up[q] : 0u;
+                    uint32_t nb[3], nbok = 0, lowok = 0;
 #pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    const uint32_t am = a == 0 ? pmask0 : (a == 1 ? pmask1 : pmask2);
-                    const bool hi = up && (q & am) != am;
-                    nb[a] = hi ? (uint32_t)up[morton_inc(q, am)] : 0u;
-                    nbok |= hi ? (1u << a) : 0u;
-                    lowok |= (q & am) ? (1u << a) : 0u;
-                }
-                const VT vals = replay8<IdxT>(wd, pv, nb, nbok, lowok, ipl + bpa + (exc & 1023u),
-                                                      compact_nibble_bits(pam), compact_nibble_bits(pdm), dnib,
-                                                      dbase + bpd + ((exc >> 10) & 1023u), P, false, bad);
-                *reinterpret_cast<VT *>(cur + 8 * q) = vals;
-                uint32_t ex8 = compact_nibble_bits(exm);
-                cbm[q] = (uint8_t)ex8;
-                if (want_list) {
-                    uint32_t pos = bex + (exc >> 20);
-                    while (ex8) {
-                        const uint32_t k = __builtin_ctz(ex8);
-                        ex8 &= ex8 - 1;
-                        if (pos < list_cap) clist[pos] = (uint16_t)(8 * q + k);
-                        pos++;
+                    for (int a = 0; a < 3; a++) {
+                        const uint32_t am = a == 0 ? pmask0 : (a == 1 ? pmask1 : pmask2);
+                        const bool hi = up && (q & am) != am;
+                        nb[a] = hi ? (uint32_t)up[morton_inc(q, am)] : 0u;
+                        nbok |= hi ? (1u << a) : 0u;
+                        lowok |= (q & am) ? (1u << a) : 0u;
+                    }
+                    const VT vals = replay8<IdxT>(wd, pv, nb, nbok, lowok, ipl + bpa + (exc & 1023u),
+                                                          compact_nibble_bits(pam), compact_nibble_bits(pdm), src,
+                                                          seg - off + bpd + ((exc >> 10) & 1023u), P, false, bad);
+                    *reinterpret_cast<VT *>(cur + 8 * q) = vals;
+                    uint32_t ex8 = compact_nibble_bits(exm);
+                    cbm[q] = (uint8_t)ex8;
+                    if (want_list) {
+                        uint32_t pos = bex + (exc >> 20);
+                        while (ex8) {
+                            const uint32_t k = __builtin_ctz(ex8);
+                            ex8 &= ex8 - 1;
+                            if (pos < list_cap) clist[pos] = (uint16_t)(8 * q + k);
+                            pos++;
+                        }
                     }
                 }
+                bpa += tot & 1023u;
+                bpd += (tot >> 10) & 1023u;
+                bex += tot >> 20;
             }
-            bpa += tot & 1023u;
-            bpd += (tot >> 10) & 1023u;
-            bex += tot >> 20;
+        };
+        const uint32_t s0 = seg >> 3, sn = ((seg_end + 7) >> 3) - s0 + 1;
+        if (m == 1) phase_mark(h.rq, 13);
+        if (sn <= kWDeltaDw) {
+            for (uint32_t e = L; e < sn; e += 64) dstage[e] = nib[s0 + e];
+            wsync();
+            run(dstage, 8 * s0);
+        } else {
+            run(nib, 0);
         }
         if (__ballot(bad) || bpd != D || (want_list && bex > list_cap)) return false;
         wave_sync<kG>();
+        if (m == 1) phase_mark(h.rq, 14);
         // neighbour references into this level: a reference to child k of
         // the -1 neighbour along a lands on child k | 1 << a, so a chain has
-        // at most three links; it is followed to its end while other lanes
-        // resolve in place (a reader sees the reference or its final value,
-        // and both lead to the same value)
+        // at most three links (child 7 holds none); it is followed to its end
+        // while other lanes resolve in place (a reader sees the reference or
+        // its final value, and both lead to the same value).  The chains of
+        // a node's children are followed together, one link each per round.
         for (uint32_t r = L; r < E; r += 64) {
             const uint32_t q = plist ? (uint32_t)plist[r] : 0u;
             VT vals = *reinterpret_cast<const VT *>(cur + 8 * q);
-            bool dirty = false;
+            uint32_t v[7], qq[7], kk[7];
+            bool more = false;
 #pragma unroll
             for (int k = 0; k < 7; k++) {
-                uint32_t v = V::get(vals, k);
-                if (v >= kMark) {
-                    uint32_t qq = q, kk = (uint32_t)k;
-                    do {
-                        const int a = (int)(v - kMark);
-                        qq = morton_dec(qq, a == 0 ? pmask0 : (a == 1 ? pmask1 : pmask2));
-                        kk |= 1u << a;
-                        v = cur[8 * qq + kk];
-                    } while (v >= kMark);
-                    V::set(vals, k, v);
-                    dirty = true;
-                }
+                v[k] = V::get(vals, k);
+                qq[k] = q;
+                kk[k] = (uint32_t)k;
+                more |= v[k] >= kMark;
             }
-            if (dirty) *reinterpret_cast<VT *>(cur + 8 * q) = vals;
+            if (more) {
+                while (more) {
+#pragma unroll
+                    for (int k = 0; k < 7; k++) {
+                        if (v[k] >= kMark) {
+                            const uint32_t a = v[k] - kMark;
+                            qq[k] = morton_dec(qq[k], pmask0 << a);  // the axis masks are shifts of each other
+                            kk[k] |= 1u << a;
+                            v[k] = cur[8 * qq[k] + kk[k]];
+                        }
+                    }
+                    more = false;
+#pragma unroll
+                    for (int k = 0; k < 7; k++) more |= v[k] >= kMark;
+                }
+#pragma unroll
+                for (int k = 0; k < 7; k++) V::set(vals, k, v[k]);
+                *reinterpret_cast<VT *>(cur + 8 * q) = vals;
+            }
         }
         wave_sync<kG>();
         phase_mark(h.rq, 13 - m);
@@ -892,6 +915,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
 struct SmallB {
     uint32_t req;
     int err;
+    uint32_t nref;  // same-level references in the leaf level (list length)
     uint32_t wt[kWavesLeaf][2];  // per-wave totals of P_a, P_delta
 };
 
@@ -926,14 +950,33 @@ __device__ __forceinline__ uint32_t morton_coord(uint32_t p) {
     return (p & 1u) | ((p >> 2) & 2u) | ((p >> 4) & 4u) | ((p >> 6) & 8u);
 }
 
+// children of one expanded node that the child replay leaves as same-level
+// references (bit 4k for child k): R_x at kx = 0, R_y at ky = 0, R_z at
+// kz = 0, each where the neighbour lies inside the brick (lowok)
+__device__ __forceinline__ uint32_t ref_children(uint32_t w, uint32_t lowok) {
+    const uint32_t y = w & 0x77777777u;
+    return (zero_nibbles(y ^ 0x11111111u) & ((lowok & 1u) ? 0x01010101u : 0u)) |
+           (zero_nibbles(y ^ 0x22222222u) & ((lowok & 2u) ? 0x00110011u : 0u)) |
+           (zero_nibbles(y ^ 0x33333333u) & ((lowok & 4u) ? 0x00001111u : 0u));
+}
+
+// 4 * byte b of q in one instruction (an SDWA source select)
+template <int B>
+__device__ __forceinline__ uint32_t byte_x4(uint32_t q) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_%c2"
+            : "=v"(r)
+            : "v"(q), "n"(B));
+    return r;
+}
+
 // follow a chain of same-level references in the dense leaf level: value v
 // at voxel i, a reference to the voxel at -1 along axis v - kMark
 template <class IdxT>
 __device__ __forceinline__ uint32_t chase(const IdxT *D, uint32_t i, uint32_t v) {
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
     while (v >= kMark) {
-        const uint32_t a = v - kMark;
-        i -= a == 0 ? 1u : (a == 1 ? 32u : 1024u);
+        i -= 1u << (5 * (v - kMark));  // 1, 32 or 1024
         v = D[i];
     }
     return v;
@@ -941,13 +984,17 @@ __device__ __forceinline__ uint32_t chase(const IdxT *D, uint32_t i, uint32_t v)
 
 // The leaf level L_0 of one brick by one workgroup, and its 32^3 output.
 // nib holds the nibbles from position nib0 on; l1m (Morton order) and bm1
-// come from the front kernel; pal is the palette; ar the arena.  False on a
-// malformed stream.
+// come from the front kernel; pal is the palette; ar the arena.  With u8
+// indices in LDS, refs (ref_cap entries) lists the voxels that hold
+// same-level references; they are resolved in one pass before the output,
+// which then needs no chasing (a brick with more references than fit
+// chases them in the output loop).  False on a malformed stream.
 template <class IdxT, bool kG, int NW>
 __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t ipl, const uint32_t *nib,
                                             uint32_t nib0, const IdxT *l1m, const uint64_t *bm1w,
                                             const uint32_t *pal, uint8_t *ar, const LayoutL &lay, SmallB *sm,
-                                            uint32_t *dst) {
+                                            uint32_t *dst, uint16_t *refs, uint32_t ref_cap) {
+    constexpr bool kList = sizeof(IdxT) == 1 && !kG;
     using V = Vec8<IdxT>;
     using VT = typename V::T;
     const uint32_t tid = threadIdx.x, L = lane(), w = tid >> 6;
@@ -1060,24 +1107,43 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
         const bool act = r < E1;
         const uint32_t wd = act ? nib8(nib, ops0 + 8 * r) : 0u;
         const uint32_t cc = act ? (uint32_t)list1[r] : 0u;
+        const uint32_t X = cc & 15u, Y = (cc >> 4) & 15u, Z = (cc >> 8) & 15u;
+        const uint32_t lowok = (X > 0 ? 1u : 0u) | (Y > 0 ? 2u : 0u) | (Z > 0 ? 4u : 0u);
         uint32_t pam, pdm, exm, cnt;
         nibble_counts(wd, act, pam, pdm, exm, cnt);
-        cnt &= 0xFFFFFu;
+        uint32_t refm = 0;  // bits 20..29 of the scan: references of this lane's children
+        if constexpr (kList) refm = act ? ref_children(wd, lowok) : 0u;
+        cnt = (cnt & 0xFFFFFu) | ((uint32_t)__builtin_popcount(refm) << 20);
         const uint32_t inc = wave_incl_scan(cnt), exc = inc - cnt;
         const uint32_t tot = uniform(__builtin_amdgcn_readlane(inc, 63));
+        // child k = kx | ky << 1 | kz << 2 at voxel (2X + kx, 2Y + ky, 2Z + kz)
+        const uint32_t v0 = 2 * X + 64 * Y + 2048 * Z;
+        if constexpr (kList) {
+            const uint32_t tr = tot >> 20;
+            if (tr) {
+                uint32_t base = 0;
+                if (L == 0) base = atomicAdd(&sm->nref, tr);
+                base = uniform(__builtin_amdgcn_readlane(base, 0));
+                if (base + tr <= ref_cap) {
+                    uint32_t pos = base + (exc >> 20);
+                    while (refm) {
+                        const uint32_t k = (uint32_t)__builtin_ctz(refm) >> 2;
+                        refm &= refm - 1u;
+                        refs[pos++] = (uint16_t)(v0 + (k & 1u) + 32 * ((k >> 1) & 1u) + 1024 * (k >> 2));
+                    }
+                }
+            }
+        }
         if (act) {
-            const uint32_t X = cc & 15u, Y = (cc >> 4) & 15u, Z = (cc >> 8) & 15u;
             const uint32_t i = X + 16 * Y + 256 * Z;
             const uint32_t pv = l1[i];
             const uint32_t nbv[3] = {X < 15 ? (uint32_t)l1[i + 1] : 0u, Y < 15 ? (uint32_t)l1[i + 16] : 0u,
                                      Z < 15 ? (uint32_t)l1[i + 256] : 0u};
             const uint32_t nbok = (X < 15 ? 1u : 0u) | (Y < 15 ? 2u : 0u) | (Z < 15 ? 4u : 0u);
-            const uint32_t lowok = (X > 0 ? 1u : 0u) | (Y > 0 ? 2u : 0u) | (Z > 0 ? 4u : 0u);
             const VT vals = replay8<IdxT>(wd, pv, nbv, nbok, lowok, ipl + bpa + (exc & 1023u),
                                           compact_nibble_bits(pam), compact_nibble_bits(pdm), nib,
                                           seg - nib0 + bpd + ((exc >> 10) & 1023u), P, true, bad);
-            // child k = kx | ky << 1 | kz << 2 at voxel (2X + kx, 2Y + ky, 2Z + kz): x pairs
-            const uint32_t v0 = 2 * X + 64 * Y + 2048 * Z;
+            // x pairs of children
             if constexpr (sizeof(IdxT) == 1) {
                 *reinterpret_cast<uint16_t *>(D + v0) = (uint16_t)(vals.x & 0xFFFFu);
                 *reinterpret_cast<uint16_t *>(D + v0 + 32) = (uint16_t)(vals.x >> 16);
@@ -1096,24 +1162,50 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     if (__ballot(bad) && L == 0) atomicOr(&sm->err, 1);
     __syncthreads();
     if (sm->err) return false;
+    phase_mark(h.rq, 15);
+    // the listed references, each followed to its value (concurrent chases
+    // see a reference or its final value, both of which lead to the value)
+    bool resolved = false;
+    if constexpr (kList) {
+        const uint32_t nref = sm->nref;
+        if (nref <= ref_cap) {
+            for (uint32_t e = tid; e < nref; e += 64 * NW) {
+                const uint32_t v = refs[e];
+                D[v] = (IdxT)chase<IdxT>(D, v, D[v]);
+            }
+            __syncthreads();
+            resolved = true;
+        }
+    }
     phase_mark(h.rq, 4);
     // output: a wave writes 8 whole rows of a z slice per store; lane L
     // covers voxels 4 (L & 7) .. + 3 of rows (L >> 3) + 8c; references are
     // followed along the dense level (at most three links)
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
-    auto slices = [&](auto al16) {
+    auto slices = [&](auto al16, auto refs_left) {
         for (uint32_t zz = w; zz < 32; zz += NW) {
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const uint32_t v0 = 4 * (L & 7u) + 32 * ((L >> 3) + 8 * (uint32_t)c) + 1024 * zz;
                 uint32_t idx[4];
-                if constexpr (sizeof(IdxT) == 1) {
+                if constexpr (sizeof(IdxT) == 1 && !kG && !decltype(refs_left)::value) {
+                    // no references left: each byte is a palette index in LDS
+                    const uint32_t q = *reinterpret_cast<const uint32_t *>(D + v0);
+                    const uint8_t *pb = reinterpret_cast<const uint8_t *>(pal);
+                    uint4 o;
+                    o.x = *reinterpret_cast<const uint32_t *>(pb + byte_x4<0>(q));
+                    o.y = *reinterpret_cast<const uint32_t *>(pb + byte_x4<1>(q));
+                    o.z = *reinterpret_cast<const uint32_t *>(pb + byte_x4<2>(q));
+                    o.w = *reinterpret_cast<const uint32_t *>(pb + byte_x4<3>(q));
+                    store4<decltype(al16)::value>(dst + v0, o);
+                    continue;
+                } else if constexpr (sizeof(IdxT) == 1) {
                     const uint32_t q = *reinterpret_cast<const uint32_t *>(D + v0);
 #pragma unroll
                     for (int b = 0; b < 4; b++) idx[b] = (q >> (8 * b)) & 0xFFu;
                     // bytes >= 252: a reference (252 never survives the checks)
                     const uint32_t t = ~q & 0xFCFCFCFCu;
-                    if (((t - 0x01010101u) & ~t & 0x80808080u) != 0) {
+                    if (decltype(refs_left)::value && ((t - 0x01010101u) & ~t & 0x80808080u) != 0) {
 #pragma unroll
                         for (int b = 0; b < 4; b++)
                             if (idx[b] >= kMark) idx[b] = chase<IdxT>(D, v0 + (uint32_t)b, idx[b]);
@@ -1137,8 +1229,14 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
             }
         }
     };
-    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) slices(std::true_type{});
-    else slices(std::false_type{});
+    const bool al = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+    if (resolved) {
+        if (al) slices(std::true_type{}, std::false_type{});
+        else slices(std::false_type{}, std::false_type{});
+    } else {
+        if (al) slices(std::true_type{}, std::true_type{});
+        else slices(std::false_type{}, std::true_type{});
+    }
     phase_mark(h.rq, 5);
     return true;
 }
@@ -1146,7 +1244,8 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
 // kSlow false: bricks whose arrays fit the LDS arena, the others deferred
 // to the slow list; kSlow true: the slow list, on an arena in global memory
 template <int NW, bool kSlow>
-__global__ __launch_bounds__(64 * NW) void leaf_kernel(DecodeArgs a, LaunchB l) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ? 4 : 6))) void leaf_kernel(DecodeArgs a,
+                                                                                                      LaunchB l) {
     constexpr uint32_t NT = 64 * NW;
     extern __shared__ __align__(16) uint8_t smem[];
     SmallB *sm = reinterpret_cast<SmallB *>(smem);
@@ -1174,7 +1273,10 @@ __global__ __launch_bounds__(64 * NW) void leaf_kernel(DecodeArgs a, LaunchB l) 
         const uint4 meta = *reinterpret_cast<const uint4 *>(sbm + kSlotBm);
         const uint32_t E1 = uniform(meta.x), ipl = uniform(meta.y);
         const uint32_t E1c = E1 < 4096 ? E1 : 4096u;
-        if (tid == 0) sm->err = 0;
+        if (tid == 0) {
+            sm->err = 0;
+            sm->nref = 0;
+        }
         bool ok = true, done = true;
         if constexpr (!kSlow) {
             // nibbles from the delta segment of L_0 on, from a 16-byte boundary
@@ -1189,7 +1291,8 @@ __global__ __launch_bounds__(64 * NW) void leaf_kernel(DecodeArgs a, LaunchB l) 
                 ok = leaf_replay<uint8_t, false, NW>(h, E1, ipl, reinterpret_cast<const uint32_t *>(arena + fast.nib),
                                                      8 * nb0, slv, reinterpret_cast<const uint64_t *>(arena + fast.bm1),
                                                      reinterpret_cast<const uint32_t *>(arena + fast.pal), arena, fast,
-                                                     sm, dst);
+                                                     sm, dst, reinterpret_cast<uint16_t *>(arena + fast.total),
+                                                     min((l.arena_bytes - fast.total) / 2, l.ref_cap));
             } else if (l.slow_list) {  // the slow kernel takes it
                 done = false;
                 if (tid == 0) l.slow_list[atomicAdd(l.slow_count, 1u)] = rq;
@@ -1204,10 +1307,11 @@ __global__ __launch_bounds__(64 * NW) void leaf_kernel(DecodeArgs a, LaunchB l) 
                 ok = false;
             else if (h.P <= kPalFast)
                 ok = leaf_replay<uint8_t, true, NW>(h, E1, ipl, gnib, 0, slv, gbm, h.rec + hdr, gslot,
-                                                    make_layout_l(false, 0, 0, 4096, 1), sm, dst);
+                                                    make_layout_l(false, 0, 0, 4096, 1), sm, dst, nullptr, 0);
             else
                 ok = leaf_replay<uint16_t, true, NW>(h, E1, ipl, gnib, 0, reinterpret_cast<const uint16_t *>(slv), gbm,
-                                                     h.rec + hdr, gslot, make_layout_l(false, 0, 0, 4096, 2), sm, dst);
+                                                     h.rec + hdr, gslot, make_layout_l(false, 0, 0, 4096, 2), sm, dst,
+                                                     nullptr, 0);
         }
         __syncthreads();
         if (done && !ok) {
@@ -1438,6 +1542,18 @@ void launch_a(const DecodeArgs &a, const LaunchA &l, uint32_t grid, size_t lds, 
 // waves_a: front-kernel waves per workgroup; groups_b: leaf workgroups
 // per CU; fixed: buffers owned by the caller (a captured graph), else the
 // stream's own set
+// CSV_REF_LIST_CAP (a decimal count) bounds the leaf kernel's list of
+// same-level references; bricks with more chase them in the output loop.
+// The default is no bound beyond the LDS arena.  Read at every launch, so
+// that tests can exercise both paths in one process.
+uint32_t ref_list_cap() {
+    const char *e = std::getenv("CSV_REF_LIST_CAP");
+    if (!e || !*e) return 0xFFFFFFFFu;
+    char *end = nullptr;
+    const unsigned long v = std::strtoul(e, &end, 10);
+    return (end && *end == 0) ? (uint32_t)std::min<unsigned long>(v, 0xFFFFFFFFul) : 0xFFFFFFFFu;
+}
+
 int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
            uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
            bool lpt, LaunchBufs *fixed = nullptr) {
@@ -1500,6 +1616,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     lb.slot_dw = B->slot_dw;
     lb.scratch = pool->d_scratch;
     lb.scratch_bytes = kArenaBytes;
+    lb.ref_cap = ref_list_cap();
     const size_t lds_b = kSmallB + (size_t)lb.arena_bytes;
     // the global-arena variant runs only for pools with bricks that may not fit the LDS arena
     const bool slow = pool->any_big_palette || pool->max_fast_bytes > lb.arena_bytes;

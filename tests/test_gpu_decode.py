@@ -178,6 +178,22 @@ def test_config2_full_lod_one_launch(csvlib, orc, cfg2):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("cap", ["0", "1200", "1600", ""])
+def test_reference_list_bound(csvlib, orc, cfg2, cap, monkeypatch):
+    # the leaf kernel resolves same-level references from a list before the
+    # output, or chases them in the output loop for a brick whose list is
+    # longer than the bound: at bound 0 every brick chases, in between the
+    # cells bricks (about 1.5k references each) split, unbounded none does
+    vol, blob = cfg2
+    monkeypatch.setenv("CSV_REF_LIST_CAP", cap)
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    ids = np.arange(1, 4096, 2)
+    log("cfg2 reference list bound %r" % cap)
+    got = gpu_decode_uniform(pool, ids, 0)
+    np.testing.assert_array_equal(got, orc.decode_bricks(blob, ids, [0] * len(ids)))
+
+
 @pytest.mark.parametrize("lod", [1, 2, 3])
 def test_config2_lower_lods(csvlib, orc, cfg2, lod):
     vol, blob = cfg2
