@@ -92,8 +92,10 @@ def serving_leg(csv, synth, seconds):
             log("serving %s" % r)
             runs.append(r)
     worst = max(r["p99_us"] for r in runs)
+    # the stated configuration is the 16 GiB cache; the 2 GiB cache is a stress case
+    stated = max(r["p99_us"] for r in runs if r["cache_gib"] == 16)
     return {"workload": "2048x2048x1024 neurite (131,072 bricks, 80,000 labels), camera-path Poisson traces",
-            "p99_us_worst": worst, "runs": runs}
+            "p99_us_16gib_cache": stated, "p99_us_worst": worst, "runs": runs}
 
 
 def main():

@@ -549,7 +549,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
             const uint32_t tb = decltype(leaf_select)::value ? (i >= leaf ? lutn : 0u) : 0u;
             const uint32_t e = lut[tb + (x & mask)];
             const uint32_t sym = e & 15u;
-            x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
+            x = __umul24(e >> 20, x >> sbits) + ((e >> 8) & 0xFFFu);
             const bool need = x < csv::kRansLower;
             const uint64_t bal = __ballot(need);
             const uint32_t wd = ring[(cursor + mbcnt(bal)) & (kRingWords - 1)];
@@ -569,17 +569,16 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
                 const uint32_t i = ((s + (uint32_t)j) << 6) + L;
                 const uint32_t tb = decltype(leaf_select)::value ? (i >= leaf ? lutn : 0u) : 0u;
                 const uint32_t e = lut[tb + (x & mask)];
-                x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
+                x = __umul24(e >> 20, x >> sbits) + ((e >> 8) & 0xFFFu);
                 const bool need = x < csv::kRansLower;
                 const uint64_t bal = __ballot(need);
-                const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, cursor & (kRingWords - 1)));
-                uint32_t wd = ring[pos];
+                // the wave's ring position is uniform: one scalar base plus each lane's rank
+                uint32_t wd = (ring + (cursor & (kRingWords - 1)))[mbcnt(bal)];
                 // every lane reads (the read is not worth a branch on the critical path)
                 __asm__ volatile("" : "+v"(wd));
                 x = need ? ((x << 16) | wd) : x;
                 cursor += (uint32_t)__popcll(bal);
-                sb[64 * j + L] = (uint8_t)(e & 15u);
+                sb[64 * j + L] = (uint8_t)e;  // the symbol (bits 4..7 of an entry are zero)
                 if (cursor >= ring_lo + 512) refill();
             }
             wsync();
@@ -605,7 +604,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
         if (act) {
             const uint32_t e = lut[(i >= leaf ? lutn : 0u) + (x & mask)];
             sym = e & 15u;
-            x = __umul24(e >> 16, x >> sbits) + ((e >> 4) & 0xFFFu);
+            x = __umul24(e >> 20, x >> sbits) + ((e >> 8) & 0xFFFu);
             need = x < csv::kRansLower;
         }
         const uint64_t bal = __ballot(need);
@@ -662,10 +661,26 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
         uint16_t *clist = lst + kLstOff[m];
         const uint32_t list_cap = 1u << (3 * (kLog2 - m));
         // children of parents that are not expanded inherit the parent's index
-        for (uint32_t q = L; q < np; q += 64) {
-            const bool ex = pbm ? ((pbm[q >> 3] >> (q & 7)) & 1u) : true;
-            cbm[q] = 0;
-            if (!ex) *reinterpret_cast<VT *>(cur + 8 * q) = V::splat(up ? (uint32_t)up[q] : 0u);
+        if (sizeof(IdxT) == 1 && !kG && up) {
+            // u8 levels in LDS: a lane takes 8 parents and writes the children
+            // of all of them (the expanded ones are overwritten below)
+            for (uint32_t g = L; g < np / 8; g += 64) {
+                const uint2 u = *reinterpret_cast<const uint2 *>(up + 8 * g);
+                *reinterpret_cast<uint2 *>(cbm + 8 * g) = make_uint2(0u, 0u);
+                uint4 *o = reinterpret_cast<uint4 *>(cur + 64 * g);
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    const uint32_t a = __builtin_amdgcn_perm(u.y, u.x, 0x01010101u * (uint32_t)j);
+                    const uint32_t b = __builtin_amdgcn_perm(u.y, u.x, 0x01010101u * (uint32_t)(j + 1));
+                    o[j / 2] = make_uint4(a, a, b, b);
+                }
+            }
+        } else {
+            for (uint32_t q = L; q < np; q += 64) {
+                const bool ex = pbm ? ((pbm[q >> 3] >> (q & 7)) & 1u) : true;
+                cbm[q] = 0;
+                if (!ex) *reinterpret_cast<VT *>(cur + 8 * q) = V::splat(up ? (uint32_t)up[q] : 0u);
+            }
         }
         wave_sync<kG>();
         const uint32_t seg = (m == kLog2 - 1) ? 0u : h.c((uint32_t)m + 1), seg_end = h.c((uint32_t)m);
@@ -857,7 +872,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     if (kLutLds)
         for (uint32_t e = threadIdx.x; e < l.lut_lds_words; e += blockDim.x) slut[e] = a.luts[e];
     __syncthreads();
-    const uint32_t L = lane(), wave = threadIdx.x >> 6;
+    const uint32_t L = lane(), wave = uniform(threadIdx.x >> 6);
     uint8_t *wl = smem + align16(4 * l.lut_lds_words) + wave * kWaveLds;
     const uint32_t wid = blockIdx.x * WPG + wave;
     for (uint32_t k = 0;; k++) {

@@ -44,8 +44,9 @@ constexpr uint64_t record_area_offset(uint64_t n_bricks) { return (kHeaderBytes 
 // u32 words before the palette in a record
 constexpr uint32_t record_header_words(int N) { return 3u + (uint32_t)N; }
 
-// Decode-table entry for one slot of a table with precision scale_bits:
-// bits 0..3 symbol, bits 4..15 slot - cumulative start, bits 16..28 frequency.
-constexpr uint32_t lut_entry(uint32_t sym, uint32_t bias, uint32_t freq) { return sym | (bias << 4) | (freq << 16); }
+// Decode-table entry for one slot of a table with precision scale_bits
+// (at most 11): bits 0..3 symbol, bits 4..7 zero (the low byte is the
+// symbol), bits 8..19 slot - cumulative start, bits 20..31 frequency.
+constexpr uint32_t lut_entry(uint32_t sym, uint32_t bias, uint32_t freq) { return sym | (bias << 8) | (freq << 20); }
 
 }  // namespace csv
