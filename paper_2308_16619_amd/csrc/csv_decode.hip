@@ -358,6 +358,18 @@ __host__ __device__ constexpr uint32_t child_selectors(int k) {
     return 4u | ((k & 1 ? 5u : 0u) << 4) | ((k & 2 ? 6u : 1u) << 8) | ((k & 4 ? 7u : 2u) << 12) | (12u << 16) |
            (12u << 20) | (12u << 24) | (12u << 28);
 }
+// the child replay builds these selectors as a table lookup by operation
+// plus 5 where the child's bit on the operation's axis is set
+constexpr bool selectors_match() {
+    for (int k = 0; k < 8; k++)
+        for (int o = 0; o < 8; o++) {
+            const uint32_t base = o == 0 ? 4u : (o <= 3 ? (uint32_t)(o - 1) : 12u);
+            const uint32_t plus = (o >= 1 && o <= 3 && ((k >> (o - 1)) & 1)) ? 5u : 0u;
+            if (((child_selectors(k) >> (4 * o)) & 15u) != base + plus) return false;
+        }
+    return true;
+}
+static_assert(selectors_match(), "child selector tables");
 
 // replay_children for u8 indices, all 8 children at once in two dwords:
 // each child's copy or reference is one byte select (v_perm_b32) out of
@@ -373,14 +385,21 @@ __device__ __forceinline__ uint2 replay_children_u8(uint32_t w, uint32_t pv, con
                              (((lowok & 4u) ? 255u : kInv) << 16) | (kInv << 24);
     const uint32_t cand_hi = pv | (((nbok & 1u) ? nb[0] : kInv) << 8) | (((nbok & 2u) ? nb[1] : kInv) << 16) |
                              (((nbok & 4u) ? nb[2] : kInv) << 24);
-    uint32_t sel_lo = 0, sel_hi = 0;
-#pragma unroll
-    for (int k = 0; k < 8; k++) {
-        const uint32_t o4 = ((w >> (4 * k)) & 7u) << 2;
-        const uint32_t sk = (child_selectors(k) >> o4) & 15u;
-        if (k < 4) sel_lo |= sk << (8 * k);
-        else sel_hi |= sk << (8 * (k - 4));
-    }
+    // selector bytes child_selectors(k)[op_k], built for the even children
+    // (0, 2, 4, 6) and the odd ones (1, 3, 5, 7) as byte vectors: a table
+    // lookup by operation (R_p 4, R_x 0, R_y 1, R_z 2, P 12), plus 5 where
+    // the child's k bit on the operation's axis is 1 (then its neighbour on
+    // that axis is the parent-level one)
+    const uint32_t ye = w & 0x07070707u, yo = (w >> 4) & 0x07070707u;
+    const uint32_t be = __builtin_amdgcn_perm(0x0C0C0C0Cu, 0x02010004u, ye);
+    const uint32_t bo = __builtin_amdgcn_perm(0x0C0C0C0Cu, 0x02010004u, yo);
+    const uint32_t f2e = __builtin_amdgcn_perm(0u, 0x00050000u, ye), f3e = __builtin_amdgcn_perm(0u, 0x05000000u, ye);
+    const uint32_t f1o = __builtin_amdgcn_perm(0u, 0x00000500u, yo), f2o = __builtin_amdgcn_perm(0u, 0x00050000u, yo),
+                   f3o = __builtin_amdgcn_perm(0u, 0x05000000u, yo);
+    const uint32_t se = be + ((f2e & 0xFF00FF00u) | (f3e & 0xFFFF0000u));          // ky at 2, 6; kz at 4, 6
+    const uint32_t so = bo + (f1o | (f2o & 0xFF00FF00u) | (f3o & 0xFFFF0000u));    // kx at all; ky at 3, 7; kz at 5, 7
+    const uint32_t sel_lo = __builtin_amdgcn_perm(so, se, 0x05010400u);            // children 0, 1, 2, 3
+    const uint32_t sel_hi = __builtin_amdgcn_perm(so, se, 0x07030602u);            // children 4, 5, 6, 7
     uint32_t lo = __builtin_amdgcn_perm(cand_hi, cand_lo, sel_lo);
     uint32_t hi = __builtin_amdgcn_perm(cand_hi, cand_lo, sel_hi);
     const uint32_t y = w & 0x77777777u;
