@@ -511,7 +511,7 @@ __device__ __forceinline__ void wave_sync() {
 // 2 KB of LDS.  False on a malformed stream.
 template <bool kLutLds>
 __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h, const uint32_t *slut,
-                                               uint32_t *ring32, uint32_t *out, uint32_t n) {
+                                               uint32_t *ring32, uint32_t *out, uint32_t *lcopy, uint32_t n) {
     const uint32_t L = lane();
     const uint32_t hdr = csv::record_header_words(kLog2);
     const uint16_t *ring = reinterpret_cast<const uint16_t *>(ring32);
@@ -575,7 +575,10 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
             x = need ? ((x << 16) | wd) : x;
             cursor += (uint32_t)__popcll(bal);
             const uint32_t g = row_or<3>(sym << (4 * (L & 7u)));
-            if ((L & 7u) == 7u) out[(i - 7) >> 3] = g;
+            if ((L & 7u) == 7u) {
+                out[(i - 7) >> 3] = g;
+                if (((i - 7) >> 3) < kWDeltaDw) lcopy[(i - 7) >> 3] = g;
+            }
             if (cursor >= ring_lo + 512) refill();
         };
         // blocks of 8 steps: each lane writes its symbol as a byte to LDS
@@ -603,7 +606,9 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
             wsync();
             const uint2 b = *reinterpret_cast<const uint2 *>(sb + 8 * L);
             const uint32_t lo = (b.x | (b.x >> 4)) & 0x00FF00FFu, hi = (b.y | (b.y >> 4)) & 0x00FF00FFu;
-            out[(s << 3) + L] = ((lo | (lo >> 8)) & 0xFFFFu) | (((hi | (hi >> 8)) & 0xFFFFu) << 16);
+            const uint32_t packed = ((lo | (lo >> 8)) & 0xFFFFu) | (((hi | (hi >> 8)) & 0xFFFFu) << 16);
+            out[(s << 3) + L] = packed;
+            if ((s << 3) + L < kWDeltaDw) lcopy[(s << 3) + L] = packed;
             wsync();
             s += 8;
         };
@@ -638,12 +643,18 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
         const uint32_t v = sym << (4 * (i & 7));
         if (W >= 8) {
             const uint32_t g = row_or<3>(v);
-            if ((L & 7) == 7 && L < W && i - 7 < n) out[(i - 7) >> 3] = g;
+            if ((L & 7) == 7 && L < W && i - 7 < n) {
+                out[(i - 7) >> 3] = g;
+                if (((i - 7) >> 3) < kWDeltaDw) lcopy[(i - 7) >> 3] = g;
+            }
         } else {
             const uint32_t g = W == 4 ? row_or<2>(v) : (W == 2 ? row_or<1>(v) : v);
             acc |= g;
             const bool full = (((s + 1) << lw) & 7) == 0;
-            if (L == W - 1 && (full || s + 1 == steps)) out[(s << lw) >> 3] = acc;
+            if (L == W - 1 && (full || s + 1 == steps)) {
+                out[(s << lw) >> 3] = acc;
+                if (((s << lw) >> 3) < kWDeltaDw) lcopy[(s << lw) >> 3] = acc;
+            }
             if (full) acc = 0;
         }
         if (cursor >= ring_lo + 512) refill();
@@ -706,9 +717,11 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
         if ((uint64_t)seg + 8ull * E > seg_end) return false;
         const uint32_t D = seg_end - seg - 8 * E, ops0 = seg + D;  // deltas precede the operations
         const uint32_t pmask0 = axis_mask(0, Bp), pmask1 = axis_mask(1, Bp), pmask2 = axis_mask(2, Bp);
-        // the level's nibbles (deltas, then operations) in LDS when they fit:
-        // one round trip to global memory per level instead of one per 64
-        // nodes.  src holds the nibbles from position off on.
+        // the level's nibbles (deltas, then operations) from LDS: the copy of
+        // the stream's first kWDeltaDw dwords that the entropy decoder wrote,
+        // else the level's segment staged (one round trip to global memory
+        // per level instead of one per 64 nodes), else global memory.  src
+        // holds the nibbles from position off on.
         uint32_t bpa = 0, bpd = 0, bex = 0;
         bool bad = false;
         auto run = [&](const uint32_t *src, uint32_t off) __attribute__((always_inline)) {
@@ -755,7 +768,10 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
         };
         const uint32_t s0 = seg >> 3, sn = ((seg_end + 7) >> 3) - s0 + 1;
         if (m == 1) phase_mark(h.rq, 13);
-        if (sn <= kWDeltaDw) {
+        if (((seg_end + 7) >> 3) < kWDeltaDw) {
+            // every nibble up to this level's end is in the entropy decoder's copy
+            run(dstage, 0);
+        } else if (sn <= kWDeltaDw) {
             for (uint32_t e = L; e < sn; e += 64) dstage[e] = nib[s0 + e];
             wsync();
             run(dstage, 8 * s0);
@@ -927,7 +943,10 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             fill_labels<64>(dst, count, 0u, L);
             continue;
         }
-        bool ok = entropy_decode<kLutLds>(a, h, slut, reinterpret_cast<uint32_t *>(wl), nib, n);
+        // the packed nibbles go to the slot, and their first kWDeltaDw dwords
+        // also to the wave's staging area (the upper levels read them there)
+        bool ok = entropy_decode<kLutLds>(a, h, slut, reinterpret_cast<uint32_t *>(wl),
+                                          nib, reinterpret_cast<uint32_t *>(wl + kWPal), n);
         phase_mark(rq, 1);
         // this wave's nibble stores before its own loads of them
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
