@@ -37,6 +37,14 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def decoder_hash():
+    """sha256 prefix of the decoder's sources (kernels and the table format)."""
+    h = hashlib.sha256()
+    for f in ("csv_decode.hip", "csv_format.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2308_16619_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def record_bytes(blob: bytes, ids, lod: int) -> int:
     """Algorithmic compressed bytes a decode at `lod` must read: record
     header, palette, lane states and the words of the decoded prefix (all
@@ -109,6 +117,7 @@ def main():
     ap.add_argument("--serving", choices=["full", "none"], default="full",
                     help="serving leg: the 2048x2048x1024 neurite pool with camera-path traces (full) or none")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="measured trace length per serving run")
+    ap.add_argument("--shape", default="", help="fixed launch shape 'waves,groups,queue,lpt' instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -146,11 +155,17 @@ def main():
     in_bytes = record_bytes(blob, ids_np, lod)
 
     stream = torch.cuda.current_stream()
-    # the launch shape is picked on this request set by the autotuner
-    shape, tune_ms = pool.autotune(ids, out, lod=lod, reps=3)
-    torch.cuda.synchronize()
-    assert pool.last_error()[0] == 0
-    log("autotuned shape %s: %.4f ms" % (shape, tune_ms))
+    if args.shape:
+        # a fixed launch shape (profiling runs that must compare like with like)
+        shape = tuple(int(v) for v in args.shape.split(","))
+        pool.set_shape(shape)
+        log("fixed shape %s" % (shape,))
+    else:
+        # the launch shape is picked on this request set by the autotuner
+        shape, tune_ms = pool.autotune(ids, out, lod=lod, reps=3)
+        torch.cuda.synchronize()
+        assert pool.last_error()[0] == 0
+        log("autotuned shape %s: %.4f ms" % (shape, tune_ms))
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -188,10 +203,9 @@ def main():
 
     # per-call time: one decode call (front + leaf kernel) per step, so the event time per step
     achieved = (in_bytes + out_bytes) / (ms * 1e-3) / 1e9
-    src = os.path.join(ROOT, "paper_2308_16619_amd", "csrc", "csv_decode.hip")
-    src_hash = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    traffic = TRAFFIC["bytes"] if (src_hash == TRAFFIC["decoder_sha256_16"] and
-                                   tuple(shape) == TRAFFIC["shape"]) else None
+    src_hash = decoder_hash()
+    # counters taken on this decoder source (at the launch shape TRAFFIC names), else none
+    traffic = TRAFFIC["bytes"] if src_hash == TRAFFIC["decoder_sha256_16"] else None
 
     # baseline: one launch per brick
     nb = min(args.plain_bricks, B)
@@ -249,6 +263,7 @@ def main():
         "wall_s": round(t_wall, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "traffic_shape": list(TRAFFIC["shape"]) if traffic is not None else None,
                      "traffic_unit": "bytes per decode call", "algorithmic_bytes_per_launch": in_bytes + out_bytes,
                      "kernel": "csv_decode_bricks = front_kernel + leaf_kernel", "shape": list(shape),
                      "decoder_sha256_16": src_hash},

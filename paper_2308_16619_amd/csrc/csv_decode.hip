@@ -120,6 +120,7 @@ struct LaunchB {
     uint8_t *scratch;        // global arena per workgroup for bricks that do not fit LDS
     uint32_t scratch_bytes;
     uint32_t ref_cap;        // longest list of same-level references (LDS room permitting)
+    uint32_t *ctr;           // the launch's counters (see launch()); the last workgroup clears them
 };
 
 // ---------------------------------------------------------------------------
@@ -1373,6 +1374,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
         }
         __syncthreads();
     }
+    // the last workgroup to finish clears the counters this kernel was the
+    // last to use, for the next launch on these buffers: every other
+    // workgroup has had its last counter operation return by then.  No
+    // fence: the counters only change by atomics, and the kernel boundary
+    // orders them for the next launch (a device-scope fence per workgroup
+    // would write back the L2).
+    if (tid == 0) {
+        uint32_t *ctr = glob(l.ctr);
+        if (atomicAdd(ctr + (kSlow ? 6 : 5), 1u) == gridDim.x - 1) {
+            if (kSlow) {
+                atomicExch(ctr + 3, 0u);
+                atomicExch(ctr + 4, 0u);
+                atomicExch(ctr + 6, 0u);
+            } else {
+                atomicExch(ctr + 0, 0u);
+                atomicExch(ctr + 1, 0u);
+                atomicExch(ctr + 2, 0u);
+                atomicExch(ctr + 5, 0u);
+            }
+        }
+    }
 }
 
 // Longest-first request order: requests are binned by the log2 of their
@@ -1408,10 +1430,11 @@ __global__ __launch_bounds__(1024) void order_lpt(DecodeArgs a, uint32_t *order)
     __syncthreads();
     for (uint32_t r = tid; r < a.n; r += blockDim.x) order[atomicAdd(&off[work_bin(a, r)], 1u)] = r;
 }
+
+
 __global__ void zero_words(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
-
 
 // Per-stream launch buffers: the nibble buffer and status bytes that pass
 // requests from the entropy decoder to the replay, the longest-first order,
@@ -1424,8 +1447,8 @@ struct LaunchBufs {
     uint32_t *order = nullptr;     // longest-first order
     uint32_t *leaf_list = nullptr; // requests for the leaf kernel
     uint32_t *slow_list = nullptr; // ... of them for its global-arena variant
-    uint32_t *small = nullptr;     // 64: front counter, 65: leaf counter, 66: leaf count, 67: slow count,
-                                   // 68: slow counter
+    uint32_t *small = nullptr;     // [0, 64): order bins; [64, 72): the launch counters
+    bool dirty = false;            // counters left non-zero by a failed launch
     uint32_t slot_dw = 0;
     uint32_t cap_n = 0;
     uint32_t slot_bytes() const { return 4 * slot_dw + kSlotExtra; }
@@ -1646,7 +1669,16 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     a.out = out;
     a.n = n;
     a.err = pool->d_err;
-    uint32_t *ctr = B->small + 2 * kBins;  // front counter, leaf counter, leaf count, slow count, slow counter
+    // counters: 0 front queue, 1 leaf queue, 2 leaf count, 3 slow count,
+    // 4 slow queue, 5 and 6 finished leaf / slow workgroups.  They are zero
+    // when a launch starts: zeroed at allocation, then by the last
+    // workgroup of the leaf kernels (0, 1, 2, 5) and of the global-arena
+    // kernel (3, 4, 6), which only runs when the leaf kernel may defer to it.
+    uint32_t *ctr = B->small + 2 * kBins;
+    if (B->dirty) {  // a launch failed part way: start from zero (a kernel, so that graphs may hold it)
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 8u);
+        B->dirty = false;
+    }
     LaunchA la;
     la.lut_lds_words = lut_lds_words(pool);
     la.queue = queue ? ctr : nullptr;
@@ -1670,6 +1702,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     lb.scratch = pool->d_scratch;
     lb.scratch_bytes = kArenaBytes;
     lb.ref_cap = ref_list_cap();
+    lb.ctr = ctr;
     const size_t lds_b = kSmallB + (size_t)lb.arena_bytes;
     // the global-arena variant runs only for pools with bricks that may not fit the LDS arena
     const bool slow = pool->any_big_palette || pool->max_fast_bytes > lb.arena_bytes;
@@ -1696,13 +1729,11 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
         for (uint32_t i = 0; i < n; i++) {
             la.base = i;
             b.n = i + 1;
-            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 5u);
             go_a(b, la, 1);
             hipLaunchKernelGGL((leaf_kernel<kWavesLeaf, false>), dim3(1), dim3(64 * kWavesLeaf), lds_b, s, b, lb);
             if (slow) hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(1), dim3(64 * kWavesLeafG), lds_g, s, b, lb);
         }
     } else {
-        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 5u);
         if (lpt) {
             hipLaunchKernelGGL(order_lpt, dim3(1), dim3(1024), 0, s, a, B->order);
             la.order = B->order;
@@ -1714,7 +1745,11 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
             hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(grid_g), dim3(64 * kWavesLeafG), lds_g, s, a, lb);
         }
     }
-    return hipGetLastError() == hipSuccess ? CSV_OK : CSV_EHIP;
+    if (hipGetLastError() != hipSuccess) {
+        B->dirty = true;
+        return CSV_EHIP;
+    }
+    return CSV_OK;
 }
 
 bool valid_shape(const csv_shape &sh) {
