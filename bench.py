@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
 # counters read for a plain 256 MiB device copy; see
 # profiles/decode_cells512_hbm_traffic.md.  Valid only for the decoder source
-# and launch shape the counters were taken with.
-TRAFFIC = {"decoder_sha256_16": "0bad906bca505b3f", "shape": (16, 3, 1, 0), "bytes": 657029837}
+# the counters were taken on (at the launch shape named here).
+TRAFFIC = {"decoder_sha256_16": "dc656aa2e8847871", "shape": (16, 3, 0, 0), "bytes": 653972940}
 
 
 def log(msg):
