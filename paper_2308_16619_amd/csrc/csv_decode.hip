@@ -788,7 +788,58 @@ __device__ __forceinline__ bool upper_replay(const Hdr &h, const uint32_t *nib, 
         // while other lanes resolve in place (a reader sees the reference or
         // its final value, and both lead to the same value).  The chains of
         // a node's children are followed together, one link each per round.
-        for (uint32_t r = L; r < E; r += 64) {
+        // At level 1 (u8, in LDS) the staging area is free by now: the
+        // children that hold references are listed there first, and each
+        // is then followed by a lane of its own.
+        bool listed = false;
+        if constexpr (sizeof(IdxT) == 1 && !kG) {
+            if (m == 1) {
+                uint16_t *refs = reinterpret_cast<uint16_t *>(dstage);
+                constexpr uint32_t kCap = 2 * kWDeltaDw;
+                uint32_t nref = 0;
+                for (uint32_t c = 0; c < (E + 63) / 64; c++) {
+                    const uint32_t r = 64 * c + L;
+                    const bool act = r < E;
+                    const uint32_t q = (act && plist) ? (uint32_t)plist[r] : 0u;
+                    const uint2 vv = act ? *reinterpret_cast<const uint2 *>(cur + 8 * q) : make_uint2(0u, 0u);
+                    // bytes >= 253 (252 has been rejected): bit 7 of each such byte
+                    const uint32_t tl = ~vv.x & 0xFCFCFCFCu, th = ~vv.y & 0xFCFCFCFCu;
+                    uint32_t fl = (tl - 0x01010101u) & ~tl & 0x80808080u;
+                    uint32_t fh = (th - 0x01010101u) & ~th & 0x80808080u;
+                    const uint32_t cnt = (uint32_t)__builtin_popcount(fl) + (uint32_t)__builtin_popcount(fh);
+                    const uint32_t inc = wave_incl_scan(cnt);
+                    const uint32_t tot = uniform(__builtin_amdgcn_readlane(inc, 63));
+                    if (nref + tot <= kCap) {
+                        uint32_t pos = nref + inc - cnt;
+                        while (fl) {
+                            refs[pos++] = (uint16_t)(8 * q + ((uint32_t)__builtin_ctz(fl) >> 3));
+                            fl &= fl - 1u;
+                        }
+                        while (fh) {
+                            refs[pos++] = (uint16_t)(8 * q + 4 + ((uint32_t)__builtin_ctz(fh) >> 3));
+                            fh &= fh - 1u;
+                        }
+                    }
+                    nref += tot;
+                }
+                if (nref <= kCap) {
+                    wsync();
+                    for (uint32_t e = L; e < nref; e += 64) {
+                        const uint32_t off = refs[e];
+                        uint32_t qq = off >> 3, kk = off & 7u, v = cur[off];
+                        while (v >= kMark) {
+                            const uint32_t a = v - kMark;
+                            qq = morton_dec(qq, pmask0 << a);
+                            kk |= 1u << a;
+                            v = cur[8 * qq + kk];
+                        }
+                        cur[off] = (IdxT)v;
+                    }
+                    listed = true;
+                }
+            }
+        }
+        for (uint32_t r = L; !listed && r < E; r += 64) {
             const uint32_t q = plist ? (uint32_t)plist[r] : 0u;
             VT vals = *reinterpret_cast<const VT *>(cur + 8 * q);
             uint32_t v[7], qq[7], kk[7];
