@@ -239,6 +239,24 @@ __device__ __forceinline__ const uint32_t *rec_at(uint64_t a) {
     return (const uint32_t *)(const __attribute__((address_space(1))) uint32_t *)a;
 }
 
+// Uniform loads of data that no kernel of the launch writes, through the
+// scalar cache: they count on lgkmcnt, so waiting for them does not wait for
+// the wave's outstanding stores (on gfx9 vmcnt counts stores too).  p must be
+// wave-uniform.  Sub-dword fields are read from their (4-byte aligned)
+// dword, which lies in the same allocation.
+template <class T>
+__device__ __forceinline__ T ld_s(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+__device__ __forceinline__ uint32_t ld_s_u8(const uint8_t *p) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    return (ld_s(reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3)) >> (8 * (a & 3))) & 0xFFu;
+}
+__device__ __forceinline__ uint32_t ld_s_u16(const uint16_t *p) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    return (ld_s(reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3)) >> (8 * (a & 2))) & 0xFFFFu;
+}
+
 // ---------------------------------------------------------------------------
 // record header
 // ---------------------------------------------------------------------------
@@ -258,27 +276,27 @@ enum ReqKind { kReqBadLod, kReqBadId, kReqCorrupt, kReqFill, kReqDecode };
 __device__ __forceinline__ ReqKind load_request(const DecodeArgs &a, uint32_t rq, Hdr &h, uint32_t *&dst,
                                                 uint32_t &count, uint32_t &fill) {
     h.rq = rq;
-    h.id = uniform(a.ids[rq]);
-    h.t = uniform(a.lods ? (uint32_t)a.lods[rq] : a.lod_scalar);
+    h.id = ld_s(a.ids + rq);
+    h.t = a.lods ? ld_s_u8(a.lods + rq) : a.lod_scalar;
     dst = nullptr;
     count = 0;
     fill = 0;
     if (h.t > (uint32_t)kLog2) return kReqBadLod;
     const uint32_t G = 32u >> h.t;
     count = G * G * G;
-    dst = a.out + (a.out_off ? a.out_off[rq] : (uint64_t)rq * count);
+    dst = a.out + (a.out_off ? ld_s(a.out_off + rq) : (uint64_t)rq * count);
     if (h.id >= a.n_bricks) return kReqBadId;
-    h.rec = rec_at(a.rec_ptr[h.id]);
-    const uint32_t size = a.rec_size[h.id];
-    h.vol = a.rec_vol[h.id];
-    h.P = h.rec[0];
-    h.W = h.rec[1];
-    h.nw = h.rec[2];
-    h.c0 = h.rec[3];
-    h.c1 = h.rec[4];
-    h.c2 = h.rec[5];
-    h.c3 = h.rec[6];
-    h.c4 = h.rec[7];
+    h.rec = rec_at(ld_s(a.rec_ptr + h.id));
+    const uint32_t size = ld_s(a.rec_size + h.id);
+    h.vol = ld_s_u16(a.rec_vol + h.id);
+    h.P = ld_s(h.rec + 0);
+    h.W = ld_s(h.rec + 1);
+    h.nw = ld_s(h.rec + 2);
+    h.c0 = ld_s(h.rec + 3);
+    h.c1 = ld_s(h.rec + 4);
+    h.c2 = ld_s(h.rec + 5);
+    h.c3 = ld_s(h.rec + 6);
+    h.c4 = ld_s(h.rec + 7);
     const uint32_t hdr = csv::record_header_words(kLog2);
     bool ok = h.P >= 1 && h.W <= 64 && (h.W & (h.W - 1)) == 0 && ((h.c0 > 0) == (h.W > 0)) && h.c0 <= kMaxSym &&
               (uint64_t)4 * (hdr + h.P + h.W) + 2ull * h.nw <= size;
@@ -286,7 +304,7 @@ __device__ __forceinline__ ReqKind load_request(const DecodeArgs &a, uint32_t rq
     if (ok) ok = (h.c0 == 0) ? (h.P == 1) : (h.P >= 2);
     if (!ok) return kReqCorrupt;
     if (h.t == (uint32_t)kLog2 || h.c0 == 0) {  // coarsest level or uniform brick: palette[0]
-        fill = h.rec[hdr];
+        fill = ld_s(h.rec + hdr);
         return kReqFill;
     }
     return kReqDecode;
@@ -516,8 +534,8 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
     const uint32_t L = lane();
     const uint32_t hdr = csv::record_header_words(kLog2);
     const uint16_t *ring = reinterpret_cast<const uint16_t *>(ring32);
-    const uint32_t sbits = a.vol_bits[h.vol], lutn = 1u << sbits, mask = lutn - 1u;
-    const uint32_t *lut = (kLutLds ? slut : glob(a.luts)) + a.lut_off[h.vol];
+    const uint32_t sbits = ld_s(a.vol_bits + h.vol), lutn = 1u << sbits, mask = lutn - 1u;
+    const uint32_t *lut = (kLutLds ? slut : glob(a.luts)) + ld_s(a.lut_off + h.vol);
     const uint32_t W = h.W, lw = 31u - (uint32_t)__builtin_clz(W), leaf = h.c1;
     const uint32_t *wg = h.rec + hdr + h.P + W;
     const uint32_t ndw = (h.nw + 1) / 2;  // word dwords in the record (the last one padded)
@@ -972,7 +990,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             req = l.base + wid + k * gridDim.x * WPG;
         }
         if (req >= a.n) break;
-        const uint32_t rq = l.order ? l.order[req] : req;
+        const uint32_t rq = l.order ? ld_s(l.order + req) : req;
         phase_mark(rq, 0);
         Hdr h;
         uint32_t *dst, count, fill;
@@ -1136,6 +1154,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
         bpre[L] = (uint16_t)(wave_incl_scan(c) - c);
     }
     __syncthreads();
+    phase_mark(h.rq, 8);
     // every voxel takes its L_1 node's value (expanded nodes are overwritten
     // below); pass 1: this wave's P_a and P_delta totals
     for (uint32_t e = tid; e < 2048; e += (64 * NW)) {  // half rows of 16 voxels
@@ -1364,9 +1383,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
     for (uint32_t k = 0;; k++) {
         if (tid == 0) sm->req = queue ? atomicAdd(queue, 1u) : blockIdx.x + k * gridDim.x;
         __syncthreads();
-        const uint32_t item = sm->req;
+        const uint32_t item = uniform(sm->req);
         if (item >= n_items) break;
-        const uint32_t rq = list[item];
+        const uint32_t rq = ld_s(list + item);
         Hdr h;
         uint32_t *dst, count, fill;
         (void)load_request(a, rq, h, dst, count, fill);  // a decode at t = 0: checked by the front kernel
@@ -1375,8 +1394,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
         const uint32_t *gnib = reinterpret_cast<const uint32_t *>(slot);
         const uint8_t *slv = slot + 4 * l.slot_dw;
         const uint8_t *sbm = slv + kSlotLv;
-        const uint4 meta = *reinterpret_cast<const uint4 *>(sbm + kSlotBm);
-        const uint32_t E1 = uniform(meta.x), ipl = uniform(meta.y);
+        const uint32_t *meta = rec_at(reinterpret_cast<uintptr_t>(l.slots) + (size_t)rq * l.slot_bytes +
+                                      4 * l.slot_dw + kSlotLv + kSlotBm);
+        const uint32_t E1 = ld_s(meta), ipl = ld_s(meta + 1);
         const uint32_t E1c = E1 < 4096 ? E1 : 4096u;
         if (tid == 0) {
             sm->err = 0;
