@@ -207,6 +207,30 @@ def main():
     # counters taken on this decoder source (at the launch shape TRAFFIC names), else none
     traffic = TRAFFIC["bytes"] if src_hash == TRAFFIC["decoder_sha256_16"] else None
 
+    # empty-space test (Sec. 4) of the same requests under a transfer
+    # function that shows a seeded 1 in 200 of the labels (a brick holds
+    # about 100, so the test splits the bricks)
+    n_lab = int(vol.max()) + 1
+    show = np.random.default_rng(11).random(n_lab) < 0.005
+    words = np.zeros((n_lab + 31) // 32, np.uint32)
+    nzl = np.nonzero(show)[0].astype(np.uint64)
+    np.bitwise_or.at(words, (nzl >> 5).astype(np.int64), (np.uint64(1) << (nzl & np.uint64(31))).astype(np.uint32))
+    d_words = torch.from_numpy(words.view(np.int32)).to(dev)
+    vmask = torch.empty(B, dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        pool.visible(ids, d_words, n_lab, out=vmask)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(20):
+        pool.visible(ids, d_words, n_lab, out=vmask)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    vis_us = ev0.elapsed_time(ev1) / 20 * 1e3
+    assert pool.last_error()[0] == 0
+    visibility = {"bricks": B, "us_per_call": round(vis_us, 2), "bricks_per_s": round(B / (vis_us * 1e-6), 1),
+                  "visible_frac": round(float(vmask.float().mean().item()), 4),
+                  "transfer_function": "a seeded 1 in 200 of the %d labels visible" % n_lab}
+
     # baseline: one launch per brick
     nb = min(args.plain_bricks, B)
     pids = ids[:nb].contiguous()
@@ -268,6 +292,7 @@ def main():
                      "kernel": "csv_decode_bricks = front_kernel + leaf_kernel", "shape": list(shape),
                      "decoder_sha256_16": src_hash},
         "plain_per_brick_launch": {"value": round(plain_gbs, 3), "unit": "GB/s", "bricks": nb},
+        "visibility_test": visibility,
         "cpu_baseline": cpu,
         "serving": serving,
     }

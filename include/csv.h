@@ -136,10 +136,13 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
  *   out          device, uint32 destination of the decoded blocks
  * Decodes every brick bit-exactly: the result is level L_lod of the brick's
  * resolution pyramid.  Two persistent launches that take requests from
- * device work counters: an entropy decoder (a wavefront per brick, many per
- * compute unit; Sec. 3.3) that leaves each brick's symbols as packed
- * nibbles in a pool buffer, then the replay (a 4-wavefront workgroup per
- * brick; Sec. 3.2, Alg. 1) that writes the level-of-detail block.
+ * device work counters (or by static round robin, per the launch shape): an
+ * entropy decoder that also replays levels 4..max(lod, 1) (a wavefront per
+ * brick, many per compute unit; Sec. 3.3, Sec. 3.2) and leaves level 1 and
+ * the leaf-level symbols of each full-LOD brick in a pool buffer, then the
+ * leaf-level replay and output (an 8-wavefront workgroup per brick; Alg. 1),
+ * plus a third launch for pools holding bricks whose leaf arrays may not
+ * fit that workgroup's LDS.
  * Each stream has its own intermediate buffers (up to 16 streams per pool
  * at once; a 17th waits for all work on the device), so decodes on
  * different streams may overlap; decodes on one stream run in order.  The
@@ -153,9 +156,10 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                       const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
-/* Baseline: the same kernels launched once per brick (a counter reset, a
- * grid of one wavefront, a grid of one workgroup: 3n launches on `stream`).
- * Same arguments and results. */
+/* Baseline: the same kernels launched once per brick (a grid of one
+ * wavefront, then a grid of one workgroup: 2n launches on `stream`, 3n for
+ * pools that need the global-memory leaf kernel).  Same arguments and
+ * results. */
 int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                             const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
 
@@ -163,8 +167,8 @@ int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, con
 typedef struct {
     int waves_per_group;    /* front kernel: wavefronts per workgroup, 4, 8 or 16 (each decodes its
                                own bricks; 8 KiB of LDS per wavefront) */
-    uint32_t groups_per_cu; /* leaf kernel: 4-wavefront workgroups per compute unit, 1..8; each holds
-                               160 KiB / groups_per_cu of LDS (rounded down to whole KiB; bricks
+    uint32_t groups_per_cu; /* leaf kernel: 8-wavefront workgroups per compute unit, 1..8; each holds
+                               160 KiB / groups_per_cu of LDS (rounded down to 4 KiB; bricks
                                whose arrays do not fit take a slower path through a global-memory
                                arena) */
     int use_queue;          /* 1: waves / workgroups take requests from device work counters;
@@ -182,6 +186,27 @@ int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *brick_ids, co
 /* The shape csv_decode_bricks uses (default {16, 3, 1, 0}). */
 int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape);
 int csv_pool_get_shape(const csv_pool *pool, csv_shape *shape);
+
+/*
+ * Empty-space test of requested bricks (Sec. 4, empty-space skipping: a
+ * brick none of whose palette labels the transfer function makes visible
+ * need not be decoded).  For i < n:
+ *   visible[i] = 1 if some label of brick brick_ids[i] (its palette: the
+ *                brick's distinct labels) has bit (label & 31) of word
+ *                label >> 5 set in visible_bits, else 0.
+ *   brick_ids     device, uint32[n], global pool ids
+ *   visible_bits  device, uint32[(n_label_bits + 31) / 32]; labels >=
+ *                 n_label_bits count as invisible (n_label_bits = 0: none
+ *                 is visible, and visible_bits may be NULL)
+ *   visible       device, uint8[n]
+ * All buffers belong to the caller; asynchronous on `stream`; n = 0 does
+ * nothing.  An unknown id gives 0 and CSV_ERANGE in the pool's error word
+ * (with the request index), a record whose palette does not fit its size
+ * gives 0 and CSV_ECORRUPT (with the brick id); read them with
+ * csv_pool_last_error.
+ */
+int csv_bricks_visible(const csv_pool *pool, const uint32_t *brick_ids, uint32_t n, const uint32_t *visible_bits,
+                       uint32_t n_label_bits, uint8_t *visible, void *stream);
 
 /* Autotuner: decodes the given request set (same arguments as
  * csv_decode_bricks; `out` is overwritten) with every candidate shape

@@ -99,6 +99,7 @@ def lib():
         L.csv_decode_bricks_shaped.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(Shape)]
         L.csv_pool_set_shape.argtypes = [vp, ctypes.POINTER(Shape)]
         L.csv_pool_get_shape.argtypes = [vp, ctypes.POINTER(Shape)]
+        L.csv_bricks_visible.argtypes = [vp, vp, u32, vp, u32, vp, vp]
         L.csv_autotune.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, u32, ctypes.POINTER(Shape)]
         L.csv_graph_create.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(vp)]
         L.csv_graph_launch.argtypes = [vp, vp]
@@ -219,6 +220,21 @@ class Pool:
             _chk(lib().csv_decode_bricks_plain(*args), "csv_decode_bricks_plain")
         else:
             _chk(lib().csv_decode_bricks(*args), "csv_decode_bricks")
+
+    def visible(self, ids, visible_bits, n_label_bits: int, out=None, stream=None):
+        """Empty-space test: out[i] = 1 if some label of brick ids[i] has its
+        bit set in `visible_bits` (int32 cuda tensor, bit label & 31 of word
+        label >> 5; labels >= n_label_bits are invisible), else 0.  `out`:
+        uint8 cuda tensor of ids.numel() entries, allocated if None.
+        Returns out (asynchronous on the stream)."""
+        if out is None:
+            import torch
+            out = torch.empty(ids.numel(), dtype=torch.uint8, device=ids.device)
+        bits = visible_bits.data_ptr() if (visible_bits is not None and n_label_bits) else 0
+        _chk(lib().csv_bricks_visible(self._p, ctypes.c_void_p(ids.data_ptr()), int(ids.numel()),
+                                      ctypes.c_void_p(bits), int(n_label_bits), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_handle(stream)), "csv_bricks_visible")
+        return out
 
     def set_shape(self, shape):
         sh = Shape(int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3]) if len(shape) > 3 else 0, 0.0)

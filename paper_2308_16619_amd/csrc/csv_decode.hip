@@ -1507,6 +1507,48 @@ __global__ void zero_words(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
+// Empty-space test (Sec. 4, empty-space skipping): a brick is visible when
+// some label of its palette (the brick's distinct labels) has its bit set in
+// `bits`; labels >= n_bits are invisible.  One wave per request, 64 palette
+// entries per step, a ballot decides.
+__global__ __launch_bounds__(256) void visible_kernel(const uint64_t *rec_ptr, const uint32_t *rec_size,
+                                                      uint32_t n_bricks, const uint32_t *ids, uint32_t n,
+                                                      const uint32_t *bits, uint32_t n_bits, uint8_t *out,
+                                                      int *err) {
+    const uint32_t L = lane(), wave = uniform(threadIdx.x >> 6);
+    const uint32_t hdr = csv::record_header_words(kLog2);
+    for (uint32_t r = blockIdx.x * 4 + wave; r < n; r += gridDim.x * 4) {
+        const uint32_t id = ld_s(ids + r);
+        if (id >= n_bricks) {
+            if (L == 0) {
+                out[r] = 0;
+                report(err, CSV_ERANGE, r);
+            }
+            continue;
+        }
+        const uint32_t *rec = rec_at(ld_s(rec_ptr + id));
+        const uint32_t P = ld_s(rec);
+        if (P == 0 || (uint64_t)4 * (hdr + P) > ld_s(rec_size + id)) {
+            if (L == 0) {
+                out[r] = 0;
+                report(err, CSV_ECORRUPT, id);
+            }
+            continue;
+        }
+        bool vis = false;
+        for (uint32_t b = 0; b < P; b += 64) {
+            const uint32_t e = b + L;
+            const uint32_t lab = e < P ? rec[hdr + e] : 0xFFFFFFFFu;
+            const bool v = lab < n_bits && ((bits[lab >> 5] >> (lab & 31u)) & 1u) != 0;
+            if (__ballot(v) != 0) {
+                vis = true;
+                break;
+            }
+        }
+        if (L == 0) out[r] = vis ? 1 : 0;
+    }
+}
+
 // Per-stream launch buffers: the nibble buffer and status bytes that pass
 // requests from the entropy decoder to the replay, the longest-first order,
 // and the two work counters.  Launches on one stream are ordered, so they
@@ -1976,6 +2018,22 @@ int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *
     const csv_shape sh = pool->shape;
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0);
+}
+
+int csv_bricks_visible(const csv_pool *pool, const uint32_t *ids, uint32_t n, const uint32_t *visible_bits,
+                       uint32_t n_label_bits, uint8_t *visible, void *stream) {
+    if (!pool) return CSV_EINVAL;
+    if (n == 0) return CSV_OK;
+    if (!ids || !visible || (n_label_bits && !visible_bits)) return CSV_EINVAL;
+    csv_pool *p = const_cast<csv_pool *>(pool);
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->rec_ptr.empty() || !p->d_err) return CSV_EINVAL;
+    DeviceGuard g(p->device);
+    const uint32_t cu = (uint32_t)std::max(1, p->n_cu);
+    const uint32_t grid = std::max(1u, std::min((n + 3) / 4, cu * 8));
+    hipLaunchKernelGGL(visible_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, p->d_rec_ptr, p->d_rec_size,
+                       (uint32_t)p->rec_ptr.size(), ids, n, visible_bits, n_label_bits, visible, p->d_err);
+    return hipGetLastError() == hipSuccess ? CSV_OK : CSV_EHIP;
 }
 
 int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,

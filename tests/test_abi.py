@@ -34,6 +34,14 @@ def test_library_exports_every_declared_symbol():
     assert L.csv_abi_version() == 1
 
 
+def test_visibility_test_rejects_a_missing_pool():
+    import ctypes
+    import paper_2308_16619_amd as csv
+    L = csv.lib()
+    assert L.csv_bricks_visible(None, None, 0, None, 0, None, None) == csv.CSV_EINVAL
+    assert L.csv_bricks_visible(None, ctypes.c_void_p(16), 4, None, 0, ctypes.c_void_p(16), None) == csv.CSV_EINVAL
+
+
 def test_strerror():
     import paper_2308_16619_amd as csv
     assert csv.lib().csv_strerror(-3) == b"corrupt data"
