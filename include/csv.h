@@ -272,7 +272,7 @@ typedef struct {
     uint32_t elems;
     int32_t status;        /* CSV_OK, CSV_ERANGE (bad id or LOD) or a decode error */
     uint32_t hit;          /* 1: served from the cache */
-    uint32_t pad;
+    uint32_t skipped;      /* 1: invisible under the visibility table, not decoded (data NULL) */
     uint64_t t_arrival_ns, t_done_ns;
 } csv_completion;
 
@@ -286,6 +286,7 @@ typedef struct {
     uint64_t worker_launch_ns; /* ... of which launching batches */
     uint64_t stall_batch, stall_inflight, stall_slot; /* admission rounds stopped by: no free batch,
                                                          the in-flight budget, no cache slot */
+    uint64_t skipped;          /* requests completed as invisible (not in the latency figures) */
 } csv_stats;
 
 /* Clock of arrival and completion times (steady, nanoseconds). */
@@ -305,6 +306,14 @@ int csv_server_stats(csv_server *server, csv_stats *stats);
  * next csv_server_poll, like the completion itself. */
 int csv_server_read(csv_server *server, const csv_completion *completion, uint32_t *host_dst);
 int csv_server_reset_stats(csv_server *server);
+/* Empty-space skipping in serving (Sec. 4): with a visibility table set, a
+ * request for a brick whose byte is 0 completes at once without a decode
+ * (status CSV_OK, skipped 1, data NULL, elems 0).  visible: host, one byte
+ * per global brick id (n_bricks must be the pool's brick count; e.g. from
+ * csv_bricks_visible over every brick), copied; NULL clears the table (every
+ * brick is decoded).  Thread safe; requests submitted after it returns are
+ * admitted under the new table. */
+int csv_server_set_visible(csv_server *server, const uint8_t *visible, uint32_t n_bricks);
 /* Replay a trace in real time (arrival times relative to the start); see csv_server.cpp. */
 int csv_server_run_trace(csv_server *server, const csv_request *requests, uint32_t n, csv_completion *done,
                          uint64_t timeout_ns, uint32_t *n_done);

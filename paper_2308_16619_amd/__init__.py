@@ -49,7 +49,7 @@ class Shape(ctypes.Structure):
 
 REQUEST_DTYPE = np.dtype([("brick_id", "<u4"), ("lod", "<u4"), ("tag", "<u8"), ("t_arrival_ns", "<u8")])
 COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("brick_id", "<u4"), ("lod", "<u4"), ("data", "<u8"), ("elems", "<u4"),
-                             ("status", "<i4"), ("hit", "<u4"), ("pad", "<u4"), ("t_arrival_ns", "<u8"),
+                             ("status", "<i4"), ("hit", "<u4"), ("skipped", "<u4"), ("t_arrival_ns", "<u8"),
                              ("t_done_ns", "<u8")])
 
 
@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
         (n, ctypes.c_double) for n in ("p50_us", "p99_us", "p50_miss_us", "p99_miss_us", "max_us")] + [
         ("error", ctypes.c_int32), ("pad", ctypes.c_int32), ("worker_busy_ns", ctypes.c_uint64),
         ("worker_launch_ns", ctypes.c_uint64), ("stall_batch", ctypes.c_uint64), ("stall_inflight", ctypes.c_uint64),
-        ("stall_slot", ctypes.c_uint64)]
+        ("stall_slot", ctypes.c_uint64), ("skipped", ctypes.c_uint64)]
 
 
 class PoolInfo(ctypes.Structure):
@@ -111,6 +111,7 @@ def lib():
         L.csv_server_submit.argtypes = [vp, vp, u32]
         L.csv_server_poll.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         L.csv_server_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.csv_server_set_visible.argtypes = [vp, vp, u32]
         L.csv_server_reset_stats.argtypes = [vp]
         L.csv_server_read.argtypes = [vp, vp, vp]
         L.csv_server_run_trace.argtypes = [vp, vp, u32, vp, u64, ctypes.POINTER(u32)]
@@ -345,6 +346,15 @@ class Server:
 
     def reset_stats(self):
         _chk(lib().csv_server_reset_stats(self._s), "csv_server_reset_stats")
+
+    def set_visible(self, visible):
+        """Visibility table (uint8 per global brick id, host) or None: requests
+        for bricks whose byte is 0 complete at once as skipped."""
+        if visible is None:
+            _chk(lib().csv_server_set_visible(self._s, ctypes.c_void_p(0), 0), "csv_server_set_visible")
+            return
+        v = np.ascontiguousarray(visible, dtype=np.uint8)
+        _chk(lib().csv_server_set_visible(self._s, _np_ptr(v), len(v)), "csv_server_set_visible")
 
     def close(self):
         if self._s:

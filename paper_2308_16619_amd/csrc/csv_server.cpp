@@ -96,6 +96,9 @@ struct csv_server {
     // requests
     std::mutex in_mu;
     std::vector<csv_request> inbox;
+    std::vector<uint8_t> vis_in;     // visibility table handed in (under in_mu)
+    int vis_new = 0;                 // 1: vis_in is a new table, 2: clear the table
+    std::vector<uint8_t> visible;    // the worker's table (empty: every brick visible)
     std::deque<Pending> pending;
     std::vector<csv_request> reqs;   // request table (worker)
     std::vector<int32_t> req_next;   // next waiter of the same decode
@@ -114,12 +117,12 @@ struct csv_server {
     std::vector<csv_completion> c_local;
     std::vector<int32_t> e_local;
     std::vector<float> l_all, l_miss;
-    uint64_t d_req = 0, d_hit = 0, d_miss = 0, d_join = 0, d_busy = 0, d_launch = 0;
+    uint64_t d_req = 0, d_hit = 0, d_miss = 0, d_join = 0, d_busy = 0, d_launch = 0, d_skip = 0;
     // stats
     std::mutex st_mu;
     std::deque<float> lat_all, lat_miss;  // a deque grows without copying what it holds
     uint64_t n_req = 0, n_hit = 0, n_miss = 0, n_join = 0, n_batches = 0, n_evict = 0, n_rebuild = 0,
-             decoded_bytes = 0, n_launch_err = 0, busy_ns = 0, launch_ns = 0;
+             decoded_bytes = 0, n_launch_err = 0, busy_ns = 0, launch_ns = 0, n_skip = 0;
     uint64_t stall[3] = {0, 0, 0};  // admission stopped: no free batch, in-flight budget, no slot
 
     std::atomic<uint64_t> submitted{0}, completed{0};
@@ -130,7 +133,7 @@ struct csv_server {
 
 namespace {
 
-void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint64_t t) {
+void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint64_t t, bool skipped = false) {
     const csv_request &r = s->reqs[ridx];
     csv_completion c{};
     c.tag = r.tag;
@@ -138,6 +141,7 @@ void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint
     c.lod = r.lod;
     c.status = status;
     c.hit = hit ? 1u : 0u;
+    c.skipped = skipped ? 1u : 0u;
     c.t_arrival_ns = r.t_arrival_ns;
     c.t_done_ns = t;
     int32_t eid = -1;
@@ -148,8 +152,10 @@ void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint
         eid = (int32_t)(e - s->entries.data());
     }
     const float us = (float)((double)(t - r.t_arrival_ns) * 1e-3);
-    s->l_all.push_back(us);
-    if (!hit) s->l_miss.push_back(us);
+    if (!skipped) {
+        s->l_all.push_back(us);
+        if (!hit) s->l_miss.push_back(us);
+    }
     s->c_local.push_back(c);
     s->e_local.push_back(eid);
     s->free_reqs.push_back(ridx);
@@ -158,7 +164,7 @@ void complete(csv_server *s, uint32_t ridx, Entry *e, int status, bool hit, uint
 // hand this loop's statistics, then its completions, to the client side
 // (a completion the client sees is already counted)
 void publish(csv_server *s) {
-    if (!s->l_all.empty() || s->d_req || s->d_hit || s->d_miss || s->d_join || s->d_busy) {
+    if (!s->l_all.empty() || s->d_req || s->d_hit || s->d_miss || s->d_join || s->d_busy || s->d_skip) {
         std::lock_guard<std::mutex> lk(s->st_mu);
         s->busy_ns += s->d_busy;
         s->launch_ns += s->d_launch;
@@ -169,9 +175,10 @@ void publish(csv_server *s) {
         s->n_hit += s->d_hit;
         s->n_miss += s->d_miss;
         s->n_join += s->d_join;
+        s->n_skip += s->d_skip;
         s->l_all.clear();
         s->l_miss.clear();
-        s->d_req = s->d_hit = s->d_miss = s->d_join = 0;
+        s->d_req = s->d_hit = s->d_miss = s->d_join = s->d_skip = 0;
     }
     if (!s->c_local.empty()) {
         const size_t k = s->c_local.size();
@@ -350,6 +357,11 @@ bool admit(csv_server *s, const Pending &p, uint64_t t_now) {
         complete(s, p.idx, nullptr, CSV_ERANGE, false, t_now);
         return true;
     }
+    if (!s->visible.empty() && !s->visible[r.brick_id]) {  // empty space: nothing to decode
+        complete(s, p.idx, nullptr, CSV_OK, false, t_now, true);
+        s->d_skip++;
+        return true;
+    }
     const size_t key = (size_t)r.brick_id * kClasses + r.lod;
     int32_t id = s->index[key];
     if (id >= 0) {
@@ -425,6 +437,9 @@ void worker_main(csv_server *s) {
         {
             std::lock_guard<std::mutex> lk(s->in_mu);
             take.swap(s->inbox);
+            if (s->vis_new == 1) s->visible.swap(s->vis_in);
+            if (s->vis_new == 2) s->visible.clear();
+            s->vis_new = 0;
         }
         for (const csv_request &r : take) {
             uint32_t idx;
@@ -616,6 +631,7 @@ int csv_server_stats(csv_server *s, csv_stats *st) {
     st->stall_batch = s->stall[0];
     st->stall_inflight = s->stall[1];
     st->stall_slot = s->stall[2];
+    st->skipped = s->n_skip;
     return CSV_OK;
 }
 
@@ -628,6 +644,23 @@ int csv_server_reset_stats(csv_server *s) {
     s->decoded_bytes = 0;
     s->busy_ns = s->launch_ns = 0;
     s->stall[0] = s->stall[1] = s->stall[2] = 0;
+    s->n_skip = 0;
+    return CSV_OK;
+}
+
+int csv_server_set_visible(csv_server *s, const uint8_t *visible, uint32_t n_bricks) {
+    if (!s || (visible && n_bricks != s->n_bricks)) return CSV_EINVAL;
+    std::vector<uint8_t> v;
+    if (visible) {
+        try {
+            v.assign(visible, visible + n_bricks);
+        } catch (...) {
+            return CSV_ENOMEM;
+        }
+    }
+    std::lock_guard<std::mutex> lk(s->in_mu);
+    s->vis_in.swap(v);
+    s->vis_new = visible ? 1 : 2;
     return CSV_OK;
 }
 

@@ -92,6 +92,55 @@ def test_bad_requests(setup):
     srv.close()
 
 
+def test_visibility_table_skips_invisible_bricks(setup, orc):
+    # the visibility of every brick comes from csv_bricks_visible under a
+    # transfer function showing a few labels; requests for the invisible
+    # bricks complete as skipped, the others decode to the oracle's bytes,
+    # and clearing the table decodes everything again
+    csv, b1, b2 = setup
+    torch = torch_cuda()
+    pool = csv.Pool()
+    pool.add_volume(b1)
+    pool.add_volume(b2)
+    n_b = 8 + 512
+    n_lab = 19 ** 3 + 1
+    show = np.zeros(n_lab, bool)
+    show[np.random.default_rng(3).choice(n_lab, 60, replace=False)] = True
+    words = np.zeros((n_lab + 31) // 32, np.uint32)
+    for lab in np.nonzero(show)[0]:
+        words[lab >> 5] |= np.uint32(1 << (lab & 31))
+    d_ids = torch.arange(n_b, dtype=torch.int32, device="cuda")
+    vis = pool.visible(d_ids, torch.from_numpy(words.view(np.int32)).cuda(), n_lab).cpu().numpy()
+    assert 0 < vis.sum() < n_b
+    srv = csv.Server(pool, cache_bytes=64 << 20, max_batch=128)
+    srv.set_visible(vis)
+    rng = np.random.default_rng(9)
+    ids = rng.integers(0, n_b, 1500).astype(np.uint32)
+    lods = rng.choice([0, 1, 3], 1500).astype(np.uint32)
+    srv.submit(srv.requests(ids, lods, tags=np.arange(1500)))
+    skipped = 0
+    for comp in wait_all(srv, 1500):
+        for c in comp:
+            assert c["status"] == 0 and c["brick_id"] == ids[c["tag"]]
+            if vis[c["brick_id"]]:
+                assert c["skipped"] == 0
+                np.testing.assert_array_equal(srv.read(c), oracle_brick(orc, b1, b2, c["brick_id"], c["lod"]))
+            else:
+                assert c["skipped"] == 1 and c["data"] == 0 and c["elems"] == 0
+                skipped += 1
+    assert skipped == int((vis[ids] == 0).sum()) and srv.stats()["skipped"] == skipped
+    srv.set_visible(None)
+    hidden = np.nonzero(vis == 0)[0][:50].astype(np.uint32)
+    srv.submit(srv.requests(hidden, np.zeros(len(hidden), np.uint32)))
+    for comp in wait_all(srv, len(hidden)):
+        for c in comp:
+            assert c["skipped"] == 0
+            np.testing.assert_array_equal(srv.read(c), oracle_brick(orc, b1, b2, c["brick_id"], 0))
+    with pytest.raises(Exception):
+        srv.set_visible(np.ones(n_b + 1, np.uint8))
+    srv.close()
+
+
 def test_trace_replay(setup, orc):
     csv, b1, b2 = setup
     pool = csv.Pool()
