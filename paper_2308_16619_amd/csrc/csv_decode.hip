@@ -1044,9 +1044,8 @@ struct SmallB {
 
 // Arena of a leaf brick: palette (P entries) and nib4 16-byte groups of
 // nibbles (staged only in LDS), L_1 as a dense 16^3 array, its expansion
-// bits (Morton order) and their rank prefix, the expanded L_1 nodes (dense
-// coordinates X | Y << 4 | Z << 8, stream order; list_cap entries) and the
-// dense 32^3 leaf level
+// bits (Morton order) and their rank prefix, the expanded L_1 nodes (Morton
+// indices, stream order; list_cap entries) and the dense 32^3 leaf level
 struct LayoutL {
     uint32_t pal, nib, l1, bm1, bpre, list1, leaf, total;
 };
@@ -1198,16 +1197,16 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
         sm->wt[w][1] = tpd;
     }
     __syncthreads();
-    // the expanded L_1 nodes in Morton (= stream) order, from the bitmask
-    for (uint32_t t = tid; t < 256; t += (64 * NW)) {
-        const uint32_t wd = t >> 2, q = t & 3u;
+    // the expanded L_1 nodes (Morton indices) in Morton (= stream) order,
+    // from the bitmask: 8 bits per thread
+    for (uint32_t t = tid; t < 512; t += (64 * NW)) {
+        const uint32_t wd = t >> 3, q = t & 7u;
         const uint64_t word = bm1w[wd];
-        uint32_t bits = (uint32_t)(word >> (16 * q)) & 0xFFFFu;
-        uint32_t pos = bpre[wd] + (uint32_t)__popcll(word & ((1ull << (16 * q)) - 1ull));
+        uint32_t bits = (uint32_t)(word >> (8 * q)) & 0xFFu;
+        uint32_t pos = bpre[wd] + (uint32_t)__popcll(word & ((1ull << (8 * q)) - 1ull));
         while (bits) {
-            const uint32_t p = 64 * wd + 16 * q + (uint32_t)__builtin_ctz(bits);
+            if (pos < E1) list1[pos] = (uint16_t)(64 * wd + 8 * q + (uint32_t)__builtin_ctz(bits));
             bits &= bits - 1;
-            if (pos < E1) list1[pos] = (uint16_t)(morton_coord(p) | (morton_coord(p >> 1) << 4) | (morton_coord(p >> 2) << 8));
             pos++;
         }
     }
@@ -1230,8 +1229,8 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
         const uint32_t r = 64 * c + L;
         const bool act = r < E1;
         const uint32_t wd = act ? nib8(nib, ops0 + 8 * r) : 0u;
-        const uint32_t cc = act ? (uint32_t)list1[r] : 0u;
-        const uint32_t X = cc & 15u, Y = (cc >> 4) & 15u, Z = (cc >> 8) & 15u;
+        const uint32_t cc = act ? (uint32_t)list1[r] : 0u;  // Morton index of the node
+        const uint32_t X = morton_coord(cc), Y = morton_coord(cc >> 1), Z = morton_coord(cc >> 2);
         const uint32_t lowok = (X > 0 ? 1u : 0u) | (Y > 0 ? 2u : 0u) | (Z > 0 ? 4u : 0u);
         uint32_t pam, pdm, exm, cnt;
         nibble_counts(wd, act, pam, pdm, exm, cnt);
