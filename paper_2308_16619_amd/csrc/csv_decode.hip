@@ -1134,10 +1134,16 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
                               256 * ((((t >> 1) & 1u) << 1) | (((t >> 4) & 1u) << 2) | (((t >> 7) & 1u) << 3));
         IdxT v[16];
         if constexpr (sizeof(IdxT) == 1) {
+            // byte j goes to x + (j & 1) + 2 ((j >> 3) & 1), y + ((j >> 1) & 1),
+            // z + ((j >> 2) & 1): four dense rows of four bytes, one byte
+            // permute each (bytes 0..3 of q.x / q.y, then of q.z / q.w)
             const uint4 q = reinterpret_cast<const uint4 *>(l1m)[t];
-            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int j = 0; j < 16; j++) v[j] = (IdxT)((qq[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+            uint32_t *o = reinterpret_cast<uint32_t *>(l1 + base);
+            o[0] = __builtin_amdgcn_perm(q.z, q.x, 0x05040100u);   // j = 0, 1, 8, 9
+            o[4] = __builtin_amdgcn_perm(q.z, q.x, 0x07060302u);   // j = 2, 3, 10, 11 (y + 1)
+            o[64] = __builtin_amdgcn_perm(q.w, q.y, 0x05040100u);  // j = 4, 5, 12, 13 (z + 1)
+            o[68] = __builtin_amdgcn_perm(q.w, q.y, 0x07060302u);  // j = 6, 7, 14, 15
+            continue;
         } else {
             const uint4 q0 = reinterpret_cast<const uint4 *>(l1m)[2 * t], q1 = reinterpret_cast<const uint4 *>(l1m)[2 * t + 1];
             const uint32_t qq[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
