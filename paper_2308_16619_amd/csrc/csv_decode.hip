@@ -1115,7 +1115,8 @@ template <class IdxT, bool kG, int NW>
 __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t ipl, const uint32_t *nib,
                                             uint32_t nib0, const IdxT *l1m, const uint64_t *bm1w,
                                             const uint32_t *pal, uint8_t *ar, const LayoutL &lay, SmallB *sm,
-                                            uint32_t *dst, uint16_t *refs, uint32_t ref_cap) {
+                                            uint32_t *dst, uint16_t *refs, uint32_t ref_cap,
+                                            const uint4 *l1pre = nullptr) {
     constexpr bool kList = sizeof(IdxT) == 1 && !kG;
     using V = Vec8<IdxT>;
     using VT = typename V::T;
@@ -1137,7 +1138,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
             // byte j goes to x + (j & 1) + 2 ((j >> 3) & 1), y + ((j >> 1) & 1),
             // z + ((j >> 2) & 1): four dense rows of four bytes, one byte
             // permute each (bytes 0..3 of q.x / q.y, then of q.z / q.w)
-            const uint4 q = reinterpret_cast<const uint4 *>(l1m)[t];
+            const uint4 q = l1pre ? *l1pre : reinterpret_cast<const uint4 *>(l1m)[t];
             uint32_t *o = reinterpret_cast<uint32_t *>(l1 + base);
             o[0] = __builtin_amdgcn_perm(q.z, q.x, 0x05040100u);   // j = 0, 1, 8, 9
             o[4] = __builtin_amdgcn_perm(q.z, q.x, 0x07060302u);   // j = 2, 3, 10, 11 (y + 1)
@@ -1376,6 +1377,7 @@ template <int NW, bool kSlow>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ? 4 : 6))) void leaf_kernel(DecodeArgs a,
                                                                                                       LaunchB l) {
     constexpr uint32_t NT = 64 * NW;
+    static_assert(kSlow || NT >= 256, "thread t < 256 preloads level-1 group t");
     extern __shared__ __align__(16) uint8_t smem[];
     SmallB *sm = reinterpret_cast<SmallB *>(smem);
     uint8_t *arena = smem + align16(sizeof(SmallB));
@@ -1417,12 +1419,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
                 for (uint32_t e = tid; e < nib4; e += NT)
                     reinterpret_cast<uint4 *>(arena + fast.nib)[e] = reinterpret_cast<const uint4 *>(gnib + nb0)[e];
                 if (tid < 32) reinterpret_cast<uint4 *>(arena + fast.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
+                // level 1 (Morton order) with the other loads: one round trip
+                const uint4 l1q = tid < 256 ? reinterpret_cast<const uint4 *>(slv)[tid] : make_uint4(0u, 0u, 0u, 0u);
                 __syncthreads();
                 ok = leaf_replay<uint8_t, false, NW>(h, E1, ipl, reinterpret_cast<const uint32_t *>(arena + fast.nib),
                                                      8 * nb0, slv, reinterpret_cast<const uint64_t *>(arena + fast.bm1),
                                                      reinterpret_cast<const uint32_t *>(arena + fast.pal), arena, fast,
                                                      sm, dst, reinterpret_cast<uint16_t *>(arena + fast.total),
-                                                     min((l.arena_bytes - fast.total) / 2, l.ref_cap));
+                                                     min((l.arena_bytes - fast.total) / 2, l.ref_cap), &l1q);
             } else if (l.slow_list) {  // the slow kernel takes it
                 done = false;
                 if (tid == 0) l.slow_list[atomicAdd(l.slow_count, 1u)] = rq;
