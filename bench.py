@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # counters read for a plain 256 MiB device copy; see
 # profiles/decode_cells512_hbm_traffic.md.  Valid only for the decoder source
 # the counters were taken on (at the launch shape named here).
-TRAFFIC = {"decoder_sha256_16": "3ec2fe1fa28c6d11", "shape": (16, 3, 0, 0), "bytes": 655299077}
+TRAFFIC = {"decoder_sha256_16": "be5086659e5b28da", "shape": (16, 3, 0, 0), "bytes": 655405533}
 
 
 def log(msg):
@@ -106,6 +106,75 @@ def serving_leg(csv, synth, seconds):
             "p99_us_16gib_cache": stated, "p99_us_worst": worst, "runs": runs}
 
 
+def detail_leg(csv, torch, blob, ids_np, ids, out, shape, whole_pool, reps=10):
+    """Detail separation (Sec. 4.2) on the same volume: a second pool keeps in
+    HBM only each record's level-1 prefix and the level-0 detail in pinned
+    host memory.  A frame stages the detail of the requested bricks through
+    the staging buffer (8 MiB, as in the paper) and decodes them at full LOD;
+    its output must equal the whole-record pool's."""
+    B = len(ids_np)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    dpool = csv.Pool(0)
+    dpool.add_volume(blob, detail_host=True)
+    add_s = time.perf_counter() - t0
+    dpool.set_shape(shape)
+    host = dpool.info()["host_bytes"]
+    rec = csv.blob_info(blob)["record_bytes"]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def timed(pool, o, lod, n=10):
+        pool.decode(ids, o, lod=lod)
+        ev[0].record(stream)
+        for _ in range(n):
+            pool.decode(ids, o, lod=lod)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / n
+
+    # level 1 of every brick from the device prefix alone
+    o1 = torch.empty(B * 16 ** 3, dtype=torch.int32, device=out.device)
+    w1 = torch.empty_like(o1)
+    whole_ms = timed(whole_pool, w1, 1)
+    split_ms = timed(dpool, o1, 1)
+    assert dpool.last_error()[0] == 0 and whole_pool.last_error()[0] == 0
+    assert torch.equal(o1, w1), "level 1 of the split pool differs"
+    del o1, w1
+    # frames: stage, decode at full LOD, release
+    out2 = torch.empty_like(out)
+    st, dec, wall, done = [], [], [], 0
+    for r in range(reps + 2):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev[0].record(stream)
+        done = dpool.stage_detail(ids_np, stream)
+        ev[1].record(stream)
+        dpool.decode(ids[:done], out2, lod=0)
+        ev[2].record(stream)
+        dpool.release_detail(stream)
+        torch.cuda.synchronize()
+        if r >= 2:
+            wall.append((time.perf_counter() - w0) * 1e3)
+            st.append(ev[0].elapsed_time(ev[1]))
+            dec.append(ev[1].elapsed_time(ev[2]))
+    assert dpool.last_error()[0] == 0
+    n_el = done * 32 ** 3
+    assert torch.equal(out2[:n_el], out[:n_el]), "staged full-LOD decode differs"
+    # full LOD with nothing staged: level 1 upsampled, CSV_EDETAIL recorded
+    fb_ms = timed(dpool, out2, 0)
+    assert dpool.last_error()[0] == csv.CSV_EDETAIL
+    med = lambda v: sorted(v)[len(v) // 2]
+    staged_bytes = host if done == B else None
+    return {"record_bytes": rec, "hbm_record_bytes": rec - host, "host_detail_bytes": host,
+            "detail_frac": round(host / rec, 4), "add_volume_s": round(add_s, 3),
+            "lod1_ms_split": round(split_ms, 4), "lod1_ms_whole": round(whole_ms, 4),
+            "frame": {"bricks": done, "staging_bytes": 8 << 20, "detail_bytes": staged_bytes,
+                      "stage_ms": round(med(st), 4), "decode_ms": round(med(dec), 4),
+                      "wall_ms": round(med(wall), 4),
+                      "stage_gbs": round(staged_bytes / (med(st) * 1e-3) / 1e9, 2) if staged_bytes else None},
+            "unstaged_full_lod_ms": round(fb_ms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +186,8 @@ def main():
     ap.add_argument("--serving", choices=["full", "none"], default="full",
                     help="serving leg: the 2048x2048x1024 neurite pool with camera-path traces (full) or none")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="measured trace length per serving run")
+    ap.add_argument("--detail", choices=["full", "none"], default="full",
+                    help="detail-separation leg (a second pool of the volume with level-0 detail in host memory)")
     ap.add_argument("--shape", default="", help="fixed launch shape 'waves,groups,queue,lpt' instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for hardware byte counters)")
@@ -245,6 +316,11 @@ def main():
     plain_gbs = nb * 32 ** 3 * 4 / (plain_ms * 1e-3) / 1e9
     assert pool.last_error()[0] == 0
 
+    detail = None
+    if args.detail == "full":
+        log("detail separation leg")
+        detail = detail_leg(csv, torch, blob, ids_np, ids, out, shape, pool)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -293,6 +369,7 @@ def main():
                      "decoder_sha256_16": src_hash},
         "plain_per_brick_launch": {"value": round(plain_gbs, 3), "unit": "GB/s", "bricks": nb},
         "visibility_test": visibility,
+        "detail_separation": detail,
         "cpu_baseline": cpu,
         "serving": serving,
     }

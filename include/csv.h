@@ -39,7 +39,10 @@ enum {
     CSV_ECORRUPT = -3, /* malformed container or record */
     CSV_ENOMEM = -4,   /* host or device allocation failed */
     CSV_EHIP = -5,     /* a HIP runtime call failed */
-    CSV_EBUSY = -6     /* resource temporarily exhausted (server admission) */
+    CSV_EBUSY = -6,    /* resource temporarily exhausted (server admission) */
+    CSV_EDETAIL = -7   /* a full-LOD request whose level-0 detail is not on the device (pool with
+                          detail in host memory, csv_pool_stage_detail): level 1 was decoded and
+                          written upsampled 2x */
 };
 
 #define CSV_ABI_VERSION 1u
@@ -110,10 +113,46 @@ void csv_pool_destroy(csv_pool *pool);
  */
 int csv_pool_add_volume(csv_pool *pool, const uint8_t *blob, size_t blob_bytes, uint32_t *first_brick_id);
 
+/*
+ * Detail separation (Sec. 4.2): with flags CSV_DETAIL_HOST the pool keeps
+ * in HBM each record only up to the words that levels >= 1 read (the stream
+ * prefix property, Sec. 3.4; found by decoding every brick to level 1 once,
+ * which synchronises the device), and the rest of the words in pinned host
+ * memory.  Levels of detail >= 1 decode as usual; a full-LOD request needs
+ * the brick's detail staged with csv_pool_stage_detail, else level 1 is
+ * decoded, written upsampled 2x and CSV_EDETAIL is recorded in the pool's
+ * error word.  flags 0 is csv_pool_add_volume.  Errors as
+ * csv_pool_add_volume; a brick whose level-1 decode fails keeps its whole
+ * record in HBM (the error stays in the pool's error word).
+ */
+#define CSV_DETAIL_HOST 1u
+int csv_pool_add_volume_ex(csv_pool *pool, const uint8_t *blob, size_t blob_bytes, uint32_t flags,
+                           uint32_t *first_brick_id);
+
+/*
+ * Upload the level-0 detail of bricks brick_ids[0 .. n) (host memory) into
+ * the pool's staging buffer in HBM (8 MiB unless csv_pool_set_detail_staging
+ * says otherwise; the paper's frames upload 8 MB), asynchronously on
+ * `stream`, in order, until the buffer is full.  *n_done receives how many
+ * leading ids were handled (bricks of ordinary volumes and bricks already
+ * staged count as handled): decodes of those at full LOD, on the same
+ * stream after this call, read their detail.  Staged detail stays until
+ * csv_pool_release_detail.  Staging, decodes and release of one pool belong
+ * on one stream; not for stream capture.  Errors: CSV_EINVAL, CSV_ERANGE (an
+ * id out of range: *n_done is its index), CSV_ENOMEM, CSV_EHIP.
+ */
+int csv_pool_stage_detail(csv_pool *pool, const uint32_t *brick_ids, uint32_t n, void *stream, uint32_t *n_done);
+/* Drop all staged detail (after the decodes that used it, in stream order). */
+int csv_pool_release_detail(csv_pool *pool, void *stream);
+/* Size of the staging buffer (bytes, 4 KiB .. 64 GiB); CSV_EBUSY while detail is staged. */
+int csv_pool_set_detail_staging(csv_pool *pool, uint64_t bytes);
+
 typedef struct {
     uint32_t n_volumes, n_bricks;
     uint64_t device_bytes; /* HBM held by the pool */
     int device;
+    int32_t pad;
+    uint64_t host_bytes;   /* pinned host memory holding level-0 detail (CSV_DETAIL_HOST volumes) */
 } csv_pool_info;
 int csv_pool_info_get(const csv_pool *pool, csv_pool_info *info);
 
@@ -293,7 +332,9 @@ typedef struct {
 uint64_t csv_now_ns(void);
 
 /* Start a server on a pool (its own worker thread, streams, HBM cache).
- * The pool must outlive the server and gain no volumes while it runs. */
+ * The pool must outlive the server and gain no volumes while it runs; a
+ * pool holding level-0 detail in host memory (CSV_DETAIL_HOST) is refused
+ * with CSV_EINVAL. */
 int csv_server_create(csv_pool *pool, const csv_server_opts *opts, csv_server **server);
 /* Queue n requests (host memory; thread safe; returns at once). */
 int csv_server_submit(csv_server *server, const csv_request *requests, uint32_t n);

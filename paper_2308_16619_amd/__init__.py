@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libcsv.so")
 BRICK = 32
 MAX_LOD = 5
 
-CSV_OK, CSV_EINVAL, CSV_ERANGE, CSV_ECORRUPT, CSV_ENOMEM, CSV_EHIP, CSV_EBUSY = 0, -1, -2, -3, -4, -5, -6
+CSV_OK, CSV_EINVAL, CSV_ERANGE, CSV_ECORRUPT, CSV_ENOMEM, CSV_EHIP, CSV_EBUSY, CSV_EDETAIL = 0, -1, -2, -3, -4, -5, -6, -7
+CSV_DETAIL_HOST = 1
 _lib = None
 
 
@@ -69,7 +70,7 @@ class Stats(ctypes.Structure):
 
 class PoolInfo(ctypes.Structure):
     _fields_ = [("n_volumes", ctypes.c_uint32), ("n_bricks", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
-                ("device", ctypes.c_int)]
+                ("device", ctypes.c_int), ("pad", ctypes.c_int32), ("host_bytes", ctypes.c_uint64)]
 
 
 def lib():
@@ -92,6 +93,10 @@ def lib():
         L.csv_pool_create.argtypes = [ctypes.POINTER(vp), i32]
         L.csv_pool_destroy.argtypes = [vp]
         L.csv_pool_add_volume.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(u32)]
+        L.csv_pool_add_volume_ex.argtypes = [vp, vp, ctypes.c_size_t, u32, ctypes.POINTER(u32)]
+        L.csv_pool_stage_detail.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u32)]
+        L.csv_pool_release_detail.argtypes = [vp, vp]
+        L.csv_pool_set_detail_staging.argtypes = [vp, u64]
         L.csv_pool_info_get.argtypes = [vp, ctypes.POINTER(PoolInfo)]
         L.csv_output_elems.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
         for f in ("csv_decode_bricks", "csv_decode_bricks_plain"):
@@ -191,10 +196,30 @@ class Pool:
         except Exception:
             pass
 
-    def add_volume(self, blob: bytes) -> int:
+    def add_volume(self, blob: bytes, detail_host: bool = False) -> int:
+        """Add one container; detail_host keeps level-0 detail in pinned host memory (Sec. 4.2)."""
         first = ctypes.c_uint32()
-        _chk(lib().csv_pool_add_volume(self._p, blob, len(blob), ctypes.byref(first)), "csv_pool_add_volume")
+        if detail_host:
+            _chk(lib().csv_pool_add_volume_ex(self._p, blob, len(blob), CSV_DETAIL_HOST, ctypes.byref(first)),
+                 "csv_pool_add_volume_ex")
+        else:
+            _chk(lib().csv_pool_add_volume(self._p, blob, len(blob), ctypes.byref(first)), "csv_pool_add_volume")
         return first.value
+
+    def stage_detail(self, ids_host, stream=None) -> int:
+        """Upload the level-0 detail of host brick ids (in order, until the staging
+        buffer is full); returns how many leading ids are ready for full-LOD decode."""
+        a = np.ascontiguousarray(np.asarray(ids_host, dtype=np.uint32))
+        done = ctypes.c_uint32()
+        _chk(lib().csv_pool_stage_detail(self._p, a.ctypes.data if a.size else None, int(a.size),
+                                         _stream_handle(stream), ctypes.byref(done)), "csv_pool_stage_detail")
+        return done.value
+
+    def release_detail(self, stream=None) -> None:
+        _chk(lib().csv_pool_release_detail(self._p, _stream_handle(stream)), "csv_pool_release_detail")
+
+    def set_detail_staging(self, nbytes: int) -> None:
+        _chk(lib().csv_pool_set_detail_staging(self._p, int(nbytes)), "csv_pool_set_detail_staging")
 
     def info(self) -> dict:
         i = PoolInfo()

@@ -92,6 +92,11 @@ struct DecodeArgs {
     uint32_t *out;
     uint32_t n;
     int *err;  // [0] first error code, [1] brick id (or request index)
+    // pools with level-0 detail in host memory (else nullptr): per brick the
+    // word dwords held in the device record (0xFFFFFFFF: all of them) and the
+    // device address of the staged remaining dwords (0: not staged)
+    const uint32_t *pfx_dw;
+    const uint64_t *sfx;
 };
 
 struct LaunchA {
@@ -104,6 +109,9 @@ struct LaunchA {
     uint32_t *leaf_list;     // requests left for the leaf kernel
     uint32_t *leaf_count;
     uint32_t base;           // first request index
+    uint32_t *words_out;     // prefix pass (else nullptr): per request the words the decode of its
+                             // level of detail consumed (0 for uniform bricks, 0xFFFFFFFF on error);
+                             // nothing is written to the output
 };
 
 struct LaunchB {
@@ -262,6 +270,9 @@ __device__ __forceinline__ uint32_t ld_s_u16(const uint16_t *p) {
 // ---------------------------------------------------------------------------
 struct Hdr {
     const uint32_t *rec;
+    const uint32_t *sfx;  // staged word dwords from pdw on (detail in host memory), else nullptr
+    uint32_t pdw;         // word dwords in the device record (0xFFFFFFFF: all)
+    bool up;              // full LOD requested, level 1 decoded and written upsampled
     uint32_t P, W, nw, t, vol, rq, id;
     // cumulative symbol counts (scalars: a run-time level never indexes a private array)
     uint32_t c0, c1, c2, c3, c4;
@@ -276,6 +287,9 @@ enum ReqKind { kReqBadLod, kReqBadId, kReqCorrupt, kReqFill, kReqDecode };
 __device__ __forceinline__ ReqKind load_request(const DecodeArgs &a, uint32_t rq, Hdr &h, uint32_t *&dst,
                                                 uint32_t &count, uint32_t &fill) {
     h.rq = rq;
+    h.sfx = nullptr;
+    h.pdw = 0xFFFFFFFFu;
+    h.up = false;
     h.id = ld_s(a.ids + rq);
     h.t = a.lods ? ld_s_u8(a.lods + rq) : a.lod_scalar;
     dst = nullptr;
@@ -297,15 +311,27 @@ __device__ __forceinline__ ReqKind load_request(const DecodeArgs &a, uint32_t rq
     h.c2 = ld_s(h.rec + 5);
     h.c3 = ld_s(h.rec + 6);
     h.c4 = ld_s(h.rec + 7);
+    if (a.pfx_dw) {
+        h.pdw = ld_s(a.pfx_dw + h.id);
+        if (h.pdw != 0xFFFFFFFFu) {
+            const uint64_t s = ld_s(a.sfx + h.id);
+            h.sfx = s ? rec_at(s) : nullptr;
+        }
+    }
     const uint32_t hdr = csv::record_header_words(kLog2);
+    // the record holds its words up to pdw dwords (the rest is staged)
     bool ok = h.P >= 1 && h.W <= 64 && (h.W & (h.W - 1)) == 0 && ((h.c0 > 0) == (h.W > 0)) && h.c0 <= kMaxSym &&
-              (uint64_t)4 * (hdr + h.P + h.W) + 2ull * h.nw <= size;
+              (uint64_t)4 * (hdr + h.P + h.W) + std::min<uint64_t>(2ull * h.nw, 4ull * h.pdw) <= size;
     ok = ok && h.c0 >= h.c1 && h.c1 >= h.c2 && h.c2 >= h.c3 && h.c3 >= h.c4;
     if (ok) ok = (h.c0 == 0) ? (h.P == 1) : (h.P >= 2);
     if (!ok) return kReqCorrupt;
     if (h.t == (uint32_t)kLog2 || h.c0 == 0) {  // coarsest level or uniform brick: palette[0]
         fill = ld_s(h.rec + hdr);
         return kReqFill;
+    }
+    if (h.t == 0 && h.pdw != 0xFFFFFFFFu && !h.sfx) {  // level 0 not on the device: level 1, upsampled
+        h.t = 1;
+        h.up = true;
     }
     return kReqDecode;
 }
@@ -530,7 +556,8 @@ __device__ __forceinline__ void wave_sync() {
 // 2 KB of LDS.  False on a malformed stream.
 template <bool kLutLds>
 __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h, const uint32_t *slut,
-                                               uint32_t *ring32, uint32_t *out, uint32_t *lcopy, uint32_t n) {
+                                               uint32_t *ring32, uint32_t *out, uint32_t *lcopy, uint32_t n,
+                                               uint32_t &words) {
     const uint32_t L = lane();
     const uint32_t hdr = csv::record_header_words(kLog2);
     const uint16_t *ring = reinterpret_cast<const uint16_t *>(ring32);
@@ -539,6 +566,11 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
     const uint32_t W = h.W, lw = 31u - (uint32_t)__builtin_clz(W), leaf = h.c1;
     const uint32_t *wg = h.rec + hdr + h.P + W;
     const uint32_t ndw = (h.nw + 1) / 2;  // word dwords in the record (the last one padded)
+    // dword d of the word stream: from the record below pdw, then from the
+    // staged detail (0 past what is there: never consumed)
+    const uint32_t pdw = min(h.pdw, ndw);
+    const uint32_t *sfx = h.sfx;
+    auto wdw = [&](uint32_t d) -> uint32_t { return d < pdw ? wg[d] : ((sfx && d < ndw) ? sfx[d - pdw] : 0u); };
     uint32_t x = L < W ? h.rec[hdr + h.P + L] : 0u;
     // the ring holds words [ring_lo, ring_lo + 1024) at positions word & 1023,
     // and positions 0..63 again after position 1023 (a read of 64 words from
@@ -547,7 +579,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const uint32_t d = L + 64 * q;
-        const uint32_t v = d < ndw ? wg[d] : 0u;
+        const uint32_t v = wdw(d);
         ring32[d] = v;
         if (q == 0 && L < 32) ring32[kRingWords / 2 + L] = v;
     }
@@ -555,7 +587,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const uint32_t d = 512 + L + 64 * q;
-        pf[q] = d < ndw ? wg[d] : 0u;
+        pf[q] = wdw(d);
     }
     wsync();
     uint32_t cursor = 0, acc = 0;
@@ -572,7 +604,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const uint32_t d = d0 + L + 64 * q;
-            pf[q] = d < ndw ? wg[d] : 0u;
+            pf[q] = wdw(d);
         }
         wsync();
     };
@@ -680,6 +712,7 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
     }
     // a complete decode ends in the encoder's initial states with every word read
     if (!bad && h.t == 0) bad = (__ballot(L < W && x != csv::kRansLower) != 0) || cursor != h.nw;
+    words = cursor;
     return !bad;
 }
 
@@ -926,6 +959,25 @@ __device__ __forceinline__ void upper_output(const IdxT *lv, uint32_t t, const u
     else rows(std::false_type{});
 }
 
+// level 1 written as a 32^3 block, every voxel the value of its level-1
+// node (full LOD requested, level-0 detail not on the device), by one wave
+template <class IdxT, bool kG>
+__device__ __forceinline__ void upper_output_up2(const IdxT *lv, const uint32_t *pal, uint32_t P, uint32_t *dst) {
+    const uint32_t L = lane();
+    const IdxT *res = lv + kLvOff[1];
+    auto rows = [&](auto al16) {
+        for (uint32_t e = 4 * L; e < 32768u; e += 256) {
+            const uint32_t x0 = e & 31u, yy = (e >> 5) & 31u, zz = e >> 10;
+            // x0 / 2 is even: its +1 neighbour in x differs in Morton bit 0
+            const uint32_t m0 = spread4(x0 >> 1) | (spread4(yy >> 1) << 1) | (spread4(zz >> 1) << 2);
+            const uint32_t a = pal_at<kG>(pal, res[m0], P), b = pal_at<kG>(pal, res[m0 | 1u], P);
+            store4<decltype(al16)::value>(dst + e, make_uint4(a, a, b, b));
+        }
+    };
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) rows(std::true_type{});
+    else rows(std::false_type{});
+}
+
 // one brick of the front kernel after its entropy decode; false on a
 // malformed stream
 template <class IdxT, bool kG>
@@ -949,7 +1001,8 @@ __device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, con
             wsync();
             pal = sp;
         }
-        upper_output<IdxT, kG>(lv, h.t, pal, h.P, dst);
+        if (h.up) upper_output_up2<IdxT, kG>(lv, pal, h.P, dst);
+        else upper_output<IdxT, kG>(lv, h.t, pal, h.P, dst);
         return true;
     }
     // t = 0: hand L_1 to the leaf kernel
@@ -995,6 +1048,10 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         Hdr h;
         uint32_t *dst, count, fill;
         const ReqKind kind = load_request(a, rq, h, dst, count, fill);
+        if (l.words_out && kind != kReqDecode) {
+            if (L == 0) l.words_out[rq] = kind == kReqFill ? 0u : 0xFFFFFFFFu;
+            continue;
+        }
         if (kind == kReqBadLod) {
             if (L == 0) report(a.err, CSV_ERANGE, rq);
             continue;
@@ -1005,18 +1062,29 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             fill_labels<64>(dst, count, kind == kReqFill ? fill : 0u, L);
             continue;
         }
+        if (h.up && L == 0) report(a.err, CSV_EDETAIL, h.id);
         const uint32_t n = h.c(h.t);
         uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
         uint32_t *nib = reinterpret_cast<uint32_t *>(slot);
         if (n + 16 > 8 * l.slot_dw) {  // the slots are sized for the pool's largest brick
             if (L == 0) report(a.err, CSV_EINVAL, h.id);
-            fill_labels<64>(dst, count, 0u, L);
+            if (l.words_out) {
+                if (L == 0) l.words_out[rq] = 0xFFFFFFFFu;
+            } else {
+                fill_labels<64>(dst, count, 0u, L);
+            }
             continue;
         }
         // the packed nibbles go to the slot, and their first kWDeltaDw dwords
         // also to the wave's staging area (the upper levels read them there)
+        uint32_t words = 0;
         bool ok = entropy_decode<kLutLds>(a, h, slut, reinterpret_cast<uint32_t *>(wl),
-                                          nib, reinterpret_cast<uint32_t *>(wl + kWPal), n);
+                                          nib, reinterpret_cast<uint32_t *>(wl + kWPal), n, words);
+        if (l.words_out) {
+            if (L == 0) l.words_out[rq] = ok ? words : 0xFFFFFFFFu;
+            wsync();
+            continue;
+        }
         phase_mark(rq, 1);
         // this wave's nibble stores before its own loads of them
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1639,6 +1707,21 @@ struct csv_pool {
     uint32_t generation = 0;                  // bumped when device tables move
     csv_shape shape{16, 3, 1, 0, 0.f};        // launch shape of csv_decode_bricks
     uint64_t record_bytes = 0;
+    // level-0 detail in host memory (csv_pool_add_volume_ex, CSV_DETAIL_HOST)
+    bool any_split = false;
+    std::vector<uint32_t> pfx_dw;            // per brick: word dwords in the device record (~0u: all)
+    std::vector<const uint8_t *> det_host;   // per brick: the remaining dwords in pinned host memory
+    std::vector<uint32_t> det_bytes;
+    std::vector<uint8_t> staged;             // per brick: its detail is in the staging buffer
+    std::vector<void *> host_bufs;           // pinned detail buffers
+    uint64_t host_bytes = 0;
+    uint32_t *d_pfx_dw = nullptr;
+    uint64_t *d_sfx = nullptr;               // per brick: device address of the staged detail (0: none)
+    uint64_t *h_sfx = nullptr;               // its pinned host image (n_sfx entries)
+    uint32_t n_sfx = 0;
+    uint8_t *d_stage = nullptr, *h_stage = nullptr;  // staging buffer and its pinned host image
+    uint64_t stage_cap = 8ull << 20, stage_used = 0, stage_alloc = 0;
+    hipEvent_t stage_ev = nullptr;           // the last staging copies
     std::mutex mu;
 };
 
@@ -1666,6 +1749,35 @@ int upload(T **dptr, const std::vector<T> &h) {
     if (hipMalloc(reinterpret_cast<void **>(dptr), sizeof(T) * h.size()) != hipSuccess) return CSV_ENOMEM;
     if (hipMemcpy(*dptr, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice) != hipSuccess) return CSV_EHIP;
     return CSV_OK;
+}
+
+// the per-brick arrays of pools with level-0 detail in host memory, sized to
+// the pool's bricks (bricks of ordinary volumes keep their whole record);
+// staged detail stays staged
+int sync_split(csv_pool *p) {
+    if (!p->any_split) return CSV_OK;
+    const size_t nb = p->rec_ptr.size();
+    p->pfx_dw.resize(nb, 0xFFFFFFFFu);
+    p->det_host.resize(nb, nullptr);
+    p->det_bytes.resize(nb, 0u);
+    p->staged.resize(nb, 0u);
+    int rc = upload(&p->d_pfx_dw, p->pfx_dw);
+    if (rc) return rc;
+    if (p->n_sfx != nb) {
+        uint64_t *h = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void **>(&h), 8 * nb, hipHostMallocDefault) != hipSuccess) return CSV_ENOMEM;
+        std::memset(h, 0, 8 * nb);
+        if (p->h_sfx) {
+            std::memcpy(h, p->h_sfx, 8ull * p->n_sfx);
+            (void)hipHostFree(p->h_sfx);
+        }
+        p->h_sfx = h;
+        (void)hipFree(p->d_sfx);
+        p->d_sfx = nullptr;
+        if (hipMalloc(reinterpret_cast<void **>(&p->d_sfx), 8 * nb) != hipSuccess) return CSV_ENOMEM;
+        p->n_sfx = (uint32_t)nb;
+    }
+    return hipMemcpy(p->d_sfx, p->h_sfx, 8ull * p->n_sfx, hipMemcpyHostToDevice) == hipSuccess ? CSV_OK : CSV_EHIP;
 }
 
 bool capturing(hipStream_t s) {
@@ -1754,7 +1866,7 @@ uint32_t ref_list_cap() {
 
 int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
            uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
-           bool lpt, LaunchBufs *fixed = nullptr) {
+           bool lpt, LaunchBufs *fixed = nullptr, uint32_t *words_out = nullptr) {
     if (!pool || (n && (!ids || !out))) return CSV_EINVAL;
     if (!lods && lod_scalar > (uint32_t)kLog2) return CSV_ERANGE;
     if (lods && !out_off) return CSV_EINVAL;
@@ -1791,6 +1903,8 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     a.out = out;
     a.n = n;
     a.err = pool->d_err;
+    a.pfx_dw = pool->any_split ? pool->d_pfx_dw : nullptr;
+    a.sfx = pool->any_split ? pool->d_sfx : nullptr;
     // counters: 0 front queue, 1 leaf queue, 2 leaf count, 3 slow count,
     // 4 slow queue, 5 and 6 finished leaf / slow workgroups.  They are zero
     // when a launch starts: zeroed at allocation, then by the last
@@ -1811,6 +1925,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     la.leaf_list = B->leaf_list;
     la.leaf_count = ctr + 2;
     la.base = 0;
+    la.words_out = words_out;
     LaunchB lb;
     lb.arena_bytes = arena_b(groups_b);
     lb.queue = (queue || plain) ? ctr + 1 : nullptr;
@@ -1921,6 +2036,13 @@ void csv_pool_destroy(csv_pool *p) {
     (void)hipFree(p->d_bits);
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_scratch);
+    (void)hipFree(p->d_pfx_dw);
+    (void)hipFree(p->d_sfx);
+    (void)hipFree(p->d_stage);
+    (void)hipHostFree(p->h_sfx);
+    (void)hipHostFree(p->h_stage);
+    for (void *b : p->host_bufs) (void)hipHostFree(b);
+    if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
     for (auto &b : p->bufs) b.release();
     delete p;
 }
@@ -1990,9 +2112,201 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
             for (uint32_t q = 0; q < info.freq[tb][s]; q++) p->luts.push_back(csv::lut_entry(s, q, info.freq[tb][s]));
     if ((rc = upload(&p->d_rec_ptr, p->rec_ptr)) || (rc = upload(&p->d_rec_size, p->rec_size)) ||
         (rc = upload(&p->d_rec_vol, p->rec_vol)) || (rc = upload(&p->d_luts, p->luts)) ||
-        (rc = upload(&p->d_lut_off, p->lut_off)) || (rc = upload(&p->d_bits, p->bits)))
+        (rc = upload(&p->d_lut_off, p->lut_off)) || (rc = upload(&p->d_bits, p->bits)) || (rc = sync_split(p)))
         return rc;
     if (first_brick_id) *first_brick_id = first;
+    return CSV_OK;
+}
+
+int csv_pool_add_volume_ex(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uint32_t flags,
+                           uint32_t *first_brick_id) {
+    if (!p || !blob || (flags & ~(uint32_t)CSV_DETAIL_HOST)) return CSV_EINVAL;
+    uint32_t first = 0;
+    int rc = csv_pool_add_volume(p, blob, blob_bytes, &first);
+    if (rc) return rc;
+    if (first_brick_id) *first_brick_id = first;
+    if (!(flags & CSV_DETAIL_HOST)) return CSV_OK;
+    csv_volume_info info;
+    if ((rc = csv_blob_info(blob, blob_bytes, &info))) return rc;
+    const uint32_t nb = info.n_bricks;
+    if (nb == 0) return CSV_OK;
+    DeviceGuard g(p->device);
+    // Sec. 4.2: levels >= 1 read a prefix of a brick's word stream; a decode
+    // of every brick to level 1 counts the words of that prefix
+    std::vector<uint32_t> ids(nb), words(nb, 0xFFFFFFFFu);
+    for (uint32_t i = 0; i < nb; i++) ids[i] = first + i;
+    uint32_t *d_ids = nullptr, *d_words = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d_ids), 4ull * nb) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_words), 4ull * nb) != hipSuccess) {
+        (void)hipFree(d_ids);
+        return CSV_ENOMEM;
+    }
+    rc = hipMemcpy(d_ids, ids.data(), 4ull * nb, hipMemcpyHostToDevice) == hipSuccess ? CSV_OK : CSV_EHIP;
+    if (!rc)
+        rc = launch(p, d_ids, nullptr, 1, nullptr, nb, d_words /* not written in this mode */, nullptr, false, 16,
+                    p->shape.groups_per_cu, false, false, nullptr, d_words);
+    if (!rc && (hipDeviceSynchronize() != hipSuccess ||
+                hipMemcpy(words.data(), d_words, 4ull * nb, hipMemcpyDeviceToHost) != hipSuccess))
+        rc = CSV_EHIP;
+    (void)hipFree(d_ids);
+    (void)hipFree(d_words);
+    if (rc) return rc;
+    // bricks whose pass failed keep their whole record (the error stays in the pool's error word);
+    // device records up to the end of that prefix (whole dwords); the rest in pinned host memory
+    const uint64_t rs = csv::record_area_offset(nb);
+    const uint64_t *index = reinterpret_cast<const uint64_t *>(blob + csv::kHeaderBytes);
+    const uint32_t hdr = csv::record_header_words(kLog2);
+    std::vector<uint64_t> keep(nb), det(nb);
+    std::vector<uint32_t> pfx(nb, 0xFFFFFFFFu);
+    uint64_t dev_total = 0, host_total = 0;
+    for (uint32_t i = 0; i < nb; i++) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(blob + rs + index[i]);
+        const uint32_t P = w[0], W = w[1], nw = w[2], ndw = (nw + 1) / 2;
+        keep[i] = index[i + 1] - index[i];
+        det[i] = 0;
+        // (a brick whose level-1 prefix is all its words keeps its whole record)
+        if (words[i] != 0xFFFFFFFFu && words[i] <= nw && (words[i] + 1) / 2 < ndw) {
+            pfx[i] = std::min((words[i] + 1) / 2, ndw);
+            keep[i] = 4ull * (hdr + P + W + pfx[i]);
+            det[i] = 4ull * (ndw - pfx[i]);
+        }
+        dev_total += keep[i];
+        host_total += det[i];
+    }
+    std::vector<uint8_t> img(dev_total);
+    uint8_t *hbuf = nullptr;
+    if (host_total && hipHostMalloc(reinterpret_cast<void **>(&hbuf), host_total, hipHostMallocDefault) != hipSuccess)
+        return CSV_ENOMEM;
+    std::vector<uint64_t> off(nb), hoff(nb);
+    uint64_t o = 0, ho = 0;
+    for (uint32_t i = 0; i < nb; i++) {
+        const uint8_t *r = blob + rs + index[i];
+        std::memcpy(img.data() + o, r, keep[i]);
+        off[i] = o;
+        o += keep[i];
+        if (det[i]) std::memcpy(hbuf + ho, r + keep[i], det[i]);  // the words after the kept prefix
+        hoff[i] = ho;
+        ho += det[i];
+    }
+    void *dbuf = nullptr;
+    if (hipMalloc(&dbuf, dev_total + 64) != hipSuccess) {
+        (void)hipHostFree(hbuf);
+        return CSV_ENOMEM;
+    }
+    if (hipMemcpy(dbuf, img.data(), dev_total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dbuf);
+        (void)hipHostFree(hbuf);
+        return CSV_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    (void)hipDeviceSynchronize();  // nothing may still read the full records
+    const uint64_t old_base = p->rec_ptr[first] - index[0];
+    for (size_t v = 0; v < p->vol_bufs.size(); v++)
+        if (reinterpret_cast<uint64_t>(p->vol_bufs[v]) == old_base) {
+            (void)hipFree(p->vol_bufs[v]);
+            p->vol_bufs[v] = dbuf;
+        }
+    p->record_bytes = p->record_bytes - info.record_bytes + dev_total;
+    p->any_split = true;
+    p->pfx_dw.resize(p->rec_ptr.size(), 0xFFFFFFFFu);
+    p->det_host.resize(p->rec_ptr.size(), nullptr);
+    p->det_bytes.resize(p->rec_ptr.size(), 0u);
+    for (uint32_t i = 0; i < nb; i++) {
+        p->rec_ptr[first + i] = reinterpret_cast<uint64_t>(dbuf) + off[i];
+        p->rec_size[first + i] = (uint32_t)keep[i];
+        p->pfx_dw[first + i] = pfx[i];
+        p->det_host[first + i] = det[i] ? hbuf + hoff[i] : nullptr;
+        p->det_bytes[first + i] = (uint32_t)det[i];
+    }
+    if (hbuf) p->host_bufs.push_back(hbuf);
+    p->host_bytes += host_total;
+    p->generation++;
+    if ((rc = upload(&p->d_rec_ptr, p->rec_ptr)) || (rc = upload(&p->d_rec_size, p->rec_size)) ||
+        (rc = sync_split(p)))
+        return rc;
+    return CSV_OK;
+}
+
+int csv_pool_set_detail_staging(csv_pool *p, uint64_t bytes) {
+    if (!p || bytes < 4096 || bytes > (1ull << 36)) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->stage_used) return CSV_EBUSY;  // release the staged detail first
+    DeviceGuard g(p->device);
+    if (p->stage_ev) (void)hipEventSynchronize(p->stage_ev);
+    if (p->stage_alloc != bytes) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p->d_stage);
+        (void)hipHostFree(p->h_stage);
+        p->d_stage = p->h_stage = nullptr;
+        p->stage_alloc = 0;
+    }
+    p->stage_cap = bytes;
+    return CSV_OK;
+}
+
+int csv_pool_stage_detail(csv_pool *p, const uint32_t *ids, uint32_t n, void *stream, uint32_t *n_done) {
+    if (!p || (n && !ids) || !n_done) return CSV_EINVAL;
+    *n_done = 0;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->any_split) {
+        *n_done = n;
+        return CSV_OK;
+    }
+    DeviceGuard g(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!p->d_stage) {
+        if (hipMalloc(reinterpret_cast<void **>(&p->d_stage), p->stage_cap) != hipSuccess) return CSV_ENOMEM;
+        if (hipHostMalloc(reinterpret_cast<void **>(&p->h_stage), p->stage_cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipFree(p->d_stage);
+            p->d_stage = nullptr;
+            return CSV_ENOMEM;
+        }
+        p->stage_alloc = p->stage_cap;
+    }
+    if (!p->stage_ev && hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming) != hipSuccess) return CSV_EHIP;
+    (void)hipEventSynchronize(p->stage_ev);  // the host images are not read by earlier copies any more
+    const uint64_t start = p->stage_used;
+    const uint32_t nb = (uint32_t)p->rec_ptr.size();
+    uint32_t i = 0;
+    for (; i < n; i++) {
+        const uint32_t id = ids[i];
+        if (id >= nb) break;
+        if (p->pfx_dw[id] == 0xFFFFFFFFu || p->staged[id] || !p->det_bytes[id]) continue;
+        const uint64_t b = p->det_bytes[id], b16 = (b + 15) & ~15ull;
+        if (p->stage_used + b16 > p->stage_alloc) break;
+        std::memcpy(p->h_stage + p->stage_used, p->det_host[id], b);
+        p->h_sfx[id] = reinterpret_cast<uint64_t>(p->d_stage) + p->stage_used;
+        p->staged[id] = 1;
+        p->stage_used += b16;
+    }
+    const bool bad_id = i < n && ids[i] >= nb;
+    *n_done = i;
+    if (p->stage_used > start) {
+        if (hipMemcpyAsync(p->d_stage + start, p->h_stage + start, p->stage_used - start, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(p->d_sfx, p->h_sfx, 8ull * p->n_sfx, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipEventRecord(p->stage_ev, s) != hipSuccess)
+            return CSV_EHIP;
+    }
+    return bad_id ? CSV_ERANGE : CSV_OK;
+}
+
+int csv_pool_release_detail(csv_pool *p, void *stream) {
+    if (!p) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->any_split || !p->stage_used) return CSV_OK;
+    DeviceGuard g(p->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    (void)hipEventSynchronize(p->stage_ev);
+    for (size_t id = 0; id < p->staged.size(); id++)
+        if (p->staged[id]) {
+            p->staged[id] = 0;
+            p->h_sfx[id] = 0;
+        }
+    p->stage_used = 0;
+    if (hipMemcpyAsync(p->d_sfx, p->h_sfx, 8ull * p->n_sfx, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(p->stage_ev, s) != hipSuccess)
+        return CSV_EHIP;
     return CSV_OK;
 }
 
@@ -2001,10 +2315,13 @@ int csv_pool_info_get(const csv_pool *p, csv_pool_info *info) {
     info->n_volumes = (uint32_t)p->bits.size();
     info->n_bricks = (uint32_t)p->rec_ptr.size();
     info->device = p->device;
+    info->pad = 0;
     uint64_t lb = 0;
     for (const auto &b : p->bufs) lb += b.bytes();
     info->device_bytes = p->record_bytes + p->rec_ptr.size() * (8 + 4 + 2) + p->luts.size() * 4 +
-                         (uint64_t)p->slot_bytes * (p->d_scratch ? p->n_slots : 0) + lb;
+                         (uint64_t)p->slot_bytes * (p->d_scratch ? p->n_slots : 0) + lb +
+                         (p->any_split ? p->rec_ptr.size() * (4 + 8) + p->stage_alloc : 0);
+    info->host_bytes = p->host_bytes;
     return CSV_OK;
 }
 

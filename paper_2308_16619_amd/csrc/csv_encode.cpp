@@ -290,6 +290,7 @@ const char *csv_strerror(int code) {
         case CSV_ENOMEM: return "out of memory";
         case CSV_EHIP: return "HIP runtime error";
         case CSV_EBUSY: return "busy";
+        case CSV_EDETAIL: return "level-0 detail not on the device (level 1 upsampled)";
         default: return "unknown error";
     }
 }

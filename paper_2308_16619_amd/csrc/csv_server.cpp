@@ -532,7 +532,8 @@ int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out
     csv_pool_info info;
     int rc = csv_pool_info_get(pool, &info);
     if (rc) return rc;
-    if (info.n_bricks == 0) return CSV_EINVAL;
+    // a full-LOD miss must not be served (and cached) from level 1
+    if (info.n_bricks == 0 || info.host_bytes) return CSV_EINVAL;
     csv_server *s = new (std::nothrow) csv_server;
     if (!s) return CSV_ENOMEM;
     s->pool = pool;

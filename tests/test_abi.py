@@ -42,6 +42,19 @@ def test_visibility_test_rejects_a_missing_pool():
     assert L.csv_bricks_visible(None, ctypes.c_void_p(16), 4, None, 0, ctypes.c_void_p(16), None) == csv.CSV_EINVAL
 
 
+def test_detail_separation_rejects_a_missing_pool():
+    import paper_2308_16619_amd as csv
+    L = csv.lib()
+    src = open(os.path.join(ROOT, "include", "csv.h")).read()
+    assert int(re.search(r"#define CSV_DETAIL_HOST (\d+)u", src).group(1)) == csv.CSV_DETAIL_HOST
+    done = ctypes.c_uint32(7)
+    assert L.csv_pool_add_volume_ex(None, b"x", 1, csv.CSV_DETAIL_HOST, None) == csv.CSV_EINVAL
+    assert L.csv_pool_stage_detail(None, None, 0, None, ctypes.byref(done)) == csv.CSV_EINVAL
+    assert L.csv_pool_release_detail(None, None) == csv.CSV_EINVAL
+    assert L.csv_pool_set_detail_staging(None, 1 << 20) == csv.CSV_EINVAL
+    assert L.csv_strerror(csv.CSV_EDETAIL) != b"unknown error"
+
+
 def test_strerror():
     import paper_2308_16619_amd as csv
     assert csv.lib().csv_strerror(-3) == b"corrupt data"
