@@ -80,6 +80,22 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
 
 void csv_free(void *p);
 
+/*
+ * The same container as csv_encode_volume, byte for byte, compressed on the
+ * GPU (Sec. 3: pyramid, operations, two sampled frequency tables,
+ * interleaved rANS; the paper leaves a GPU encoder to future work, Sec. 5.1).
+ * labels: device memory of `device`, nx*ny*nz uint32, x fastest; the work
+ * runs on `stream` (NULL: the null stream) and the call returns when the
+ * blob is in host memory (*blob, release with csv_free).  Only 32^3 bricks
+ * (opts->brick_log2 5); opts->threads is ignored.  Device scratch of about
+ * 430 KiB per workgroup (4 per CU) plus the records is allocated for the
+ * call.  Errors: CSV_EINVAL (null pointers, zero dims, options out of
+ * range, a bad device), CSV_ERANGE (2^32 or more bricks), CSV_ENOMEM,
+ * CSV_EHIP.
+ */
+int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t nz, const csv_encode_opts *opts,
+                          int device, void *stream, uint8_t **blob, size_t *blob_bytes);
+
 typedef struct {
     uint32_t nx, ny, nz, brick_log2, nbx, nby, nbz, n_bricks;
     uint32_t scale_bits, lane_k, lane_max, sample_stride;

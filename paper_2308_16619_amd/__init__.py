@@ -88,6 +88,8 @@ def lib():
         L.csv_encode_opts_default.argtypes = [ctypes.POINTER(EncodeOpts)]
         L.csv_encode_volume.argtypes = [vp, u32, u32, u32, ctypes.POINTER(EncodeOpts), ctypes.POINTER(vp),
                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.csv_encode_volume_gpu.argtypes = [vp, u32, u32, u32, ctypes.POINTER(EncodeOpts), i32, vp,
+                                            ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
         L.csv_free.argtypes = [vp]
         L.csv_blob_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(VolumeInfo)]
         L.csv_pool_create.argtypes = [ctypes.POINTER(vp), i32]
@@ -147,6 +149,30 @@ def encode_volume(vol: np.ndarray, brick_log2: int = 5, scale_bits: int = 10, la
     n = ctypes.c_size_t()
     _chk(L.csv_encode_volume(_np_ptr(vol), nx, ny, nz, ctypes.byref(o), ctypes.byref(p), ctypes.byref(n)),
          "csv_encode_volume")
+    try:
+        return ctypes.string_at(p, n.value)
+    finally:
+        L.csv_free(p)
+
+
+def encode_volume_gpu(vol, brick_log2: int = 5, scale_bits: int = 10, lane_k: int = 64, lane_max: int = 64,
+                      sample_stride: int = 0, stream=None) -> bytes:
+    """Compress a (nz, ny, nx) label volume on the GPU (same blob as
+    encode_volume).  vol: a CUDA tensor of 4-byte labels (int32 or uint32
+    bit patterns), or a numpy array, which is uploaded first."""
+    import torch
+    L = lib()
+    if not isinstance(vol, torch.Tensor):
+        vol = torch.from_numpy(np.ascontiguousarray(vol, dtype=np.uint32).view(np.int32)).cuda()
+    if not vol.is_cuda or vol.dim() != 3 or vol.element_size() != 4:
+        raise ValueError("vol must be a 3-d CUDA tensor of 4-byte labels")
+    vol = vol.contiguous()
+    nz, ny, nx = vol.shape
+    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, 0)
+    p = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    _chk(L.csv_encode_volume_gpu(ctypes.c_void_p(vol.data_ptr()), nx, ny, nz, ctypes.byref(o), vol.device.index or 0,
+                                 _stream_handle(stream), ctypes.byref(p), ctypes.byref(n)), "csv_encode_volume_gpu")
     try:
         return ctypes.string_at(p, n.value)
     finally:

@@ -277,6 +277,10 @@ void parallel_for(uint64_t n, unsigned threads, F &&fn) {
 
 }  // namespace
 
+namespace csv {
+void normalize_counts(const uint64_t cnt[16], uint32_t M, uint32_t f[16]) { normalize(cnt, M, f); }
+}  // namespace csv
+
 extern "C" {
 
 uint32_t csv_abi_version(void) { return CSV_ABI_VERSION; }

@@ -1,0 +1,574 @@
+// GPU compressor for 32^3 bricks: the container of csv_encode_volume, byte
+// for byte, built on the device from a label volume resident in HBM.
+//
+//   resolution pyramid (Sec. 3.1)      level 1 from the volume, levels 2..5
+//                                      in LDS; level 0 read where needed
+//   operations (Sec. 3.2, Alg. 2)      per child level, the children of the
+//                                      expanded parents in Morton order: the
+//                                      reuse operations (parent, neighbours)
+//                                      in parallel, then the palette
+//                                      operations of the remaining children
+//                                      in order by one wavefront holding the
+//                                      last 17 palette entries in its lanes
+//   frequency tables (Sec. 3.3, 3.4)   a counting pass over the sampled
+//                                      bricks, normalised on the host
+//   interleaved rANS (Sec. 3.3)        one wavefront, one state per lane,
+//                                      symbols from last to first; the words
+//                                      of a step are placed by ballot
+//   packing                            records into an arena, a device scan
+//                                      of record sizes, one copy kernel
+//
+// One 256-thread workgroup encodes one brick at a time (persistent grid);
+// per-workgroup scratch in global memory holds the symbol stream, palette
+// and words of the brick in flight.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "csv.h"
+#include "csv_format.hpp"
+
+namespace csv {
+// frequency normalisation of the host compressor (same arithmetic, one copy)
+void normalize_counts(const uint64_t cnt[16], uint32_t M, uint32_t f[16]);
+}
+
+namespace {
+
+constexpr int kN = 5;
+constexpr uint32_t kThreads = 256;
+constexpr uint32_t kNodes = 4681;           // levels 1..5 of a 32^3 brick
+constexpr uint32_t kMaxChildren = 37448;    // 8 * (1 + 8 + 64 + 512 + 4096)
+constexpr uint32_t kMaxSym = 2 * kMaxChildren;  // operations and deltas
+// per-workgroup scratch (bytes)
+constexpr size_t kOffSym = 0;
+constexpr size_t kOffOps = 76800;           // >= kMaxSym
+constexpr size_t kOffDel = kOffOps + 32768;
+constexpr size_t kOffPal = kOffDel + 32768;
+constexpr size_t kOffWords = kOffPal + 4 * 37456;  // palette <= kMaxChildren + 1
+constexpr size_t kScratch = kOffWords + 2 * (size_t)kMaxSym + 64;
+
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0xFF0000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
+}
+// Morton index: bit 0 of each 3-bit group is x, then y, then z
+__device__ __forceinline__ uint32_t morton(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+// offset of level l (1..5) in the LDS node arrays
+__device__ __forceinline__ uint32_t lvl_off(int l) {
+    return l == 1 ? 0u : (l == 2 ? 4096u : (l == 3 ? 4608u : (l == 4 ? 4672u : 4680u)));
+}
+
+struct EncArgs {
+    const uint32_t *vol;
+    uint32_t nx, ny, nz, nbx, nby;
+    uint32_t n_items, stride;  // item i encodes brick i * stride
+    uint32_t count_mode;       // 1: symbol histograms of the items only
+    unsigned long long *hist;  // count mode: 2 x 16 counters
+    uint32_t f[2][16], c[2][16];
+    uint32_t bits, lane_k, lane_max;
+    uint8_t *scratch;
+    uint8_t *arena;
+    uint64_t arena_cap;
+    unsigned long long *arena_top;
+    uint32_t *sizes;  // per brick: record bytes
+    uint64_t *aoff;   // per brick: record offset in the arena
+};
+
+struct Brick {
+    uint64_t x0, y0, z0;
+};
+
+__device__ __forceinline__ uint32_t voxel(const EncArgs &a, const Brick &b, uint32_t cx, uint32_t cy, uint32_t cz) {
+    const uint64_t x = b.x0 + cx, y = b.y0 + cy, z = b.z0 + cz;
+    if (x < a.nx && y < a.ny && z < a.nz) return a.vol[x + (uint64_t)a.nx * (y + (uint64_t)a.ny * z)];
+    return 0u;  // padding beyond the volume
+}
+
+// label of node j (Morton) on level m
+__device__ __forceinline__ uint32_t label_at(const EncArgs &a, const Brick &b, const uint32_t *lab, int m, uint32_t j) {
+    if (m >= 1) return lab[lvl_off(m) + j];
+    return voxel(a, b, compact3(j), compact3(j >> 1), compact3(j >> 2));
+}
+
+// rank of this thread's flag among the workgroup's set flags, and their count
+__device__ __forceinline__ uint32_t wg_rank(bool f, uint32_t &total, uint32_t *wcnt) {
+    const uint64_t m = __ballot(f);
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane() == 0) wcnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kThreads / 64; k++) {
+        const uint32_t c = wcnt[k];
+        before += k < w ? c : 0u;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return before + mbcnt(m);
+}
+
+__device__ __forceinline__ uint32_t lanes_for(uint32_t n, uint32_t K, uint32_t Wmax) {
+    if (n == 0) return 0;
+    uint32_t W = 1;
+    while (2 * W <= Wmax && (uint64_t)2 * W * K <= n) W *= 2;
+    return W;
+}
+
+// the most frequent of 8 children, the earliest winning a tie; same: all equal
+__device__ __forceinline__ uint32_t mode8(const uint32_t ch[8], bool &same) {
+    same = true;
+#pragma unroll
+    for (int k = 1; k < 8; k++) same &= ch[k] == ch[0];
+    if (same) return ch[0];
+    int bestk = 0, bestn = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        int n = 0;
+#pragma unroll
+        for (int r = 0; r < 8; r++) n += ch[r] == ch[k];
+        if (n > bestn) {
+            bestn = n;
+            bestk = k;
+        }
+    }
+    uint32_t v = ch[0];
+#pragma unroll
+    for (int k = 1; k < 8; k++) v = k == bestk ? ch[k] : v;
+    return v;
+}
+
+__global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
+    __shared__ uint32_t lab[kNodes];
+    __shared__ uint8_t cst[kNodes];
+    __shared__ uint16_t expl[4096];
+    __shared__ uint32_t c_lab[kThreads];
+    __shared__ uint8_t c_op[kThreads];
+    __shared__ uint32_t wcnt[kThreads / 64];
+    __shared__ uint32_t share[8];  // 0: deltas of a level; 1..3: words, states, palette; 4, 5: arena offset
+    __shared__ uint32_t s_cum[kN];
+    __shared__ uint32_t xs[64];
+    __shared__ uint32_t tf[2][16], tc[2][16];
+    __shared__ uint32_t hist_l[32];
+    const uint32_t t = threadIdx.x, L = lane(), w = t >> 6;
+    uint8_t *scr = a.scratch + (size_t)blockIdx.x * kScratch;
+    uint8_t *sym = scr + kOffSym;
+    uint8_t *ops = scr + kOffOps;
+    uint8_t *dels = scr + kOffDel;
+    uint32_t *pal = reinterpret_cast<uint32_t *>(scr + kOffPal);
+    uint16_t *words = reinterpret_cast<uint16_t *>(scr + kOffWords);
+    if (t < 32) {
+        tf[t >> 4][t & 15] = a.f[t >> 4][t & 15];
+        tc[t >> 4][t & 15] = a.c[t >> 4][t & 15];
+    }
+    for (uint32_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+        const uint64_t id = (uint64_t)item * a.stride;
+        Brick b;
+        b.x0 = (id % a.nbx) * 32;
+        b.y0 = ((id / a.nbx) % a.nby) * 32;
+        b.z0 = (id / ((uint64_t)a.nbx * a.nby)) * 32;
+        // level 1 from the volume (every level-0 node is a constant subtree)
+        for (uint32_t q = t; q < 4096; q += kThreads) {
+            const uint32_t x = 2 * compact3(q), y = 2 * compact3(q >> 1), z = 2 * compact3(q >> 2);
+            uint32_t ch[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) ch[k] = voxel(a, b, x + (k & 1), y + ((k >> 1) & 1), z + (k >> 2));
+            bool same;
+            lab[q] = mode8(ch, same);
+            cst[q] = same ? 1 : 0;
+        }
+        __syncthreads();
+        for (int l = 2; l <= kN; l++) {
+            const uint32_t n = 1u << (3 * (kN - l)), lo = lvl_off(l - 1), hi = lvl_off(l);
+            for (uint32_t q = t; q < n; q += kThreads) {
+                uint32_t ch[8];
+                bool allc = true;
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    ch[k] = lab[lo + 8 * q + k];
+                    allc &= cst[lo + 8 * q + k] != 0;
+                }
+                bool same;
+                lab[hi + q] = mode8(ch, same);
+                cst[hi + q] = (same && allc) ? 1 : 0;
+            }
+            __syncthreads();
+        }
+        // symbol stream: child levels 4 .. 0
+        uint32_t win = 0, P = 1, D = 0;  // wavefront 0: palette window (lane i: entry P-1-i), size, deltas
+        if (w == 0 && L == 0) {
+            win = lab[lvl_off(kN)];
+            pal[0] = win;
+        }
+        uint32_t base = 0;
+        for (int m = kN - 1; m >= 0; m--) {
+            const int l = m + 1;
+            const uint32_t np = 1u << (3 * (kN - l)), G = 32u >> m;
+            uint32_t E = 0;
+            for (uint32_t q0 = 0; q0 < np; q0 += kThreads) {
+                const uint32_t q = q0 + t;
+                const bool f = q < np && !cst[lvl_off(l) + q];
+                uint32_t tot;
+                const uint32_t r = wg_rank(f, tot, wcnt);
+                if (f) expl[E + r] = (uint16_t)q;
+                E += tot;
+            }
+            __syncthreads();
+            D = 0;
+            for (uint32_t s0 = 0; s0 < 8 * E; s0 += kThreads) {
+                const uint32_t s = s0 + t;
+                const bool valid = s < 8 * E;
+                uint32_t op = csv::kPa, stop = 0, lbl = 0;
+                if (valid) {
+                    const uint32_t q = expl[s >> 3], j = 8 * q + (s & 7);
+                    lbl = label_at(a, b, lab, m, j);
+                    stop = (m >= 1 && cst[lvl_off(m) + j]) ? 1u : 0u;
+                    if (lab[lvl_off(l) + q] == lbl) {
+                        op = csv::kRp;
+                    } else {
+                        const uint32_t cx = compact3(j), cy = compact3(j >> 1), cz = compact3(j >> 2);
+                        for (uint32_t ax = 0; ax < 3 && op == csv::kPa; ax++) {
+                            const uint32_t c = ax == 0 ? cx : (ax == 1 ? cy : cz);
+                            uint32_t v;
+                            if ((c & 1u) == 0) {  // the same-level node at -1
+                                if (c == 0) continue;
+                                v = label_at(a, b, lab, m, morton(cx - (ax == 0), cy - (ax == 1), cz - (ax == 2)));
+                            } else {  // the parent of the node at +1
+                                if (c + 1 >= G) continue;
+                                v = lab[lvl_off(l) + morton((cx + (ax == 0)) >> 1, (cy + (ax == 1)) >> 1,
+                                                            (cz + (ax == 2)) >> 1)];
+                            }
+                            if (v == lbl) op = csv::kRx + ax;
+                        }
+                    }
+                }
+                const bool cand = valid && op == csv::kPa;
+                uint32_t nc;
+                const uint32_t r = wg_rank(cand, nc, wcnt);
+                if (cand) c_lab[r] = lbl;
+                __syncthreads();
+                if (w == 0) {
+                    // palette operations in order: P_0, else the smallest delta
+                    // among the 16 entries before it, else append
+                    for (uint32_t c = 0; c < nc; c++) {
+                        const uint32_t lc = c_lab[c];
+                        const uint64_t mm = __ballot(L <= 16 && L < P && win == lc);
+                        uint32_t o;
+                        if (mm & 1ull) {
+                            o = csv::kP0;
+                        } else if (mm) {
+                            o = csv::kPd;
+                            if (L == 0) dels[D] = (uint8_t)(__builtin_ctzll(mm) - 1);
+                            D++;
+                        } else {
+                            o = csv::kPa;
+                            win = __shfl_up(win, 1u);
+                            if (L == 0) {
+                                win = lc;
+                                pal[P] = lc;
+                            }
+                            P++;
+                        }
+                        if (L == 0) c_op[c] = (uint8_t)o;
+                    }
+                }
+                __syncthreads();
+                if (valid) ops[s] = (uint8_t)((cand ? c_op[r] : op) | (stop << 3));
+            }
+            if (t == 0) share[0] = D;
+            __syncthreads();
+            const uint32_t nd = share[0];
+            // a level's delta nibbles precede its operation nibbles
+            for (uint32_t i = t; i < nd; i += kThreads) sym[base + i] = dels[i];
+            for (uint32_t i = t; i < 8 * E; i += kThreads) sym[base + nd + i] = ops[i];
+            base += nd + 8 * E;
+            if (t == 0) s_cum[m] = base;
+            __syncthreads();
+        }
+        const uint32_t n = base, leaf = s_cum[1];
+        if (a.count_mode) {
+            if (t < 32) hist_l[t] = 0;
+            __syncthreads();
+            for (uint32_t i = t; i < n; i += kThreads) atomicAdd(&hist_l[(i >= leaf ? 16u : 0u) + sym[i]], 1u);
+            __syncthreads();
+            if (t < 32 && hist_l[t]) atomicAdd(&a.hist[t], (unsigned long long)hist_l[t]);
+            __syncthreads();
+            continue;
+        }
+        // interleaved rANS, symbols from last to first: symbol i to state i mod W
+        if (w == 0) {
+            const uint32_t W = lanes_for(n, a.lane_k, a.lane_max);
+            const uint64_t xmax_unit = (uint64_t)((csv::kRansLower >> a.bits) << 16);
+            uint32_t x = csv::kRansLower, pushed = 0;
+            if (n) {
+                for (int64_t s = (int64_t)((n - 1) / W); s >= 0; s--) {
+                    const uint32_t i = (uint32_t)s * W + L;
+                    const bool act = L < W && i < n;
+                    bool emit = false;
+                    uint32_t wd = 0;
+                    if (act) {
+                        const uint32_t tb = i >= leaf ? 1u : 0u, sy = sym[i];
+                        const uint32_t f = tf[tb][sy], c = tc[tb][sy];
+                        uint32_t v = x;
+                        if ((uint64_t)v >= xmax_unit * f) {
+                            emit = true;
+                            wd = v & 0xFFFFu;
+                            v >>= 16;
+                        }
+                        x = ((v / f) << a.bits) + v % f + c;
+                    }
+                    // the host order within a step is descending lanes
+                    const uint64_t em = __ballot(emit);
+                    if (emit) words[pushed + (uint32_t)__popcll(L == 63 ? 0ull : (em >> (L + 1)))] = (uint16_t)wd;
+                    pushed += (uint32_t)__popcll(em);
+                }
+            }
+            if (L < W) xs[L] = x;
+            if (L == 0) {
+                share[1] = pushed;
+                share[2] = W;
+                share[3] = P;
+            }
+        }
+        __syncthreads();
+        const uint32_t nw = share[1], W = share[2], Pn = share[3];
+        const uint32_t hdr = csv::record_header_words(kN);
+        const uint32_t size = (4 * (hdr + Pn + W) + 2 * nw + 3) & ~3u;
+        if (t == 0) {
+            const uint64_t off = atomicAdd(a.arena_top, (unsigned long long)size);
+            a.sizes[id] = size;
+            a.aoff[id] = off;
+            share[4] = (uint32_t)off;
+            share[5] = (uint32_t)(off >> 32);
+        }
+        __syncthreads();
+        const uint64_t off = ((uint64_t)share[5] << 32) | share[4];
+        if (off + size <= a.arena_cap) {
+            uint32_t *r = reinterpret_cast<uint32_t *>(a.arena + off);
+            if (t == 0) {
+                r[0] = Pn;
+                r[1] = W;
+                r[2] = nw;
+                for (int m = 0; m < kN; m++) r[3 + m] = s_cum[m];
+            }
+            for (uint32_t i = t; i < Pn; i += kThreads) r[hdr + i] = pal[i];
+            for (uint32_t i = t; i < W; i += kThreads) r[hdr + Pn + i] = xs[i];
+            uint16_t *wr = reinterpret_cast<uint16_t *>(r + hdr + Pn + W);
+            // the decoder reads words in symbol order: the reverse of the push order
+            for (uint32_t q = t; q < nw; q += kThreads) wr[q] = words[nw - 1 - q];
+            if (t == 0 && (nw & 1u)) wr[nw] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// exclusive scan of the record sizes into the container's u64 index
+__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t *sizes, uint32_t n, uint64_t *index) {
+    __shared__ uint64_t part[1024];
+    const uint32_t t = threadIdx.x;
+    uint64_t carry = 0;
+    for (uint32_t b0 = 0; b0 < n; b0 += 1024) {
+        const uint64_t v = b0 + t < n ? sizes[b0 + t] : 0;
+        part[t] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            const uint64_t o = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += o;
+            __syncthreads();
+        }
+        if (b0 + t < n) index[b0 + t] = carry + part[t] - v;
+        carry += part[1023];
+        __syncthreads();
+    }
+    if (t == 0) index[n] = carry;
+}
+
+// records from the arena to their place in the container's record area
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *arena, const uint64_t *aoff, const uint32_t *sizes,
+                                                   const uint64_t *index, uint32_t n, uint8_t *records) {
+    for (uint32_t id = blockIdx.x; id < n; id += gridDim.x) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(arena + aoff[id]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(records + index[id]);
+        const uint32_t nd = sizes[id] / 4;
+        for (uint32_t i = threadIdx.x; i < nd; i += 256) dst[i] = src[i];
+    }
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    bool alloc(size_t bytes) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        return hipMalloc(&p, std::max<size_t>(bytes, 16)) == hipSuccess;
+    }
+    template <class T>
+    T *as() const {
+        return reinterpret_cast<T *>(p);
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t nz,
+                                     const csv_encode_opts *opts, int device, void *stream, uint8_t **blob,
+                                     size_t *blob_bytes) {
+    if (!labels || !blob || !blob_bytes || !nx || !ny || !nz) return CSV_EINVAL;
+    csv_encode_opts o;
+    csv_encode_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.brick_log2 != (uint32_t)kN || o.scale_bits < 8 || o.scale_bits > 12 || o.lane_k < 1 || o.lane_max < 1 ||
+        o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)))
+        return CSV_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CSV_EINVAL;
+    const uint32_t nbx = (nx + 31) / 32, nby = (ny + 31) / 32, nbz = (nz + 31) / 32;
+    const uint64_t B64 = (uint64_t)nbx * nby * nbz;
+    if (B64 >= (1ull << 32)) return CSV_ERANGE;
+    const uint32_t B = (uint32_t)B64;
+    const uint32_t stride = o.sample_stride ? o.sample_stride : (B64 > (1ull << 20) ? 4096u : 512u);
+    DeviceGuard g(device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1) cu = 1;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(B64, (uint64_t)cu * 4);
+    const uint64_t raw = (uint64_t)nx * ny * nz * 4;
+    uint64_t cap = std::max<uint64_t>(16ull << 20, raw / 8);
+    DevBuf scratch, hist, sizes, aoff, top, arena, dblob;
+    if (!scratch.alloc(kScratch * grid) || !hist.alloc(32 * 8) || !sizes.alloc(4ull * B) || !aoff.alloc(8ull * B) ||
+        !top.alloc(8) || !arena.alloc(cap))
+        return CSV_ENOMEM;
+    EncArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.vol = labels;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.nbx = nbx;
+    a.nby = nby;
+    a.bits = o.scale_bits;
+    a.lane_k = o.lane_k;
+    a.lane_max = o.lane_max;
+    a.scratch = scratch.as<uint8_t>();
+    a.hist = hist.as<unsigned long long>();
+    a.arena_top = top.as<unsigned long long>();
+    a.sizes = sizes.as<uint32_t>();
+    a.aoff = aoff.as<uint64_t>();
+    // prepass: symbol histograms of the sampled bricks
+    const uint32_t n_samples = (uint32_t)((B64 + stride - 1) / stride);
+    a.count_mode = 1;
+    a.n_items = n_samples;
+    a.stride = stride;
+    if (hipMemsetAsync(a.hist, 0, 32 * 8, s) != hipSuccess) return CSV_EHIP;
+    hipLaunchKernelGGL(encode_kernel, dim3(std::min(grid, n_samples)), dim3(kThreads), 0, s, a);
+    uint64_t cnt[2][16];
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(cnt, a.hist, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return CSV_EHIP;
+    uint32_t f[2][16];
+    for (int k = 0; k < 2; k++) {
+        csv::normalize_counts(cnt[k], 1u << o.scale_bits, f[k]);
+        uint32_t c = 0;
+        for (int q = 0; q < 16; q++) {
+            a.f[k][q] = f[k][q];
+            a.c[k][q] = c;
+            c += f[k][q];
+        }
+    }
+    // all bricks; a second pass with the exact arena size if the records did not fit
+    a.count_mode = 0;
+    a.n_items = B;
+    a.stride = 1;
+    uint64_t used = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        a.arena = arena.as<uint8_t>();
+        a.arena_cap = cap;
+        if (hipMemsetAsync(a.arena_top, 0, 8, s) != hipSuccess) return CSV_EHIP;
+        hipLaunchKernelGGL(encode_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&used, a.arena_top, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return CSV_EHIP;
+        if (used <= cap) break;
+        cap = used;
+        if (pass == 1 || !arena.alloc(cap)) return CSV_ENOMEM;
+    }
+    // container: header (host), index (device scan), records (device copy)
+    const uint64_t rs = csv::record_area_offset(B);
+    const uint64_t total = rs + used;
+    if (!dblob.alloc(total)) return CSV_ENOMEM;
+    uint64_t *index = reinterpret_cast<uint64_t *>(dblob.as<uint8_t>() + csv::kHeaderBytes);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a.sizes, B, index);
+    hipLaunchKernelGGL(pack_kernel, dim3(std::min<uint32_t>(B, (uint32_t)cu * 8)), dim3(256), 0, s,
+                       (const uint8_t *)a.arena, (const uint64_t *)a.aoff, (const uint32_t *)a.sizes,
+                       (const uint64_t *)index, B, dblob.as<uint8_t>() + rs);
+    uint8_t *out = static_cast<uint8_t *>(std::malloc(total));
+    if (!out) return CSV_ENOMEM;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(out, dblob.p, total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        std::free(out);
+        return CSV_EHIP;
+    }
+    csv::VolumeHeader h;
+    std::memset(&h, 0, sizeof(h));
+    h.magic = csv::kMagic;
+    h.version = csv::kVersion;
+    h.nx = nx;
+    h.ny = ny;
+    h.nz = nz;
+    h.brick_log2 = (uint32_t)kN;
+    h.nbx = nbx;
+    h.nby = nby;
+    h.nbz = nbz;
+    h.n_bricks = B;
+    h.scale_bits = o.scale_bits;
+    h.lane_k = o.lane_k;
+    h.lane_max = o.lane_max;
+    h.sample_stride = stride;
+    for (int k = 0; k < 2; k++)
+        for (int q = 0; q < 16; q++) h.freq[k][q] = (uint16_t)f[k][q];
+    std::memcpy(out, &h, sizeof(h));
+    const uint64_t idx_end = csv::kHeaderBytes + 8ull * (B + 1);
+    std::memset(out + idx_end, 0, rs - idx_end);  // padding before the record area
+    *blob = out;
+    *blob_bytes = total;
+    return CSV_OK;
+}

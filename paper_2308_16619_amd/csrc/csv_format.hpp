@@ -15,9 +15,9 @@
 //             u32 state[W], u16 words[n_words], zero padding to 4 bytes.
 //
 // Symbol stream of a brick (decoded order): one segment per child level m
-// = N-1 .. 0; a segment holds 8 (op | stop << 3) nibbles per expanded parent
-// in Morton order, then one delta nibble per P_delta operation of the
-// segment, in the same order.  Symbol i belongs to interleaved state
+// = N-1 .. 0; a segment holds one delta nibble per P_delta operation of
+// the segment, in operation order, then 8 (op | stop << 3) nibbles per
+// expanded parent in Morton order.  Symbol i belongs to interleaved state
 // i mod W; words are read in symbol order.
 #pragma once
 #include <cstdint>

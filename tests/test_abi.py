@@ -55,6 +55,15 @@ def test_detail_separation_rejects_a_missing_pool():
     assert L.csv_strerror(csv.CSV_EDETAIL) != b"unknown error"
 
 
+def test_gpu_encoder_rejects_bad_arguments():
+    import paper_2308_16619_amd as csv
+    L = csv.lib()
+    p, n = ctypes.c_void_p(), ctypes.c_size_t()
+    assert L.csv_encode_volume_gpu(None, 4, 4, 4, None, 0, None, ctypes.byref(p), ctypes.byref(n)) == csv.CSV_EINVAL
+    assert L.csv_encode_volume_gpu(ctypes.c_void_p(16), 0, 4, 4, None, 0, None, ctypes.byref(p),
+                                   ctypes.byref(n)) == csv.CSV_EINVAL
+
+
 def test_strerror():
     import paper_2308_16619_amd as csv
     assert csv.lib().csv_strerror(-3) == b"corrupt data"
