@@ -175,6 +175,27 @@ def detail_leg(csv, torch, blob, ids_np, ids, out, shape, whole_pool, reps=10):
             "unstaged_full_lod_ms": round(fb_ms, 4)}
 
 
+def encoder_leg(csv, torch, vol, blob, host_s, host_threads, reps=3):
+    """GPU compression of the volume (labels resident in HBM; the call returns
+    with the container in host memory), checked byte for byte against the
+    host compressor's container, which was timed when the volume was encoded."""
+    d = torch.from_numpy(vol.view(np.int32)).to("cuda:0")
+    torch.cuda.synchronize()
+    got = csv.encode_volume_gpu(d)
+    assert got == blob, "GPU container differs from the host compressor's"
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        csv.encode_volume_gpu(d)
+        ts.append(time.perf_counter() - t0)
+    s = sorted(ts)[len(ts) // 2]
+    raw = vol.nbytes
+    return {"gpu_ms": round(s * 1e3, 2), "gpu_gbs": round(raw / s / 1e9, 2), "host_ms": round(host_s * 1e3, 1),
+            "host_gbs": round(raw / host_s / 1e9, 3), "host_threads": host_threads,
+            "identical_bytes": True, "raw_bytes": raw, "compressed_bytes": len(blob)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +209,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="measured trace length per serving run")
     ap.add_argument("--detail", choices=["full", "none"], default="full",
                     help="detail-separation leg (a second pool of the volume with level-0 detail in host memory)")
+    ap.add_argument("--encoder", choices=["full", "none"], default="full",
+                    help="GPU compressor leg (the same volume compressed on the device)")
     ap.add_argument("--shape", default="", help="fixed launch shape 'waves,groups,queue,lpt' instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for hardware byte counters)")
@@ -209,10 +232,12 @@ def main():
     t0 = time.time()
     vol = synth.cells(n=512, grid=37, p_noise=0.5, seed=2)
     log("generated in %.1fs; encoding" % (time.time() - t0))
-    t0 = time.time()
-    blob = csv.encode_volume(vol)
+    host_threads = 16
+    t0 = time.perf_counter()
+    blob = csv.encode_volume(vol, threads=host_threads)
+    host_s = time.perf_counter() - t0
     info = csv.blob_info(blob)
-    log("encoded in %.1fs: %d bytes, CR %.3f%%" % (time.time() - t0, len(blob), 100.0 * len(blob) / vol.nbytes))
+    log("encoded in %.1fs: %d bytes, CR %.3f%%" % (host_s, len(blob), 100.0 * len(blob) / vol.nbytes))
 
     pool = csv.Pool(0)
     pool.add_volume(blob)
@@ -321,6 +346,11 @@ def main():
         log("detail separation leg")
         detail = detail_leg(csv, torch, blob, ids_np, ids, out, shape, pool)
 
+    encoder = None
+    if args.encoder == "full":
+        log("GPU compressor leg")
+        encoder = encoder_leg(csv, torch, vol, blob, host_s, host_threads)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -370,6 +400,7 @@ def main():
         "plain_per_brick_launch": {"value": round(plain_gbs, 3), "unit": "GB/s", "bricks": nb},
         "visibility_test": visibility,
         "detail_separation": detail,
+        "encoder": encoder,
         "cpu_baseline": cpu,
         "serving": serving,
     }

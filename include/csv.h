@@ -87,14 +87,18 @@ void csv_free(void *p);
  * labels: device memory of `device`, nx*ny*nz uint32, x fastest; the work
  * runs on `stream` (NULL: the null stream) and the call returns when the
  * blob is in host memory (*blob, release with csv_free).  Only 32^3 bricks
- * (opts->brick_log2 5); opts->threads is ignored.  Device scratch of about
- * 430 KiB per workgroup (4 per CU) plus the records is allocated for the
- * call.  Errors: CSV_EINVAL (null pointers, zero dims, options out of
- * range, a bad device), CSV_ERANGE (2^32 or more bricks), CSV_ENOMEM,
- * CSV_EHIP.
+ * (opts->brick_log2 5); opts->threads is ignored.  The call keeps its device
+ * buffers (about 430 KiB per workgroup, 4 workgroups per CU, plus the
+ * records and the container) and a pinned host buffer of the container's
+ * size for later calls on the same device, until csv_encode_gpu_release;
+ * calls on one device run one at a time.  Errors: CSV_EINVAL (null
+ * pointers, zero dims, options out of range, a bad device), CSV_ERANGE
+ * (2^32 or more bricks), CSV_ENOMEM, CSV_EHIP.
  */
 int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t nz, const csv_encode_opts *opts,
                           int device, void *stream, uint8_t **blob, size_t *blob_bytes);
+/* Free the buffers csv_encode_volume_gpu keeps for `device` (waits for the device). */
+int csv_encode_gpu_release(int device);
 
 typedef struct {
     uint32_t nx, ny, nz, brick_log2, nbx, nby, nbz, n_bricks;

@@ -90,6 +90,7 @@ def lib():
                                         ctypes.POINTER(ctypes.c_size_t)]
         L.csv_encode_volume_gpu.argtypes = [vp, u32, u32, u32, ctypes.POINTER(EncodeOpts), i32, vp,
                                             ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
+        L.csv_encode_gpu_release.argtypes = [i32]
         L.csv_free.argtypes = [vp]
         L.csv_blob_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(VolumeInfo)]
         L.csv_pool_create.argtypes = [ctypes.POINTER(vp), i32]
@@ -177,6 +178,11 @@ def encode_volume_gpu(vol, brick_log2: int = 5, scale_bits: int = 10, lane_k: in
         return ctypes.string_at(p, n.value)
     finally:
         L.csv_free(p)
+
+
+def encode_gpu_release(device: int = 0) -> None:
+    """Free the device buffers the GPU compressor keeps between calls."""
+    _chk(lib().csv_encode_gpu_release(device), "csv_encode_gpu_release")
 
 
 def blob_info(blob: bytes) -> dict:

@@ -26,6 +26,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <new>
 #include <vector>
 
 #include "csv.h"
@@ -40,6 +42,9 @@ namespace {
 
 constexpr int kN = 5;
 constexpr uint32_t kThreads = 256;
+constexpr uint32_t kPer = 4;                  // child slots per thread per chunk
+constexpr uint32_t kChunk = kThreads * kPer;
+constexpr uint32_t kNone = 0xFFFFFFFFu;       // no slot
 constexpr uint32_t kNodes = 4681;           // levels 1..5 of a 32^3 brick
 constexpr uint32_t kMaxChildren = 37448;    // 8 * (1 + 8 + 64 + 512 + 4096)
 constexpr uint32_t kMaxSym = 2 * kMaxChildren;  // operations and deltas
@@ -80,6 +85,31 @@ __device__ __forceinline__ uint32_t lvl_off(int l) {
     return l == 1 ? 0u : (l == 2 ? 4096u : (l == 3 ? 4608u : (l == 4 ? 4672u : 4680u)));
 }
 
+// Per-workgroup phase clocks, only in builds with CSV_PHASE_TIMING: 8 u64
+// per workgroup, the shader clocks its thread 0 spent in each phase.
+#ifdef CSV_PHASE_TIMING
+__device__ uint64_t *g_enc_phase = nullptr;
+struct PhaseClock {
+    uint64_t acc[8] = {}, t0 = 0;
+    __device__ void start() { t0 = __builtin_amdgcn_s_memtime(); }
+    __device__ void stop(int i) {
+        const uint64_t t = __builtin_amdgcn_s_memtime();
+        acc[i] += t - t0;
+        t0 = t;
+    }
+    __device__ void flush() {
+        if (g_enc_phase && threadIdx.x == 0)
+            for (int i = 0; i < 8; i++) g_enc_phase[8 * (size_t)blockIdx.x + i] += acc[i];
+    }
+};
+#else
+struct PhaseClock {
+    __device__ void start() {}
+    __device__ void stop(int) {}
+    __device__ void flush() {}
+};
+#endif
+
 struct EncArgs {
     const uint32_t *vol;
     uint32_t nx, ny, nz, nbx, nby;
@@ -100,10 +130,15 @@ struct Brick {
     uint64_t x0, y0, z0;
 };
 
+// label of voxel (cx, cy, cz) of the brick; 0 beyond the volume (padding).
+// The address is clamped into the volume and the value masked, so that the
+// loads of a thread need no branches and issue together.
 __device__ __forceinline__ uint32_t voxel(const EncArgs &a, const Brick &b, uint32_t cx, uint32_t cy, uint32_t cz) {
     const uint64_t x = b.x0 + cx, y = b.y0 + cy, z = b.z0 + cz;
-    if (x < a.nx && y < a.ny && z < a.nz) return a.vol[x + (uint64_t)a.nx * (y + (uint64_t)a.ny * z)];
-    return 0u;  // padding beyond the volume
+    const bool in = x < a.nx && y < a.ny && z < a.nz;
+    const uint64_t xc = in ? x : 0, yc = in ? y : 0, zc = in ? z : 0;
+    const uint32_t v = a.vol[xc + (uint64_t)a.nx * (yc + (uint64_t)a.ny * zc)];
+    return in ? v : 0u;
 }
 
 // label of node j (Morton) on level m
@@ -164,13 +199,15 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
     __shared__ uint32_t lab[kNodes];
     __shared__ uint8_t cst[kNodes];
     __shared__ uint16_t expl[4096];
-    __shared__ uint32_t c_lab[kThreads];
-    __shared__ uint8_t c_op[kThreads];
+    __shared__ uint32_t c_lab[kChunk];
+    __shared__ uint8_t c_op[kChunk];
     __shared__ uint32_t wcnt[kThreads / 64];
+    __shared__ uint32_t wcnt4[kPer][kThreads / 64];
     __shared__ uint32_t share[8];  // 0: deltas of a level; 1..3: words, states, palette; 4, 5: arena offset
     __shared__ uint32_t s_cum[kN];
     __shared__ uint32_t xs[64];
     __shared__ uint32_t tf[2][16], tc[2][16];
+    __shared__ double trcp[2][16];
     __shared__ uint32_t hist_l[32];
     const uint32_t t = threadIdx.x, L = lane(), w = t >> 6;
     uint8_t *scr = a.scratch + (size_t)blockIdx.x * kScratch;
@@ -182,14 +219,18 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
     if (t < 32) {
         tf[t >> 4][t & 15] = a.f[t >> 4][t & 15];
         tc[t >> 4][t & 15] = a.c[t >> 4][t & 15];
+        trcp[t >> 4][t & 15] = 1.0 / (double)a.f[t >> 4][t & 15];
     }
+    PhaseClock pc;
     for (uint32_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+        pc.start();
         const uint64_t id = (uint64_t)item * a.stride;
         Brick b;
         b.x0 = (id % a.nbx) * 32;
         b.y0 = ((id / a.nbx) % a.nby) * 32;
         b.z0 = (id / ((uint64_t)a.nbx * a.nby)) * 32;
         // level 1 from the volume (every level-0 node is a constant subtree)
+#pragma unroll 2
         for (uint32_t q = t; q < 4096; q += kThreads) {
             const uint32_t x = 2 * compact3(q), y = 2 * compact3(q >> 1), z = 2 * compact3(q >> 2);
             uint32_t ch[8];
@@ -216,6 +257,7 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
             }
             __syncthreads();
         }
+        pc.stop(0);  // pyramid
         // symbol stream: child levels 4 .. 0
         uint32_t win = 0, P = 1, D = 0;  // wavefront 0: palette window (lane i: entry P-1-i), size, deltas
         if (w == 0 && L == 0) {
@@ -237,65 +279,114 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
             }
             __syncthreads();
             D = 0;
-            for (uint32_t s0 = 0; s0 < 8 * E; s0 += kThreads) {
-                const uint32_t s = s0 + t;
-                const bool valid = s < 8 * E;
-                uint32_t op = csv::kPa, stop = 0, lbl = 0;
-                if (valid) {
-                    const uint32_t q = expl[s >> 3], j = 8 * q + (s & 7);
-                    lbl = label_at(a, b, lab, m, j);
-                    stop = (m >= 1 && cst[lvl_off(m) + j]) ? 1u : 0u;
-                    if (lab[lvl_off(l) + q] == lbl) {
-                        op = csv::kRp;
-                    } else {
+            for (uint32_t s0 = 0; s0 < 8 * E; s0 += kChunk) {
+                // kPer child slots per thread (slot s0 + u * kThreads + t),
+                // their label and neighbour loads all in flight together
+                uint32_t opv[kPer], lblv[kPer], rk[kPer];
+                uint64_t bal[kPer];
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; u++) {
+                    const uint32_t s = s0 + u * kThreads + t;
+                    const bool valid = s < 8 * E;
+                    uint32_t op = kNone, lbl = 0;
+                    if (valid) {
+                        const uint32_t q = expl[s >> 3], j = 8 * q + (s & 7);
                         const uint32_t cx = compact3(j), cy = compact3(j >> 1), cz = compact3(j >> 2);
-                        for (uint32_t ax = 0; ax < 3 && op == csv::kPa; ax++) {
+                        lbl = label_at(a, b, lab, m, j);
+                        const uint32_t par = lab[lvl_off(l) + q];
+                        uint32_t nv[3];
+                        bool nok[3];
+#pragma unroll
+                        for (uint32_t ax = 0; ax < 3; ax++) {
                             const uint32_t c = ax == 0 ? cx : (ax == 1 ? cy : cz);
-                            uint32_t v;
                             if ((c & 1u) == 0) {  // the same-level node at -1
-                                if (c == 0) continue;
-                                v = label_at(a, b, lab, m, morton(cx - (ax == 0), cy - (ax == 1), cz - (ax == 2)));
+                                nok[ax] = c > 0;
+                                const uint32_t d = nok[ax] ? 1u : 0u;
+                                nv[ax] = label_at(a, b, lab, m,
+                                                  morton(cx - (ax == 0 ? d : 0u), cy - (ax == 1 ? d : 0u),
+                                                         cz - (ax == 2 ? d : 0u)));
                             } else {  // the parent of the node at +1
-                                if (c + 1 >= G) continue;
-                                v = lab[lvl_off(l) + morton((cx + (ax == 0)) >> 1, (cy + (ax == 1)) >> 1,
-                                                            (cz + (ax == 2)) >> 1)];
+                                nok[ax] = c + 1 < G;
+                                const uint32_t d = nok[ax] ? 1u : 0u;
+                                nv[ax] = lab[lvl_off(l) + morton((cx + (ax == 0 ? d : 0u)) >> 1,
+                                                                 (cy + (ax == 1 ? d : 0u)) >> 1,
+                                                                 (cz + (ax == 2 ? d : 0u)) >> 1)];
                             }
-                            if (v == lbl) op = csv::kRx + ax;
                         }
+                        op = par == lbl ? csv::kRp
+                                        : (nok[0] && nv[0] == lbl
+                                               ? csv::kRx
+                                               : (nok[1] && nv[1] == lbl ? csv::kRy
+                                                                         : (nok[2] && nv[2] == lbl ? csv::kRz : csv::kPa)));
+                        const uint32_t stop = (m >= 1 && cst[lvl_off(m) + j]) ? 1u : 0u;
+                        op |= stop << 8;
                     }
+                    opv[u] = op;
+                    lblv[u] = lbl;
+                    bal[u] = __ballot(op != kNone && (op & 0xFFu) == csv::kPa);
+                    if (L == 0) wcnt4[u][w] = (uint32_t)__popcll(bal[u]);
                 }
-                const bool cand = valid && op == csv::kPa;
-                uint32_t nc;
-                const uint32_t r = wg_rank(cand, nc, wcnt);
-                if (cand) c_lab[r] = lbl;
                 __syncthreads();
+                // candidates ranked in slot order
+                uint32_t nc = 0;
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; u++) {
+                    uint32_t bw = 0, tu = 0;
+#pragma unroll
+                    for (uint32_t k = 0; k < kThreads / 64; k++) {
+                        const uint32_t c = wcnt4[u][k];
+                        bw += k < w ? c : 0u;
+                        tu += c;
+                    }
+                    rk[u] = nc + bw + mbcnt(bal[u]);
+                    nc += tu;
+                    if ((bal[u] >> L) & 1ull) c_lab[rk[u]] = lblv[u];
+                }
+                __syncthreads();
+                pc.stop(m == 0 ? 2 : 1);  // reuse operations
                 if (w == 0) {
                     // palette operations in order: P_0, else the smallest delta
-                    // among the 16 entries before it, else append
-                    for (uint32_t c = 0; c < nc; c++) {
-                        const uint32_t lc = c_lab[c];
-                        const uint64_t mm = __ballot(L <= 16 && L < P && win == lc);
-                        uint32_t o;
-                        if (mm & 1ull) {
-                            o = csv::kP0;
-                        } else if (mm) {
-                            o = csv::kPd;
-                            if (L == 0) dels[D] = (uint8_t)(__builtin_ctzll(mm) - 1);
-                            D++;
-                        } else {
-                            o = csv::kPa;
-                            win = __shfl_up(win, 1u);
-                            if (L == 0) {
-                                win = lc;
-                                pal[P] = lc;
+                    // among the 16 entries before it, else append.  Lane k
+                    // holds candidate c0 + k and receives its operation.
+                    for (uint32_t c0 = 0; c0 < nc; c0 += 64) {
+                        const uint32_t lv = c0 + L < nc ? c_lab[c0 + L] : 0u;
+                        const uint32_t cn = min(64u, nc - c0);
+                        uint32_t mine = 0;
+                        for (uint32_t k = 0; k < cn; k++) {
+                            const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)k);
+                            const uint64_t mm = __ballot(L <= 16 && L < P && win == lc);
+                            uint32_t o;
+                            if (mm & 1ull) {
+                                o = csv::kP0;
+                            } else if (mm) {
+                                o = csv::kPd;
+                                if (L == 0) dels[D] = (uint8_t)(__builtin_ctzll(mm) - 1);
+                                D++;
+                            } else {
+                                o = csv::kPa;
+                                // lane i takes lane i - 1's entry (DPP wave shift right by one)
+                                win = (uint32_t)__builtin_amdgcn_update_dpp((int)win, (int)win, 0x138, 0xF, 0xF, false);
+                                if (L == 0) {
+                                    win = lc;
+                                    pal[P] = lc;
+                                }
+                                P++;
                             }
-                            P++;
+                            mine = L == k ? o : mine;
                         }
-                        if (L == 0) c_op[c] = (uint8_t)o;
+                        if (c0 + L < nc) c_op[c0 + L] = (uint8_t)mine;
                     }
                 }
                 __syncthreads();
-                if (valid) ops[s] = (uint8_t)((cand ? c_op[r] : op) | (stop << 3));
+                pc.stop(3);  // palette operations
+#pragma unroll
+                for (uint32_t u = 0; u < kPer; u++) {
+                    const uint32_t s = s0 + u * kThreads + t;
+                    if (opv[u] != kNone) {
+                        const uint32_t o = ((bal[u] >> L) & 1ull) ? c_op[rk[u]] : (opv[u] & 0xFFu);
+                        ops[s] = (uint8_t)(o | ((opv[u] >> 8) << 3));
+                    }
+                }
             }
             if (t == 0) share[0] = D;
             __syncthreads();
@@ -307,6 +398,7 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
             if (t == 0) s_cum[m] = base;
             __syncthreads();
         }
+        pc.stop(4);  // level ends
         const uint32_t n = base, leaf = s_cum[1];
         if (a.count_mode) {
             if (t < 32) hist_l[t] = 0;
@@ -323,26 +415,50 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
             const uint64_t xmax_unit = (uint64_t)((csv::kRansLower >> a.bits) << 16);
             uint32_t x = csv::kRansLower, pushed = 0;
             if (n) {
-                for (int64_t s = (int64_t)((n - 1) / W); s >= 0; s--) {
-                    const uint32_t i = (uint32_t)s * W + L;
-                    const bool act = L < W && i < n;
-                    bool emit = false;
-                    uint32_t wd = 0;
-                    if (act) {
-                        const uint32_t tb = i >= leaf ? 1u : 0u, sy = sym[i];
-                        const uint32_t f = tf[tb][sy], c = tc[tb][sy];
-                        uint32_t v = x;
-                        if ((uint64_t)v >= xmax_unit * f) {
-                            emit = true;
-                            wd = v & 0xFFFFu;
-                            v >>= 16;
-                        }
-                        x = ((v / f) << a.bits) + v % f + c;
+                constexpr int kBlk = 16;
+                for (int64_t s_hi = (int64_t)((n - 1) / W); s_hi >= 0; s_hi -= kBlk) {
+                    uint32_t sy[kBlk];
+#pragma unroll
+                    for (int k = 0; k < kBlk; k++) {
+                        const int64_t s = s_hi - k;
+                        const uint32_t i = (uint32_t)s * W + L;
+                        sy[k] = (s >= 0 && L < W && i < n) ? (uint32_t)sym[i] : 0xFFu;
                     }
-                    // the host order within a step is descending lanes
-                    const uint64_t em = __ballot(emit);
-                    if (emit) words[pushed + (uint32_t)__popcll(L == 63 ? 0ull : (em >> (L + 1)))] = (uint16_t)wd;
-                    pushed += (uint32_t)__popcll(em);
+#pragma unroll
+                    for (int k = 0; k < kBlk; k++) {
+                        const int64_t s = s_hi - k;
+                        const uint32_t i = (uint32_t)s * W + L;
+                        const bool act = sy[k] != 0xFFu;  // (false for every lane once s < 0)
+                        bool emit = false;
+                        uint32_t wd = 0;
+                        if (act) {
+                            const uint32_t tb = i >= leaf ? 1u : 0u;
+                            const uint32_t f = tf[tb][sy[k]], c = tc[tb][sy[k]];
+                            uint32_t v = x;
+                            if ((uint64_t)v >= xmax_unit * f) {
+                                emit = true;
+                                wd = v & 0xFFFFu;
+                                v >>= 16;
+                            }
+                            // v / f: a double reciprocal is within one of the
+                            // quotient; the remainder corrects it
+                            uint32_t q = (uint32_t)((double)v * trcp[tb][sy[k]]);
+                            int64_t r = (int64_t)v - (int64_t)q * f;
+                            if (r < 0) {
+                                q--;
+                                r += f;
+                            } else if (r >= (int64_t)f) {
+                                q++;
+                                r -= f;
+                            }
+                            x = (q << a.bits) + (uint32_t)r + c;
+                        }
+                        // the host order within a step is descending lanes
+                        const uint64_t em = __ballot(emit);
+                        if (emit)
+                            words[pushed + (uint32_t)__popcll(L == 63 ? 0ull : (em >> (L + 1)))] = (uint16_t)wd;
+                        pushed += (uint32_t)__popcll(em);
+                    }
                 }
             }
             if (L < W) xs[L] = x;
@@ -353,6 +469,7 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
             }
         }
         __syncthreads();
+        pc.stop(5);  // rANS
         const uint32_t nw = share[1], W = share[2], Pn = share[3];
         const uint32_t hdr = csv::record_header_words(kN);
         const uint32_t size = (4 * (hdr + Pn + W) + 2 * nw + 3) & ~3u;
@@ -381,7 +498,9 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
             if (t == 0 && (nw & 1u)) wr[nw] = 0;
         }
         __syncthreads();
+        pc.stop(6);  // record
     }
+    pc.flush();
 }
 
 // exclusive scan of the record sizes into the container's u64 index
@@ -417,21 +536,59 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t *arena, const u
     }
 }
 
+// a device buffer that grows on demand
 struct DevBuf {
     void *p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    bool alloc(size_t bytes) {
+    size_t bytes = 0;
+    bool ensure(size_t need) {
+        need = std::max<size_t>(need, 256);
+        if (bytes >= need) return true;
         if (p) (void)hipFree(p);
         p = nullptr;
-        return hipMalloc(&p, std::max<size_t>(bytes, 16)) == hipSuccess;
+        bytes = 0;
+        if (hipMalloc(&p, need) != hipSuccess) return false;
+        bytes = need;
+        return true;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
     }
     template <class T>
     T *as() const {
         return reinterpret_cast<T *>(p);
     }
 };
+
+// per device: the buffers of the last call, kept for the next one
+struct EncCache {
+    std::mutex mu;
+    DevBuf scratch, hist, sizes, aoff, top, arena, dblob;
+    uint8_t *h_pin = nullptr;  // pinned staging of the container on its way to host memory
+    size_t h_pin_bytes = 0;
+    void release() {
+        scratch.release();
+        hist.release();
+        sizes.release();
+        aoff.release();
+        top.release();
+        arena.release();
+        dblob.release();
+        if (h_pin) (void)hipHostFree(h_pin);
+        h_pin = nullptr;
+        h_pin_bytes = 0;
+    }
+};
+constexpr int kMaxDevices = 64;
+EncCache *g_cache[kMaxDevices] = {};
+std::mutex g_cache_mu;
+
+EncCache *cache_for(int device) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (!g_cache[device]) g_cache[device] = new (std::nothrow) EncCache;
+    return g_cache[device];
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -458,7 +615,8 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
         o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)))
         return CSV_EINVAL;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CSV_EINVAL;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev || device >= kMaxDevices)
+        return CSV_EINVAL;
     const uint32_t nbx = (nx + 31) / 32, nby = (ny + 31) / 32, nbz = (nz + 31) / 32;
     const uint64_t B64 = (uint64_t)nbx * nby * nbz;
     if (B64 >= (1ull << 32)) return CSV_ERANGE;
@@ -471,10 +629,15 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     const uint32_t grid = (uint32_t)std::min<uint64_t>(B64, (uint64_t)cu * 4);
     const uint64_t raw = (uint64_t)nx * ny * nz * 4;
     uint64_t cap = std::max<uint64_t>(16ull << 20, raw / 8);
-    DevBuf scratch, hist, sizes, aoff, top, arena, dblob;
-    if (!scratch.alloc(kScratch * grid) || !hist.alloc(32 * 8) || !sizes.alloc(4ull * B) || !aoff.alloc(8ull * B) ||
-        !top.alloc(8) || !arena.alloc(cap))
+    EncCache *ec = cache_for(device);
+    if (!ec) return CSV_ENOMEM;
+    std::lock_guard<std::mutex> lk(ec->mu);  // one compression per device at a time
+    DevBuf &scratch = ec->scratch, &hist = ec->hist, &sizes = ec->sizes, &aoff = ec->aoff, &top = ec->top,
+           &arena = ec->arena, &dblob = ec->dblob;
+    if (!scratch.ensure(kScratch * grid) || !hist.ensure(32 * 8) || !sizes.ensure(4ull * B) ||
+        !aoff.ensure(8ull * B) || !top.ensure(8) || !arena.ensure(cap))
         return CSV_ENOMEM;
+    cap = arena.bytes;
     EncArgs a;
     std::memset(&a, 0, sizeof(a));
     a.vol = labels;
@@ -528,25 +691,32 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
             return CSV_EHIP;
         if (used <= cap) break;
         cap = used;
-        if (pass == 1 || !arena.alloc(cap)) return CSV_ENOMEM;
+        if (pass == 1 || !arena.ensure(cap)) return CSV_ENOMEM;
     }
     // container: header (host), index (device scan), records (device copy)
     const uint64_t rs = csv::record_area_offset(B);
     const uint64_t total = rs + used;
-    if (!dblob.alloc(total)) return CSV_ENOMEM;
+    if (!dblob.ensure(total)) return CSV_ENOMEM;
     uint64_t *index = reinterpret_cast<uint64_t *>(dblob.as<uint8_t>() + csv::kHeaderBytes);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a.sizes, B, index);
     hipLaunchKernelGGL(pack_kernel, dim3(std::min<uint32_t>(B, (uint32_t)cu * 8)), dim3(256), 0, s,
                        (const uint8_t *)a.arena, (const uint64_t *)a.aoff, (const uint32_t *)a.sizes,
                        (const uint64_t *)index, B, dblob.as<uint8_t>() + rs);
+    if (ec->h_pin_bytes < total) {
+        if (ec->h_pin) (void)hipHostFree(ec->h_pin);
+        ec->h_pin = nullptr;
+        ec->h_pin_bytes = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&ec->h_pin), total, hipHostMallocDefault) != hipSuccess)
+            return CSV_ENOMEM;
+        ec->h_pin_bytes = total;
+    }
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(ec->h_pin, dblob.p, total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return CSV_EHIP;
     uint8_t *out = static_cast<uint8_t *>(std::malloc(total));
     if (!out) return CSV_ENOMEM;
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(out, dblob.p, total, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        std::free(out);
-        return CSV_EHIP;
-    }
+    std::memcpy(out, ec->h_pin, total);
     csv::VolumeHeader h;
     std::memset(&h, 0, sizeof(h));
     h.magic = csv::kMagic;
@@ -572,3 +742,25 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     *blob_bytes = total;
     return CSV_OK;
 }
+
+extern "C" int csv_encode_gpu_release(int device) {
+    if (device < 0 || device >= kMaxDevices) return CSV_EINVAL;
+    EncCache *ec;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        ec = g_cache[device];
+    }
+    if (!ec) return CSV_OK;
+    DeviceGuard g(device);
+    std::lock_guard<std::mutex> lk(ec->mu);
+    (void)hipDeviceSynchronize();
+    ec->release();
+    return CSV_OK;
+}
+
+#ifdef CSV_PHASE_TIMING
+// install (or clear, with NULL) a device buffer of 8 u64 clocks per workgroup
+extern "C" int csv_debug_enc_phase_buffer(uint64_t *dev_buf) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_enc_phase), &dev_buf, sizeof(dev_buf)) == hipSuccess ? CSV_OK : CSV_EHIP;
+}
+#endif

@@ -62,6 +62,7 @@ def test_gpu_encoder_rejects_bad_arguments():
     assert L.csv_encode_volume_gpu(None, 4, 4, 4, None, 0, None, ctypes.byref(p), ctypes.byref(n)) == csv.CSV_EINVAL
     assert L.csv_encode_volume_gpu(ctypes.c_void_p(16), 0, 4, 4, None, 0, None, ctypes.byref(p),
                                    ctypes.byref(n)) == csv.CSV_EINVAL
+    assert L.csv_encode_gpu_release(-1) == csv.CSV_EINVAL
 
 
 def test_strerror():

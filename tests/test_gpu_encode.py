@@ -99,6 +99,9 @@ def test_gpu_encoder_input_forms_and_errors(csvlib, orc):
     assert csvlib.encode_volume_gpu(d) == want
     torch.cuda.synchronize()
     assert csvlib.encode_volume_gpu(d, stream=torch.cuda.Stream()) == want
+    # the kept buffers released, then grown again
+    csvlib.encode_gpu_release(0)
+    assert csvlib.encode_volume_gpu(vol) == want
     one = np.full((1, 1, 1), 7, np.uint32)
     assert csvlib.encode_volume_gpu(one) == orc.encode_volume(one, scale_bits=10, lane_k=64)
     with pytest.raises(csvlib.CsvError):
