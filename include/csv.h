@@ -380,6 +380,63 @@ int csv_server_run_trace(csv_server *server, const csv_request *requests, uint32
                          uint64_t timeout_ns, uint32_t *n_done);
 void csv_server_destroy(csv_server *server);
 
+/*
+ * Frame cache of decoded bricks on the GPU (Sec. 4.1, after Shading Atlas
+ * Streaming), the per-frame alternative to the serving loop's LRU cache.
+ * The cache memory is a pool of base elements of 2^3 voxels; a brick at LOD
+ * t (0..4) takes a block of 8^(4-t) contiguous elements.  Free blocks sit on
+ * one stack per LOD; when a stack runs empty the shared top pointer
+ * advances; when the top would pass the end, the cache is rebuilt (emptied,
+ * then every brick of the frame decoded again).  A block keeps its LOD.
+ * Each frame's request list decides the contents: entries that the frame
+ * does not request, or that its visibility test rejects, are evicted and
+ * their blocks pushed on their stacks.  LOD 5 is the brick's palette[0] and
+ * is never stored.
+ */
+typedef struct csv_frame_cache csv_frame_cache;
+typedef struct {
+    uint32_t frame;            /* frame number, from 1 */
+    uint32_t requests;         /* n */
+    uint32_t distinct;         /* distinct visible (brick, LOD < 5) keys */
+    uint32_t new_entries;      /* ... of which not cached before the frame */
+    uint32_t decoded;          /* bricks decoded in this frame (all distinct ones after a rebuild) */
+    uint32_t hits;             /* distinct - decoded */
+    uint32_t evicted;          /* entries dropped at the start of the frame */
+    uint32_t rebuilt;          /* 1: the cache was rebuilt */
+    uint64_t used_bytes;       /* base elements handed out (top pointer), in bytes */
+    uint64_t capacity_bytes;
+} csv_frame_stats;
+
+/* A cache of cache_bytes (rounded down to 32 bytes) for frames of at most
+ * max_requests requests over the pool's current bricks.  The pool must
+ * outlive the cache and gain no volumes while it exists.  Errors:
+ * CSV_EINVAL, CSV_ENOMEM. */
+int csv_frame_cache_create(csv_pool *pool, uint64_t cache_bytes, uint32_t max_requests, csv_frame_cache **cache);
+
+/*
+ * One frame: requests brick_ids[n], lods[n] (device memory); with
+ * visible_bits / n_label_bits as in csv_bricks_visible (NULL and 0: no
+ * test), invisible requests are not cached.  On return the bricks are being
+ * decoded into the cache on `stream` and slots[i] (device uint64[n]) will
+ * hold the element offset of request i's block in csv_frame_cache_data (the
+ * (32 >> lod)^3 labels in x-fastest order), or UINT64_MAX for LOD 5,
+ * invisible or unknown requests.  The call waits for the stream once (the
+ * number of bricks to decode goes to the host between the cache update and
+ * the decode).  Frames of one cache run one at a time.  *stats (may be NULL)
+ * describes the frame.  Errors: CSV_EINVAL (null pointers, n above
+ * max_requests), CSV_ENOMEM (the frame's distinct bricks alone exceed the
+ * cache: nothing is cached, every slot UINT64_MAX), CSV_EHIP.
+ */
+int csv_frame_cache_frame(csv_frame_cache *cache, const uint32_t *brick_ids, const uint8_t *lods, uint32_t n,
+                          const uint32_t *visible_bits, uint32_t n_label_bits, uint64_t *slots, void *stream,
+                          csv_frame_stats *stats);
+/* Device address of the cache memory (uint32 labels). */
+uint32_t *csv_frame_cache_data(csv_frame_cache *cache);
+/* Copy n labels from element elem_offset of the cache to host memory (synchronous,
+ * after all work on the device).  Errors: CSV_EINVAL (out of range), CSV_EHIP. */
+int csv_frame_cache_read(csv_frame_cache *cache, uint64_t elem_offset, uint64_t n, uint32_t *host_dst);
+void csv_frame_cache_destroy(csv_frame_cache *cache);
+
 #ifdef __cplusplus
 }
 #endif

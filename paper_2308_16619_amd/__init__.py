@@ -54,6 +54,13 @@ COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("brick_id", "<u4"), ("lod", "<u4")
                              ("t_done_ns", "<u8")])
 
 
+class FrameStats(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_uint32), ("requests", ctypes.c_uint32), ("distinct", ctypes.c_uint32),
+                ("new_entries", ctypes.c_uint32), ("decoded", ctypes.c_uint32), ("hits", ctypes.c_uint32),
+                ("evicted", ctypes.c_uint32), ("rebuilt", ctypes.c_uint32), ("used_bytes", ctypes.c_uint64),
+                ("capacity_bytes", ctypes.c_uint64)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("cache_bytes", ctypes.c_uint64), ("inflight_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32)]
@@ -124,6 +131,12 @@ def lib():
         L.csv_server_read.argtypes = [vp, vp, vp]
         L.csv_server_run_trace.argtypes = [vp, vp, u32, vp, u64, ctypes.POINTER(u32)]
         L.csv_server_destroy.argtypes = [vp]
+        L.csv_frame_cache_create.argtypes = [vp, u64, u32, ctypes.POINTER(vp)]
+        L.csv_frame_cache_frame.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(FrameStats)]
+        L.csv_frame_cache_data.restype = vp
+        L.csv_frame_cache_data.argtypes = [vp]
+        L.csv_frame_cache_read.argtypes = [vp, u64, u64, vp]
+        L.csv_frame_cache_destroy.argtypes = [vp]
         if L.csv_abi_version() != 1:
             raise RuntimeError("libcsv.so ABI mismatch")
         _lib = L
@@ -417,6 +430,54 @@ class Server:
         if self._s:
             lib().csv_server_destroy(self._s)
             self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FrameCache:
+    """Per-frame cache of decoded bricks on the GPU (free stacks per LOD, a
+    top pointer, rebuild on overflow)."""
+
+    def __init__(self, pool, cache_bytes: int, max_requests: int):
+        self._c = ctypes.c_void_p()
+        self._pool = pool
+        self.max_requests = max_requests
+        _chk(lib().csv_frame_cache_create(pool._p, int(cache_bytes), int(max_requests), ctypes.byref(self._c)),
+             "csv_frame_cache_create")
+
+    def frame(self, ids, lods, visible_bits=None, n_label_bits: int = 0, slots=None, stream=None):
+        """ids (int32/uint32 CUDA tensor), lods (uint8 CUDA tensor); returns
+        (slots int64 CUDA tensor: element offsets in data(), -1 if not stored,
+        stats dict)."""
+        import torch
+        n = ids.numel()
+        if slots is None:
+            slots = torch.empty(n, dtype=torch.int64, device=ids.device)
+        st = FrameStats()
+        vb = ctypes.c_void_p(visible_bits.data_ptr()) if visible_bits is not None else None
+        _chk(lib().csv_frame_cache_frame(self._c, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(lods.data_ptr()),
+                                         n, vb, int(n_label_bits), ctypes.c_void_p(slots.data_ptr()),
+                                         _stream_handle(stream), ctypes.byref(st)), "csv_frame_cache_frame")
+        return slots, {f: getattr(st, f) for f, _ in FrameStats._fields_}
+
+    def data_ptr(self) -> int:
+        """Device address of the cache memory (uint32 labels)."""
+        return lib().csv_frame_cache_data(self._c)
+
+    def read(self, elem_offset: int, n: int) -> np.ndarray:
+        """Copy n labels from the cache, starting at elem_offset, to host memory."""
+        out = np.empty(n, dtype=np.uint32)
+        _chk(lib().csv_frame_cache_read(self._c, int(elem_offset), int(n), _np_ptr(out)), "csv_frame_cache_read")
+        return out
+
+    def close(self):
+        if self._c:
+            lib().csv_frame_cache_destroy(self._c)
+            self._c = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -65,6 +65,17 @@ def test_gpu_encoder_rejects_bad_arguments():
     assert L.csv_encode_gpu_release(-1) == csv.CSV_EINVAL
 
 
+def test_frame_cache_rejects_bad_arguments():
+    import paper_2308_16619_amd as csv
+    L = csv.lib()
+    c = ctypes.c_void_p()
+    assert L.csv_frame_cache_create(None, 1 << 20, 16, ctypes.byref(c)) == csv.CSV_EINVAL
+    assert L.csv_frame_cache_frame(None, None, None, 0, None, 0, None, None, None) == csv.CSV_EINVAL
+    assert L.csv_frame_cache_read(None, 0, 0, None) == csv.CSV_EINVAL
+    assert L.csv_frame_cache_data(None) is None
+    L.csv_frame_cache_destroy(None)
+
+
 def test_strerror():
     import paper_2308_16619_amd as csv
     assert csv.lib().csv_strerror(-3) == b"corrupt data"
