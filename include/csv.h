@@ -62,9 +62,12 @@ typedef struct {
     uint32_t sample_stride; /* frequency-table prepass samples every sample_stride-th brick; 0 = 512,
                                or 4096 above 2^20 bricks (Sec. 3.4) */
     uint32_t threads;       /* host threads; 0 = all hardware threads */
+    uint32_t tables;        /* rANS frequency tables: 2 = one for the symbols of levels >= 1 and one for L_0
+                               (Sec. 3.3); 1 = one table for all symbols (stored twice; Table 1's variant);
+                               0 = 2 */
 } csv_encode_opts;
 
-/* Defaults: brick_log2 5, scale_bits 10, lane_k 64, lane_max 64, sample_stride 0, threads 0. */
+/* Defaults: brick_log2 5, scale_bits 10, lane_k 64, lane_max 64, sample_stride 0, threads 0, tables 2. */
 void csv_encode_opts_default(csv_encode_opts *o);
 
 /*

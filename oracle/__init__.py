@@ -54,7 +54,7 @@ def _load():
         L = ctypes.CDLL(_LIB)
         vp = ctypes.c_void_p
         u32, u64 = ctypes.c_uint32, ctypes.c_uint64
-        L.orc_encode_volume.argtypes = [vp, u32, u32, u32, u32, u32, u32, u32, u32,
+        L.orc_encode_volume.argtypes = [vp, u32, u32, u32, u32, u32, u32, u32, u32, u32,
                                         ctypes.POINTER(vp), ctypes.POINTER(u64), vp]
         L.orc_decode_brick.argtypes = [vp, u64, u32, u32, vp]
         L.orc_decode_bricks.argtypes = [vp, u64, vp, vp, u32, vp]
@@ -94,15 +94,16 @@ def num_threads() -> int:
 
 # ---------------------------------------------------------------- volume --
 def encode_volume(vol: np.ndarray, brick_log2: int = 5, scale_bits: int = 12, lane_k: int = 256,
-                  lane_max: int = 64, sample_stride: int = 0, return_hist: bool = False):
-    """Encode a (nz, ny, nx) uint32 volume; returns the container bytes."""
+                  lane_max: int = 64, sample_stride: int = 0, return_hist: bool = False, tables: int = 2):
+    """Encode a (nz, ny, nx) uint32 volume; returns the container bytes.
+    tables: 2 frequency tables (levels >= 1, L_0) or 1 for all symbols."""
     vol = np.ascontiguousarray(vol, dtype=np.uint32)
     nz, ny, nx = vol.shape
     blob = ctypes.c_void_p()
     nbytes = ctypes.c_uint64()
     hist = np.zeros(8, dtype=np.uint64)
     _chk(_load().orc_encode_volume(_p(vol), nx, ny, nz, brick_log2, scale_bits, lane_k, lane_max, sample_stride,
-                                   ctypes.byref(blob), ctypes.byref(nbytes), _p(hist)))
+                                   tables, ctypes.byref(blob), ctypes.byref(nbytes), _p(hist)))
     out = ctypes.string_at(blob, nbytes.value)
     _load().orc_free(blob)
     return (out, hist) if return_hist else out

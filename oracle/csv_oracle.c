@@ -509,14 +509,17 @@ uint32_t orc_abi_version(void) { return 1; }
  * Encode a whole volume.  vol: nx*ny*nz labels, x fastest.  Bricks are
  * numbered x fastest; the volume is padded with label 0 to whole bricks.
  * sample_stride 0 means: every 512th brick, every 4096th above 2^20
- * bricks (Sec. 3.4).
+ * bricks (Sec. 3.4).  tables 2: one frequency table for the symbols of
+ * levels >= 1 and one for L_0 (the paper's default); 1: a single table
+ * from the counts of all symbols, stored twice (Table 1's variant).
  */
 int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz, uint32_t brick_log2,
                       uint32_t scale_bits, uint32_t lane_k, uint32_t lane_max, uint32_t sample_stride,
-                      uint8_t **blob_out, uint64_t *blob_bytes, uint64_t *op_hist_out) {
+                      uint32_t tables, uint8_t **blob_out, uint64_t *blob_bytes, uint64_t *op_hist_out) {
     if (!vol || !blob_out || !blob_bytes) return ORC_EINVAL;
     if (brick_log2 < 1 || brick_log2 > MAX_LOG2 || scale_bits < 8 || scale_bits > 12 || lane_k < 1 ||
-        lane_max < 1 || lane_max > 64 || (lane_max & (lane_max - 1)) || nx == 0 || ny == 0 || nz == 0)
+        lane_max < 1 || lane_max > 64 || (lane_max & (lane_max - 1)) || nx == 0 || ny == 0 || nz == 0 ||
+        (tables != 1 && tables != 2))
         return ORC_EINVAL;
     int N = (int)brick_log2;
     uint32_t b = 1u << N;
@@ -552,6 +555,8 @@ int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz
     }
     if (rc) return rc;
     uint32_t f[2][16];
+    if (tables == 1)
+        for (int q = 0; q < 16; q++) cnt[0][q] = cnt[1][q] = cnt[0][q] + cnt[1][q];
     normalize_table(cnt[0], 1u << scale_bits, f[0]);
     normalize_table(cnt[1], 1u << scale_bits, f[1]);
     rans_tables t;

@@ -31,7 +31,7 @@ class CsvError(RuntimeError):
 
 class EncodeOpts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("brick_log2", "scale_bits", "lane_k", "lane_max", "sample_stride",
-                                              "threads")]
+                                              "threads", "tables")]
 
 
 class VolumeInfo(ctypes.Structure):
@@ -153,12 +153,13 @@ def _np_ptr(a):
 
 
 def encode_volume(vol: np.ndarray, brick_log2: int = 5, scale_bits: int = 10, lane_k: int = 64, lane_max: int = 64,
-                  sample_stride: int = 0, threads: int = 0) -> bytes:
-    """Compress a (nz, ny, nx) uint32 label volume into a container blob."""
+                  sample_stride: int = 0, threads: int = 0, tables: int = 2) -> bytes:
+    """Compress a (nz, ny, nx) uint32 label volume into a container blob
+    (tables: 2 rANS frequency tables, levels >= 1 and L_0, or 1 for all)."""
     L = lib()
     vol = np.ascontiguousarray(vol, dtype=np.uint32)
     nz, ny, nx = vol.shape
-    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, threads)
+    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, threads, tables)
     p = ctypes.c_void_p()
     n = ctypes.c_size_t()
     _chk(L.csv_encode_volume(_np_ptr(vol), nx, ny, nz, ctypes.byref(o), ctypes.byref(p), ctypes.byref(n)),
@@ -170,7 +171,7 @@ def encode_volume(vol: np.ndarray, brick_log2: int = 5, scale_bits: int = 10, la
 
 
 def encode_volume_gpu(vol, brick_log2: int = 5, scale_bits: int = 10, lane_k: int = 64, lane_max: int = 64,
-                      sample_stride: int = 0, stream=None) -> bytes:
+                      sample_stride: int = 0, stream=None, tables: int = 2) -> bytes:
     """Compress a (nz, ny, nx) label volume on the GPU (same blob as
     encode_volume).  vol: a CUDA tensor of 4-byte labels (int32 or uint32
     bit patterns), or a numpy array, which is uploaded first."""
@@ -182,7 +183,7 @@ def encode_volume_gpu(vol, brick_log2: int = 5, scale_bits: int = 10, lane_k: in
         raise ValueError("vol must be a 3-d CUDA tensor of 4-byte labels")
     vol = vol.contiguous()
     nz, ny, nx = vol.shape
-    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, 0)
+    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, 0, tables)
     p = ctypes.c_void_p()
     n = ctypes.c_size_t()
     _chk(L.csv_encode_volume_gpu(ctypes.c_void_p(vol.data_ptr()), nx, ny, nz, ctypes.byref(o), vol.device.index or 0,

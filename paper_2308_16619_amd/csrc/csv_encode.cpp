@@ -307,6 +307,7 @@ void csv_encode_opts_default(csv_encode_opts *o) {
     o->lane_max = 64;
     o->sample_stride = 0;
     o->threads = 0;
+    o->tables = 2;
 }
 
 void csv_free(void *p) { std::free(p); }
@@ -318,8 +319,9 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
     csv_encode_opts_default(&o);
     if (opts) o = *opts;
     if (o.brick_log2 < 1 || o.brick_log2 > (uint32_t)kMaxLog2 || o.scale_bits < 8 || o.scale_bits > 12 ||
-        o.lane_k < 1 || o.lane_max < 1 || o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)))
+        o.lane_k < 1 || o.lane_max < 1 || o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)) || o.tables > 2)
         return CSV_EINVAL;
+    if (o.tables == 0) o.tables = 2;
     try {
         const int N = (int)o.brick_log2;
         const uint32_t b = 1u << N;
@@ -349,6 +351,8 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
         uint64_t cnt[2][16] = {};
         for (auto &h : hist)
             for (int q = 0; q < 32; q++) cnt[q / 16][q % 16] += h[q];
+        if (o.tables == 1)  // one table for all symbols
+            for (int q = 0; q < 16; q++) cnt[0][q] = cnt[1][q] = cnt[0][q] + cnt[1][q];
         Tables t;
         t.bits = o.scale_bits;
         for (int k = 0; k < 2; k++) {

@@ -612,7 +612,7 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     csv_encode_opts_default(&o);
     if (opts) o = *opts;
     if (o.brick_log2 != (uint32_t)kN || o.scale_bits < 8 || o.scale_bits > 12 || o.lane_k < 1 || o.lane_max < 1 ||
-        o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)))
+        o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)) || o.tables > 2)
         return CSV_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev || device >= kMaxDevices)
@@ -665,6 +665,8 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     if (hipGetLastError() != hipSuccess || hipMemcpyAsync(cnt, a.hist, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return CSV_EHIP;
+    if (o.tables == 1)  // one table for all symbols
+        for (int q = 0; q < 16; q++) cnt[0][q] = cnt[1][q] = cnt[0][q] + cnt[1][q];
     uint32_t f[2][16];
     for (int k = 0; k < 2; k++) {
         csv::normalize_counts(cnt[k], 1u << o.scale_bits, f[k]);

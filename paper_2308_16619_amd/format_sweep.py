@@ -1,15 +1,24 @@
-"""Format sweep: compression ratio and GPU decode throughput across the
-encoder's format parameters (Table 1's study, on a seeded synthetic volume):
+"""Format sweep: compression ratio, compression time and GPU decode
+throughput across the encoder's format parameters (Table 1's study, on a
+seeded synthetic volume):
 
-* brick edge 2^brick_log2 in {16, 32, 64} (the GPU decoder takes 32^3
-  bricks, so the other edges report the compression ratio only);
+* brick edge 2^brick_log2 in {16, 32, 64}, each with Table 1's three
+  entropy-coding variants: no rANS (the symbol stream stored as raw
+  nibbles), rANS with one frequency table for all symbols, rANS with two
+  (levels >= 1 and L_0: the default).  The GPU decoder takes 32^3 bricks,
+  so the other edges report size and host compression time only;
 * interleaved rANS states per brick W (lane_max) in {1, 4, 16, 64} (W = 1 is
   the paper's single stream per brick);
 * table precision scale_bits in {8, 9, 10, 11}.
 
-Each variant prints one JSON line: compressed bytes and ratio, and for 32^3
-bricks the decode of every brick at full LOD in one call (autotuned launch
-shape, HIP events over `reps` calls; output checked against the volume).
+The no-rANS size is exact without a separate encoder: a raw record would
+hold u32 P, u32 cum[N], the palette and the n = cum[0] nibbles packed two
+per byte (padded to 4 bytes), and P and n are in every rANS record's
+header.  Each variant prints one JSON line: compressed bytes and ratio, host
+compression seconds (16 threads), and for 32^3 bricks the GPU compressor's
+time and the decode of every brick at full LOD in one call (autotuned
+launch shape, HIP events over `reps` calls; output checked against the
+volume).
 
     python -m paper_2308_16619_amd.format_sweep [--n 512] [--reps 5]
 """
@@ -19,6 +28,7 @@ import argparse
 import json
 import os
 import sys
+import time
 
 import numpy as np
 
@@ -54,6 +64,37 @@ def decode_rate(csv, torch, vol, blob, reps):
     return out.numel() * 4 / (ms * 1e-3) / 1e9, ms, list(shape)
 
 
+def raw_nibble_bytes(csv, blob: bytes) -> int:
+    """Container size if every record held its symbols as raw nibbles."""
+    info = csv.blob_info(blob)
+    nb, N = info["n_bricks"], info["brick_log2"]
+    index = np.frombuffer(blob, dtype=np.uint64, count=nb + 1, offset=128)
+    rs = (128 + 8 * (nb + 1) + 15) & ~15
+    w = np.frombuffer(blob, dtype=np.uint8)
+    total = rs
+    for i in range(nb):
+        o = rs + int(index[i])
+        P = int(np.frombuffer(w[o:o + 4].tobytes(), np.uint32)[0])
+        n = int(np.frombuffer(w[o + 12:o + 16].tobytes(), np.uint32)[0])  # cum[0]: all symbols
+        total += 4 * (1 + N + P) + (((n + 1) // 2 + 3) & ~3)
+    return total
+
+
+def host_encode(csv, vol, **kw):
+    t0 = time.perf_counter()
+    blob = csv.encode_volume(vol, threads=16, **kw)
+    return blob, time.perf_counter() - t0
+
+
+def gpu_encode_ms(csv, torch, vol, blob, **kw):
+    d = torch.from_numpy(vol.view(np.int32)).cuda()
+    assert csv.encode_volume_gpu(d, **kw) == blob, "GPU container differs"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    csv.encode_volume_gpu(d, **kw)
+    return (time.perf_counter() - t0) * 1e3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=512, help="edge of the cells volume")
@@ -67,13 +108,32 @@ def main():
         import torch
     vol = synth.cells(n=args.n, grid=max(2, round(37 * args.n / 512)), seed=2)
     raw = vol.nbytes
-    variants = [(b, 10, 64) for b in (4, 5, 6)] + [(5, 10, w) for w in (1, 4, 16)] + \
-               [(5, s, 64) for s in (8, 9, 11)]
-    for log2, sbits, lanes in variants:
-        blob = csv.encode_volume(vol, brick_log2=log2, scale_bits=sbits, lane_max=lanes)
-        rec = {"volume": "%d^3 cells" % args.n, "brick": 1 << log2, "scale_bits": sbits, "lane_max": lanes,
-               "compressed_bytes": len(blob), "compression_ratio_pct": round(100.0 * len(blob) / raw, 4)}
-        if log2 == 5 and torch is not None:
+    name = "%d^3 cells" % args.n
+    # Table 1: brick edge x entropy coding
+    for log2 in (4, 5, 6):
+        for tables in (2, 1):
+            blob, sec = host_encode(csv, vol, brick_log2=log2, tables=tables)
+            rec = {"volume": name, "brick": 1 << log2, "coding": "rANS, %d table%s" % (tables, "s" * (tables > 1)),
+                   "scale_bits": 10, "lane_max": 64, "compressed_bytes": len(blob),
+                   "compression_ratio_pct": round(100.0 * len(blob) / raw, 4), "host_encode_s": round(sec, 3),
+                   "host_encode_gbs": round(raw / sec / 1e9, 3)}
+            if log2 == 5 and torch is not None:
+                rec["gpu_encode_ms"] = round(gpu_encode_ms(csv, torch, vol, blob, tables=tables), 3)
+                gbs, ms, shape = decode_rate(csv, torch, vol, blob, args.reps)
+                rec.update({"decode_gbs": round(gbs, 2), "ms_per_call": round(ms, 4), "shape": shape})
+            print(json.dumps(rec), flush=True)
+            if tables == 2:
+                rb = raw_nibble_bytes(csv, blob)
+                print(json.dumps({"volume": name, "brick": 1 << log2, "coding": "no rANS (raw nibbles)",
+                                  "compressed_bytes": rb, "compression_ratio_pct": round(100.0 * rb / raw, 4)}),
+                      flush=True)
+    # interleaving width and table precision (32^3 bricks, two tables)
+    for sbits, lanes in [(10, w) for w in (1, 4, 16)] + [(s, 64) for s in (8, 9, 11)]:
+        blob, sec = host_encode(csv, vol, scale_bits=sbits, lane_max=lanes)
+        rec = {"volume": name, "brick": 32, "coding": "rANS, 2 tables", "scale_bits": sbits, "lane_max": lanes,
+               "compressed_bytes": len(blob), "compression_ratio_pct": round(100.0 * len(blob) / raw, 4),
+               "host_encode_s": round(sec, 3)}
+        if torch is not None:
             gbs, ms, shape = decode_rate(csv, torch, vol, blob, args.reps)
             rec.update({"decode_gbs": round(gbs, 2), "ms_per_call": round(ms, 4), "shape": shape})
         print(json.dumps(rec), flush=True)

@@ -81,7 +81,7 @@ def test_strerror():
     assert csv.lib().csv_strerror(-3) == b"corrupt data"
 
 
-@pytest.mark.parametrize("case", ["cfg1", "random", "padded", "bits8", "k1", "b16"])
+@pytest.mark.parametrize("case", ["cfg1", "random", "padded", "bits8", "k1", "b16", "one_table", "one_table_b64"])
 def test_encoder_bytes_identical_to_oracle(orc, case):
     import paper_2308_16619_amd as csv
     kw = {}
@@ -97,9 +97,15 @@ def test_encoder_bytes_identical_to_oracle(orc, case):
     elif case == "k1":
         vol = synth.voronoi_bg(n=64, sites=90, seed=5)
         kw = dict(lane_k=1, lane_max=16)
-    else:
+    elif case == "b16":
         vol = synth.voronoi_bg(n=64, sites=90, seed=6)
         kw = dict(brick_log2=4)
+    elif case == "one_table":
+        vol = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+        kw = dict(tables=1)
+    else:
+        vol = synth.voronoi_bg(n=128, sites=300, seed=7)
+        kw = dict(tables=1, brick_log2=6)
     mine = csv.encode_volume(vol, **kw)
     ref = orc.encode_volume(vol, **{"scale_bits": 10, "lane_k": 64, **kw})
     assert mine == ref

@@ -1,20 +1,39 @@
-"""CPU test of the format sweep tool (compression ratios only): every
-variant encodes, and more interleaved rANS states cost bytes (each state
-is 4 bytes of record)."""
+"""CPU test of the format sweep tool (sizes only): every variant encodes;
+the no-rANS size equals a raw-nibble layout computed from the oracle's
+symbol streams and palettes; more interleaved rANS states cost bytes (each
+state is 4 bytes of record)."""
 import json
+import os
 import subprocess
 import sys
-import os
+
+import numpy as np
+
+import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_format_sweep_ratios():
+def test_format_sweep_ratios(orc):
     out = subprocess.run([sys.executable, "-m", "paper_2308_16619_amd.format_sweep", "--n", "64", "--no-gpu"],
                          cwd=ROOT, capture_output=True, text=True, timeout=300, check=True).stdout
     rows = [json.loads(ln) for ln in out.splitlines() if ln.startswith("{")]
-    assert len(rows) == 9
+    assert len(rows) == 15
     assert {r["brick"] for r in rows} == {16, 32, 64}
-    by_lanes = {r["lane_max"]: r["compressed_bytes"] for r in rows if r["brick"] == 32 and r["scale_bits"] == 10}
-    assert by_lanes[1] <= by_lanes[4] <= by_lanes[16] <= by_lanes[64]
     assert all(0 < r["compression_ratio_pct"] < 100 for r in rows)
+    table1 = {(r["brick"], r["coding"]): r["compressed_bytes"] for r in rows[:9]}
+    for b in (16, 32, 64):
+        assert table1[(b, "no rANS (raw nibbles)")] > max(table1[(b, "rANS, 2 tables")], table1[(b, "rANS, 1 table")])
+    by_lanes = {r["lane_max"]: r["compressed_bytes"] for r in rows[9:] if r["scale_bits"] == 10}
+    by_lanes[64] = table1[(32, "rANS, 2 tables")]
+    assert by_lanes[1] <= by_lanes[4] <= by_lanes[16] <= by_lanes[64]
+    # raw nibbles for 32^3 bricks from the oracle: u32 P, u32 cum[5], palette, nibbles two per byte
+    vol = synth.cells(n=64, grid=max(2, round(37 * 64 / 512)), seed=2)
+    total = (128 + 8 * 9 + 15) & ~15
+    for bz in range(2):
+        for by in range(2):
+            for bx in range(2):
+                br = np.ascontiguousarray(vol[32 * bz:32 * bz + 32, 32 * by:32 * by + 32, 32 * bx:32 * bx + 32])
+                sym, _, pal = orc.brick_symbols(br)
+                total += 4 * (1 + 5 + len(pal)) + (((len(sym) + 1) // 2 + 3) & ~3)
+    assert table1[(32, "no rANS (raw nibbles)")] == total

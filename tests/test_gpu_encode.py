@@ -45,7 +45,8 @@ def edge_bricks():
     return golden_volume()
 
 
-@pytest.mark.parametrize("case", ["cfg1", "edge", "padded", "bits8_stride3", "k1_w16", "w1", "bits12_k256"])
+@pytest.mark.parametrize("case", ["cfg1", "edge", "padded", "bits8_stride3", "k1_w16", "w1", "bits12_k256",
+                                  "one_table"])
 def test_gpu_encoder_matches_oracle(csvlib, orc, case):
     if case == "cfg1":
         check(csvlib, orc, case, synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1))
@@ -61,8 +62,24 @@ def test_gpu_encoder_matches_oracle(csvlib, orc, case):
         check(csvlib, orc, case, synth.voronoi_bg(n=64, sites=90, seed=5), lane_k=1, lane_max=16)
     elif case == "w1":
         check(csvlib, orc, case, synth.voronoi_bg(n=64, sites=90, seed=6), lane_max=1)
-    else:
+    elif case == "bits12_k256":
         check(csvlib, orc, case, synth.cells(n=128, grid=9, seed=8), scale_bits=12, lane_k=256)
+    else:
+        check(csvlib, orc, case, edge_bricks(), tables=1)
+
+
+def test_one_table_container_decodes(csvlib, orc):
+    # Table 1's one-table variant: both header tables equal; the decoder
+    # reads it unchanged, at every LOD
+    from gpu_util import gpu_decode_uniform
+    vol = synth.cells(n=128, grid=9, seed=8)
+    blob = check(csvlib, orc, "one_table_cells", vol, tables=1)
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    for t in range(6):
+        log("one-table container, lod %d" % t)
+        np.testing.assert_array_equal(gpu_decode_uniform(pool, np.arange(64), t),
+                                      orc.decode_bricks(blob, np.arange(64), [t] * 64))
 
 
 def test_gpu_encoder_cells_and_round_trip(csvlib, orc):

@@ -56,3 +56,26 @@ def test_tables_recount_from_sampled_bricks(orc):
     assert cnt[1][8:].sum() == 0
     for t in range(2):
         np.testing.assert_array_equal(info["freq"][t], orc.normalize_table(cnt[t], 11))
+
+
+def test_one_table_is_the_normalised_sum(orc):
+    # Table 1's variant: one frequency table from the counts of all symbols
+    # of the sampled bricks, stored in both table slots; lossless as before
+    vol = synth.voronoi_bg(n=96, sites=60, seed=21)
+    stride = 5
+    blob = orc.encode_volume(vol, sample_stride=stride, scale_bits=11, tables=1)
+    info = orc.volume_info(blob)
+    nb = info["nbx"]
+    cnt = np.zeros(16, np.uint64)
+    for bid in range(0, info["n_bricks"], stride):
+        bx, by, bz = bid % nb, (bid // nb) % nb, bid // (nb * nb)
+        br = np.ascontiguousarray(vol[bz * 32:(bz + 1) * 32, by * 32:(by + 1) * 32, bx * 32:(bx + 1) * 32])
+        sym, _, _ = orc.brick_symbols(br)
+        np.add.at(cnt, sym.astype(np.int64), 1)
+    want = orc.normalize_table(cnt, 11)
+    np.testing.assert_array_equal(info["freq"][0], want)
+    np.testing.assert_array_equal(info["freq"][1], want)
+    for bid in range(info["n_bricks"]):
+        bx, by, bz = bid % nb, (bid // nb) % nb, bid // (nb * nb)
+        np.testing.assert_array_equal(orc.decode_brick(blob, bid, 0),
+                                      vol[bz * 32:(bz + 1) * 32, by * 32:(by + 1) * 32, bx * 32:(bx + 1) * 32])
