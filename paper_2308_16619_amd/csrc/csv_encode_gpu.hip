@@ -1,26 +1,26 @@
 // GPU compressor for 32^3 bricks: the container of csv_encode_volume, byte
 // for byte, built on the device from a label volume resident in HBM.
 //
-//   resolution pyramid (Sec. 3.1)      level 1 from the volume, levels 2..5
+//   symbols kernel (a 256-thread workgroup per brick, persistent grid):
+//     resolution pyramid (Sec. 3.1)    level 1 from the volume, levels 2..5
 //                                      in LDS; level 0 read where needed
-//   operations (Sec. 3.2, Alg. 2)      per child level, the children of the
+//     operations (Sec. 3.2, Alg. 2)    per child level, the children of the
 //                                      expanded parents in Morton order: the
 //                                      reuse operations (parent, neighbours)
 //                                      in parallel, then the palette
 //                                      operations of the remaining children
 //                                      in order by one wavefront holding the
 //                                      last 17 palette entries in its lanes
-//   frequency tables (Sec. 3.3, 3.4)   a counting pass over the sampled
-//                                      bricks, normalised on the host
-//   interleaved rANS (Sec. 3.3)        one wavefront, one state per lane,
-//                                      symbols from last to first; the words
-//                                      of a step are placed by ballot
-//   packing                            records into an arena, a device scan
-//                                      of record sizes, one copy kernel
+//     frequency tables (Sec. 3.3/3.4)  histograms of the sampled bricks'
+//                                      symbols, normalised on the host
+//     the symbol stream and palette of every brick go to an arena
+//   rANS kernel (a wavefront per brick): interleaved rANS (Sec. 3.3), one
+//     state per lane, symbols from last to first, the words of a step
+//     placed by ballot; the record into a second arena
+//   packing: a device scan of record sizes, one copy kernel
 //
-// One 256-thread workgroup encodes one brick at a time (persistent grid);
-// per-workgroup scratch in global memory holds the symbol stream, palette
-// and words of the brick in flight.
+// Per-workgroup and per-wavefront scratch in global memory holds the
+// symbol stream, palette and words of the bricks in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,8 +53,9 @@ constexpr size_t kOffSym = 0;
 constexpr size_t kOffOps = 76800;           // >= kMaxSym
 constexpr size_t kOffDel = kOffOps + 32768;
 constexpr size_t kOffPal = kOffDel + 32768;
-constexpr size_t kOffWords = kOffPal + 4 * 37456;  // palette <= kMaxChildren + 1
-constexpr size_t kScratch = kOffWords + 2 * (size_t)kMaxSym + 64;
+constexpr size_t kScratch = kOffPal + 4 * 37456;  // palette <= kMaxChildren + 1
+// per-wavefront scratch of the rANS kernel: the words of one brick
+constexpr size_t kWordsScratch = 2 * (size_t)kMaxSym + 64;
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
@@ -113,12 +114,18 @@ struct PhaseClock {
 struct EncArgs {
     const uint32_t *vol;
     uint32_t nx, ny, nz, nbx, nby;
-    uint32_t n_items, stride;  // item i encodes brick i * stride
-    uint32_t count_mode;       // 1: symbol histograms of the items only
-    unsigned long long *hist;  // count mode: 2 x 16 counters
+    uint32_t n_items;          // bricks
+    uint32_t sample_stride;    // the frequency tables count every sample_stride-th brick
+    unsigned long long *hist;  // 2 x 16 symbol counters of the sampled bricks
     uint32_t f[2][16], c[2][16];
     uint32_t bits, lane_k, lane_max;
-    uint8_t *scratch;
+    uint8_t *scratch;          // symbols kernel: per workgroup
+    uint8_t *wscratch;         // rANS kernel: per wavefront
+    uint8_t *sarena;           // symbol streams and palettes (symbols kernel -> rANS kernel)
+    uint64_t sarena_cap;
+    unsigned long long *sarena_top;
+    uint64_t *soff;            // per brick: offset in sarena
+    uint32_t *sn, *sp, *scum;  // per brick: symbols, palette entries, cum[5]
     uint8_t *arena;
     uint64_t arena_cap;
     unsigned long long *arena_top;
@@ -195,7 +202,9 @@ __device__ __forceinline__ uint32_t mode8(const uint32_t ch[8], bool &same) {
     return v;
 }
 
-__global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
+// Pyramid, operations and palette of one brick per workgroup; the symbol
+// stream and palette go to the arena for the rANS kernel.
+__global__ __launch_bounds__(kThreads) void symbols_kernel(EncArgs a) {
     __shared__ uint32_t lab[kNodes];
     __shared__ uint8_t cst[kNodes];
     __shared__ uint16_t expl[4096];
@@ -203,11 +212,8 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
     __shared__ uint8_t c_op[kChunk];
     __shared__ uint32_t wcnt[kThreads / 64];
     __shared__ uint32_t wcnt4[kPer][kThreads / 64];
-    __shared__ uint32_t share[8];  // 0: deltas of a level; 1..3: words, states, palette; 4, 5: arena offset
+    __shared__ uint32_t share[8];  // 0: deltas of a level; 3: palette entries; 4, 5: arena offset
     __shared__ uint32_t s_cum[kN];
-    __shared__ uint32_t xs[64];
-    __shared__ uint32_t tf[2][16], tc[2][16];
-    __shared__ double trcp[2][16];
     __shared__ uint32_t hist_l[32];
     const uint32_t t = threadIdx.x, L = lane(), w = t >> 6;
     uint8_t *scr = a.scratch + (size_t)blockIdx.x * kScratch;
@@ -215,16 +221,10 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
     uint8_t *ops = scr + kOffOps;
     uint8_t *dels = scr + kOffDel;
     uint32_t *pal = reinterpret_cast<uint32_t *>(scr + kOffPal);
-    uint16_t *words = reinterpret_cast<uint16_t *>(scr + kOffWords);
-    if (t < 32) {
-        tf[t >> 4][t & 15] = a.f[t >> 4][t & 15];
-        tc[t >> 4][t & 15] = a.c[t >> 4][t & 15];
-        trcp[t >> 4][t & 15] = 1.0 / (double)a.f[t >> 4][t & 15];
-    }
     PhaseClock pc;
     for (uint32_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
         pc.start();
-        const uint64_t id = (uint64_t)item * a.stride;
+        const uint64_t id = item;
         Brick b;
         b.x0 = (id % a.nbx) * 32;
         b.y0 = ((id / a.nbx) % a.nby) * 32;
@@ -400,107 +400,148 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncArgs a) {
         }
         pc.stop(4);  // level ends
         const uint32_t n = base, leaf = s_cum[1];
-        if (a.count_mode) {
+        // the sampled bricks' symbol histograms (the frequency tables, Sec. 3.4)
+        if (id % a.sample_stride == 0) {
             if (t < 32) hist_l[t] = 0;
             __syncthreads();
             for (uint32_t i = t; i < n; i += kThreads) atomicAdd(&hist_l[(i >= leaf ? 16u : 0u) + sym[i]], 1u);
             __syncthreads();
             if (t < 32 && hist_l[t]) atomicAdd(&a.hist[t], (unsigned long long)hist_l[t]);
-            __syncthreads();
-            continue;
         }
-        // interleaved rANS, symbols from last to first: symbol i to state i mod W
-        if (w == 0) {
-            const uint32_t W = lanes_for(n, a.lane_k, a.lane_max);
-            const uint64_t xmax_unit = (uint64_t)((csv::kRansLower >> a.bits) << 16);
-            uint32_t x = csv::kRansLower, pushed = 0;
-            if (n) {
-                constexpr int kBlk = 16;
-                for (int64_t s_hi = (int64_t)((n - 1) / W); s_hi >= 0; s_hi -= kBlk) {
-                    uint32_t sy[kBlk];
-#pragma unroll
-                    for (int k = 0; k < kBlk; k++) {
-                        const int64_t s = s_hi - k;
-                        const uint32_t i = (uint32_t)s * W + L;
-                        sy[k] = (s >= 0 && L < W && i < n) ? (uint32_t)sym[i] : 0xFFu;
-                    }
-#pragma unroll
-                    for (int k = 0; k < kBlk; k++) {
-                        const int64_t s = s_hi - k;
-                        const uint32_t i = (uint32_t)s * W + L;
-                        const bool act = sy[k] != 0xFFu;  // (false for every lane once s < 0)
-                        bool emit = false;
-                        uint32_t wd = 0;
-                        if (act) {
-                            const uint32_t tb = i >= leaf ? 1u : 0u;
-                            const uint32_t f = tf[tb][sy[k]], c = tc[tb][sy[k]];
-                            uint32_t v = x;
-                            if ((uint64_t)v >= xmax_unit * f) {
-                                emit = true;
-                                wd = v & 0xFFFFu;
-                                v >>= 16;
-                            }
-                            // v / f: a double reciprocal is within one of the
-                            // quotient; the remainder corrects it
-                            uint32_t q = (uint32_t)((double)v * trcp[tb][sy[k]]);
-                            int64_t r = (int64_t)v - (int64_t)q * f;
-                            if (r < 0) {
-                                q--;
-                                r += f;
-                            } else if (r >= (int64_t)f) {
-                                q++;
-                                r -= f;
-                            }
-                            x = (q << a.bits) + (uint32_t)r + c;
-                        }
-                        // the host order within a step is descending lanes
-                        const uint64_t em = __ballot(emit);
-                        if (emit)
-                            words[pushed + (uint32_t)__popcll(L == 63 ? 0ull : (em >> (L + 1)))] = (uint16_t)wd;
-                        pushed += (uint32_t)__popcll(em);
-                    }
-                }
-            }
-            if (L < W) xs[L] = x;
-            if (L == 0) {
-                share[1] = pushed;
-                share[2] = W;
-                share[3] = P;
-            }
-        }
+        // symbols and palette to the arena, for the rANS kernel
+        if (w == 0 && L == 0) share[3] = P;
         __syncthreads();
-        pc.stop(5);  // rANS
-        const uint32_t nw = share[1], W = share[2], Pn = share[3];
-        const uint32_t hdr = csv::record_header_words(kN);
-        const uint32_t size = (4 * (hdr + Pn + W) + 2 * nw + 3) & ~3u;
+        const uint32_t Pn = share[3];
+        const uint64_t bytes = (((uint64_t)n + 3) & ~3ull) + 4ull * Pn;
         if (t == 0) {
-            const uint64_t off = atomicAdd(a.arena_top, (unsigned long long)size);
-            a.sizes[id] = size;
-            a.aoff[id] = off;
+            const uint64_t off = atomicAdd(a.sarena_top, (unsigned long long)bytes);
+            a.soff[id] = off;
+            a.sn[id] = n;
+            a.sp[id] = Pn;
+            for (int m = 0; m < kN; m++) a.scum[(size_t)kN * id + m] = s_cum[m];
             share[4] = (uint32_t)off;
             share[5] = (uint32_t)(off >> 32);
         }
         __syncthreads();
         const uint64_t off = ((uint64_t)share[5] << 32) | share[4];
+        if (off + bytes <= a.sarena_cap) {
+            uint8_t *d = a.sarena + off;
+            // whole dwords (the arena offset and the scratch are 4-byte aligned;
+            // the bytes past n are padding that the rANS kernel does not read)
+            const uint32_t *sw = reinterpret_cast<const uint32_t *>(sym);
+            uint32_t *dw = reinterpret_cast<uint32_t *>(d);
+            for (uint32_t i = t; i < (n + 3) / 4; i += kThreads) dw[i] = sw[i];
+            uint32_t *dp = reinterpret_cast<uint32_t *>(d + ((n + 3) & ~3u));
+            for (uint32_t i = t; i < Pn; i += kThreads) dp[i] = pal[i];
+        }
+        __syncthreads();
+        pc.stop(5);  // arena
+    }
+    pc.flush();
+}
+
+// Interleaved rANS and the record of one brick per wavefront (Sec. 3.3):
+// symbol i to state i mod W, from the last symbol to the first; the words
+// of a step are placed by ballot rank in descending lane order, then
+// reversed into the record so that the decoder reads them in symbol order.
+__global__ __launch_bounds__(kThreads) void rans_kernel(EncArgs a) {
+    __shared__ uint32_t tf[2][16], tc[2][16];
+    __shared__ double trcp[2][16];
+    const uint32_t t = threadIdx.x, L = lane(), w = t >> 6;
+    if (t < 32) {
+        tf[t >> 4][t & 15] = a.f[t >> 4][t & 15];
+        tc[t >> 4][t & 15] = a.c[t >> 4][t & 15];
+        trcp[t >> 4][t & 15] = 1.0 / (double)a.f[t >> 4][t & 15];
+    }
+    __syncthreads();
+    constexpr uint32_t kWaves = kThreads / 64;
+    uint16_t *words = reinterpret_cast<uint16_t *>(a.wscratch + ((size_t)blockIdx.x * kWaves + w) * kWordsScratch);
+    const uint64_t xmax_unit = (uint64_t)((csv::kRansLower >> a.bits) << 16);
+    const uint32_t hdr = csv::record_header_words(kN);
+    for (uint32_t id = blockIdx.x * kWaves + w; id < a.n_items; id += gridDim.x * kWaves) {
+        const uint32_t n = a.sn[id], Pn = a.sp[id], leaf = a.scum[(size_t)kN * id + 1];
+        const uint8_t *sym = a.sarena + a.soff[id];
+        const uint32_t *pal = reinterpret_cast<const uint32_t *>(sym + ((n + 3) & ~3u));
+        const uint32_t W = lanes_for(n, a.lane_k, a.lane_max);
+        uint32_t x = csv::kRansLower, pushed = 0;
+        if (n) {
+            constexpr int kBlk = 16;
+            for (int64_t s_hi = (int64_t)((n - 1) / W); s_hi >= 0; s_hi -= kBlk) {
+                uint32_t sy[kBlk];
+#pragma unroll
+                for (int k = 0; k < kBlk; k++) {
+                    const int64_t s = s_hi - k;
+                    const uint32_t i = (uint32_t)s * W + L;
+                    sy[k] = (s >= 0 && L < W && i < n) ? (uint32_t)sym[i] : 0xFFu;
+                }
+#pragma unroll
+                for (int k = 0; k < kBlk; k++) {
+                    const int64_t s = s_hi - k;
+                    const uint32_t i = (uint32_t)s * W + L;
+                    const bool act = sy[k] != 0xFFu;  // (false for every lane once s < 0)
+                    bool emit = false;
+                    uint32_t wd = 0;
+                    if (act) {
+                        const uint32_t tb = i >= leaf ? 1u : 0u;
+                        const uint32_t f = tf[tb][sy[k]], c = tc[tb][sy[k]];
+                        uint32_t v = x;
+                        if ((uint64_t)v >= xmax_unit * f) {
+                            emit = true;
+                            wd = v & 0xFFFFu;
+                            v >>= 16;
+                        }
+                        // v / f: a double reciprocal is within one of the
+                        // quotient; the remainder corrects it
+                        uint32_t q = (uint32_t)((double)v * trcp[tb][sy[k]]);
+                        int64_t r = (int64_t)v - (int64_t)q * f;
+                        if (r < 0) {
+                            q--;
+                            r += f;
+                        } else if (r >= (int64_t)f) {
+                            q++;
+                            r -= f;
+                        }
+                        x = (q << a.bits) + (uint32_t)r + c;
+                    }
+                    // the host order within a step is descending lanes
+                    const uint64_t em = __ballot(emit);
+                    if (emit) words[pushed + (uint32_t)__popcll(L == 63 ? 0ull : (em >> (L + 1)))] = (uint16_t)wd;
+                    pushed += (uint32_t)__popcll(em);
+                }
+            }
+        }
+        const uint32_t nw = pushed;
+        const uint32_t size = (4 * (hdr + Pn + W) + 2 * nw + 3) & ~3u;
+        uint32_t lo = 0, hi = 0;
+        if (L == 0) {
+            const uint64_t o = atomicAdd(a.arena_top, (unsigned long long)size);
+            a.sizes[id] = size;
+            a.aoff[id] = o;
+            lo = (uint32_t)o;
+            hi = (uint32_t)(o >> 32);
+        }
+        const uint64_t off = ((uint64_t)(uint32_t)__shfl((int)hi, 0) << 32) | (uint32_t)__shfl((int)lo, 0);
+        // this wavefront's word stores before its own loads of them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         if (off + size <= a.arena_cap) {
             uint32_t *r = reinterpret_cast<uint32_t *>(a.arena + off);
-            if (t == 0) {
+            if (L == 0) {
                 r[0] = Pn;
                 r[1] = W;
                 r[2] = nw;
-                for (int m = 0; m < kN; m++) r[3 + m] = s_cum[m];
+                for (int m = 0; m < kN; m++) r[3 + m] = a.scum[(size_t)kN * id + m];
             }
-            for (uint32_t i = t; i < Pn; i += kThreads) r[hdr + i] = pal[i];
-            for (uint32_t i = t; i < W; i += kThreads) r[hdr + Pn + i] = xs[i];
+            for (uint32_t i = L; i < Pn; i += 64) r[hdr + i] = pal[i];
+            if (L < W) r[hdr + Pn + L] = x;
             uint16_t *wr = reinterpret_cast<uint16_t *>(r + hdr + Pn + W);
-            // the decoder reads words in symbol order: the reverse of the push order
-            for (uint32_t q = t; q < nw; q += kThreads) wr[q] = words[nw - 1 - q];
-            if (t == 0 && (nw & 1u)) wr[nw] = 0;
+            for (uint32_t q = L; q < nw; q += 64) wr[q] = words[nw - 1 - q];
+            if (L == 0 && (nw & 1u)) wr[nw] = 0;
         }
-        __syncthreads();
-        pc.stop(6);  // record
+        // the words region is reused by this wavefront's next brick
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    pc.flush();
 }
 
 // exclusive scan of the record sizes into the container's u64 index
@@ -564,11 +605,14 @@ struct DevBuf {
 // per device: the buffers of the last call, kept for the next one
 struct EncCache {
     std::mutex mu;
-    DevBuf scratch, hist, sizes, aoff, top, arena, dblob;
+    DevBuf scratch, wscratch, hist, sizes, aoff, top, arena, dblob, sarena, smeta;
     uint8_t *h_pin = nullptr;  // pinned staging of the container on its way to host memory
     size_t h_pin_bytes = 0;
     void release() {
         scratch.release();
+        wscratch.release();
+        sarena.release();
+        smeta.release();
         hist.release();
         sizes.release();
         aoff.release();
@@ -632,12 +676,17 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     EncCache *ec = cache_for(device);
     if (!ec) return CSV_ENOMEM;
     std::lock_guard<std::mutex> lk(ec->mu);  // one compression per device at a time
-    DevBuf &scratch = ec->scratch, &hist = ec->hist, &sizes = ec->sizes, &aoff = ec->aoff, &top = ec->top,
-           &arena = ec->arena, &dblob = ec->dblob;
-    if (!scratch.ensure(kScratch * grid) || !hist.ensure(32 * 8) || !sizes.ensure(4ull * B) ||
-        !aoff.ensure(8ull * B) || !top.ensure(8) || !arena.ensure(cap))
+    DevBuf &scratch = ec->scratch, &wscratch = ec->wscratch, &hist = ec->hist, &sizes = ec->sizes,
+           &aoff = ec->aoff, &top = ec->top, &arena = ec->arena, &dblob = ec->dblob, &sarena = ec->sarena,
+           &smeta = ec->smeta;
+    const uint32_t waves2 = (uint32_t)std::min<uint64_t>((B64 + 3) / 4, (uint64_t)cu * 4) * 4;
+    uint64_t scap = std::max<uint64_t>(16ull << 20, raw / 8);
+    if (!scratch.ensure(kScratch * grid) || !wscratch.ensure(kWordsScratch * waves2) || !hist.ensure(32 * 8) ||
+        !sizes.ensure(4ull * B) || !aoff.ensure(8ull * B) || !top.ensure(16) || !arena.ensure(cap) ||
+        !sarena.ensure(scap) || !smeta.ensure((8ull + 4 + 4 + 4 * kN) * B))
         return CSV_ENOMEM;
     cap = arena.bytes;
+    scap = sarena.bytes;
     EncArgs a;
     std::memset(&a, 0, sizeof(a));
     a.vol = labels;
@@ -646,25 +695,41 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     a.nz = nz;
     a.nbx = nbx;
     a.nby = nby;
+    a.n_items = B;
+    a.sample_stride = stride;
     a.bits = o.scale_bits;
     a.lane_k = o.lane_k;
     a.lane_max = o.lane_max;
     a.scratch = scratch.as<uint8_t>();
+    a.wscratch = wscratch.as<uint8_t>();
     a.hist = hist.as<unsigned long long>();
     a.arena_top = top.as<unsigned long long>();
+    a.sarena_top = top.as<unsigned long long>() + 1;
     a.sizes = sizes.as<uint32_t>();
     a.aoff = aoff.as<uint64_t>();
-    // prepass: symbol histograms of the sampled bricks
-    const uint32_t n_samples = (uint32_t)((B64 + stride - 1) / stride);
-    a.count_mode = 1;
-    a.n_items = n_samples;
-    a.stride = stride;
-    if (hipMemsetAsync(a.hist, 0, 32 * 8, s) != hipSuccess) return CSV_EHIP;
-    hipLaunchKernelGGL(encode_kernel, dim3(std::min(grid, n_samples)), dim3(kThreads), 0, s, a);
+    a.soff = smeta.as<uint64_t>();
+    a.sn = reinterpret_cast<uint32_t *>(a.soff + B);
+    a.sp = a.sn + B;
+    a.scum = a.sp + B;
+    // symbols of every brick (and the sampled bricks' histograms); a second
+    // pass with the exact arena size if they did not fit
+    uint64_t used = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        a.sarena = sarena.as<uint8_t>();
+        a.sarena_cap = scap;
+        if (hipMemsetAsync(a.hist, 0, 32 * 8, s) != hipSuccess || hipMemsetAsync(a.sarena_top, 0, 8, s) != hipSuccess)
+            return CSV_EHIP;
+        hipLaunchKernelGGL(symbols_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&used, a.sarena_top, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return CSV_EHIP;
+        if (used <= scap) break;
+        scap = used;
+        if (pass == 1 || !sarena.ensure(scap)) return CSV_ENOMEM;
+    }
     uint64_t cnt[2][16];
-    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(cnt, a.hist, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return CSV_EHIP;
+    if (hipMemcpy(cnt, a.hist, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return CSV_EHIP;
     if (o.tables == 1)  // one table for all symbols
         for (int q = 0; q < 16; q++) cnt[0][q] = cnt[1][q] = cnt[0][q] + cnt[1][q];
     uint32_t f[2][16];
@@ -677,16 +742,13 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
             c += f[k][q];
         }
     }
-    // all bricks; a second pass with the exact arena size if the records did not fit
-    a.count_mode = 0;
-    a.n_items = B;
-    a.stride = 1;
-    uint64_t used = 0;
+    // rANS and records, a wavefront per brick; a second pass with the exact
+    // arena size if the records did not fit
     for (int pass = 0; pass < 2; pass++) {
         a.arena = arena.as<uint8_t>();
         a.arena_cap = cap;
         if (hipMemsetAsync(a.arena_top, 0, 8, s) != hipSuccess) return CSV_EHIP;
-        hipLaunchKernelGGL(encode_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(rans_kernel, dim3(waves2 / 4), dim3(kThreads), 0, s, a);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(&used, a.arena_top, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
