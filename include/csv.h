@@ -159,14 +159,19 @@ int csv_pool_add_volume_ex(csv_pool *pool, const uint8_t *blob, size_t blob_byte
  * `stream`, in order, until the buffer is full.  *n_done receives how many
  * leading ids were handled (bricks of ordinary volumes and bricks already
  * staged count as handled): decodes of those at full LOD, on the same
- * stream after this call, read their detail.  Staged detail stays until
- * csv_pool_release_detail.  Staging, decodes and release of one pool belong
- * on one stream; not for stream capture.  Errors: CSV_EINVAL, CSV_ERANGE (an
+ * stream after this call, read their detail (the stream also waits for the
+ * staging copies that earlier calls made on other streams).  Staged detail
+ * stays until csv_pool_release_detail, which must follow the decodes that
+ * read it; not for stream capture.  Errors: CSV_EINVAL, CSV_ERANGE (an
  * id out of range: *n_done is its index), CSV_ENOMEM, CSV_EHIP.
  */
 int csv_pool_stage_detail(csv_pool *pool, const uint32_t *brick_ids, uint32_t n, void *stream, uint32_t *n_done);
 /* Drop all staged detail (after the decodes that used it, in stream order). */
 int csv_pool_release_detail(csv_pool *pool, void *stream);
+/* The bytes brick_id's level-0 detail takes in the staging buffer (0: its
+ * record is whole in HBM), and the staging buffer's size; either pointer may
+ * be NULL.  Errors: CSV_EINVAL, CSV_ERANGE (unknown id). */
+int csv_pool_detail_bytes(const csv_pool *pool, uint32_t brick_id, uint32_t *bytes, uint64_t *staging_bytes);
 /* Size of the staging buffer (bytes, 4 KiB .. 64 GiB); CSV_EBUSY while detail is staged. */
 int csv_pool_set_detail_staging(csv_pool *pool, uint64_t bytes);
 
@@ -349,15 +354,23 @@ typedef struct {
     uint64_t stall_batch, stall_inflight, stall_slot; /* admission rounds stopped by: no free batch,
                                                          the in-flight budget, no cache slot */
     uint64_t skipped;          /* requests completed as invisible (not in the latency figures) */
+    uint64_t stall_staging;    /* admission rounds stopped by a full detail staging buffer */
+    uint64_t detail_staged_bytes; /* level-0 detail promised to full-LOD misses (staging granules) */
+    uint64_t detail_releases;  /* times the staged detail was dropped */
 } csv_stats;
 
 /* Clock of arrival and completion times (steady, nanoseconds). */
 uint64_t csv_now_ns(void);
 
 /* Start a server on a pool (its own worker thread, streams, HBM cache).
- * The pool must outlive the server and gain no volumes while it runs; a
- * pool holding level-0 detail in host memory (CSV_DETAIL_HOST) is refused
- * with CSV_EINVAL. */
+ * The pool must outlive the server and gain no volumes while it runs.  On a
+ * pool holding level-0 detail in host memory (CSV_DETAIL_HOST, Sec. 4.2) a
+ * full-LOD miss is admitted while the pool's staging buffer has room for
+ * its detail; a batch stages the detail of its full-LOD bricks on its
+ * stream before the decode, and the staged detail is released once no
+ * launched batch reads it.  A full-LOD request whose detail exceeds the
+ * staging buffer completes with CSV_EDETAIL (data NULL).  The staging
+ * buffer is not resized while the server runs. */
 int csv_server_create(csv_pool *pool, const csv_server_opts *opts, csv_server **server);
 /* Queue n requests (host memory; thread safe; returns at once). */
 int csv_server_submit(csv_server *server, const csv_request *requests, uint32_t n);

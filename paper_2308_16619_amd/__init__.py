@@ -72,7 +72,8 @@ class Stats(ctypes.Structure):
         (n, ctypes.c_double) for n in ("p50_us", "p99_us", "p50_miss_us", "p99_miss_us", "max_us")] + [
         ("error", ctypes.c_int32), ("pad", ctypes.c_int32), ("worker_busy_ns", ctypes.c_uint64),
         ("worker_launch_ns", ctypes.c_uint64), ("stall_batch", ctypes.c_uint64), ("stall_inflight", ctypes.c_uint64),
-        ("stall_slot", ctypes.c_uint64), ("skipped", ctypes.c_uint64)]
+        ("stall_slot", ctypes.c_uint64), ("skipped", ctypes.c_uint64), ("stall_staging", ctypes.c_uint64),
+        ("detail_staged_bytes", ctypes.c_uint64), ("detail_releases", ctypes.c_uint64)]
 
 
 class PoolInfo(ctypes.Structure):

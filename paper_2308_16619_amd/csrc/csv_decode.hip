@@ -2288,7 +2288,19 @@ int csv_pool_stage_detail(csv_pool *p, const uint32_t *ids, uint32_t n, void *st
             hipEventRecord(p->stage_ev, s) != hipSuccess)
             return CSV_EHIP;
     }
+    // work on this stream sees the detail staged by earlier calls on any stream
+    if (hipStreamWaitEvent(s, p->stage_ev, 0) != hipSuccess) return CSV_EHIP;
     return bad_id ? CSV_ERANGE : CSV_OK;
+}
+
+int csv_pool_detail_bytes(const csv_pool *p, uint32_t id, uint32_t *bytes, uint64_t *staging_bytes) {
+    if (!p || (!bytes && !staging_bytes)) return CSV_EINVAL;
+    if (staging_bytes) *staging_bytes = p->stage_cap;
+    if (!bytes) return CSV_OK;
+    if (id >= p->rec_ptr.size()) return CSV_ERANGE;
+    // the bytes it takes in the staging buffer (16-byte granules)
+    *bytes = id < p->det_bytes.size() ? (p->det_bytes[id] + 15u) & ~15u : 0u;
+    return CSV_OK;
 }
 
 int csv_pool_release_detail(csv_pool *p, void *stream) {

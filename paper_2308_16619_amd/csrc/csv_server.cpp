@@ -76,6 +76,9 @@ struct Batch {
     std::vector<uint32_t> entries;  // entry ids decoded by this batch
     uint64_t bytes = 0;
     bool busy = false;
+    // full-LOD bricks whose level-0 detail is in host memory: staged before the decode
+    std::vector<uint32_t> stage_ids;
+    bool staged = false;
 };
 
 }  // namespace
@@ -123,7 +126,13 @@ struct csv_server {
     std::deque<float> lat_all, lat_miss;  // a deque grows without copying what it holds
     uint64_t n_req = 0, n_hit = 0, n_miss = 0, n_join = 0, n_batches = 0, n_evict = 0, n_rebuild = 0,
              decoded_bytes = 0, n_launch_err = 0, busy_ns = 0, launch_ns = 0, n_skip = 0;
-    uint64_t stall[3] = {0, 0, 0};  // admission stopped: no free batch, in-flight budget, no slot
+    uint64_t stall[4] = {0, 0, 0, 0};  // admission stopped: no free batch, in-flight budget, no slot, staging
+    // detail separation (Sec. 4.2): bytes of the staging buffer promised to
+    // admitted full-LOD misses since the last release, launched batches that
+    // staged detail and have not retired
+    bool split = false;
+    uint64_t stage_cap = 0, stage_planned = 0, n_staged_bytes = 0, n_releases = 0;
+    uint32_t staged_inflight = 0;
 
     std::atomic<uint64_t> submitted{0}, completed{0};
     std::atomic<bool> stop{false};
@@ -317,8 +326,18 @@ void launch_batch(csv_server *s, Batch *b) {
     const uint64_t *d_off = reinterpret_cast<const uint64_t *>(b->d_buf);
     const uint32_t *d_ids = reinterpret_cast<const uint32_t *>(d_off + n);
     const uint8_t *d_lods = reinterpret_cast<const uint8_t *>(d_ids + n);
-    int rc = csv_decode_bricks(s->pool, d_ids, d_lods, 0, d_off, n,
-                               reinterpret_cast<uint32_t *>(s->d_cache), b->stream);
+    int rc = CSV_OK;
+    if (!b->stage_ids.empty()) {
+        // the level-0 detail of the batch's full-LOD bricks, on the batch's stream
+        uint32_t done = 0;
+        rc = csv_pool_stage_detail(s->pool, b->stage_ids.data(), (uint32_t)b->stage_ids.size(), b->stream, &done);
+        if (!rc && done != b->stage_ids.size()) rc = CSV_ENOMEM;
+        b->staged = true;
+        s->staged_inflight++;
+    }
+    if (!rc)
+        rc = csv_decode_bricks(s->pool, d_ids, d_lods, 0, d_off, n, reinterpret_cast<uint32_t *>(s->d_cache),
+                               b->stream);
     if (!rc && hipEventRecord(b->done, b->stream) != hipSuccess) rc = CSV_EHIP;
     if (rc) {
         s->n_launch_err++;
@@ -347,6 +366,24 @@ void retire(csv_server *s, Batch &b, uint64_t t) {
     b.entries.clear();
     b.bytes = 0;
     b.busy = false;
+    if (b.staged) {
+        s->staged_inflight--;
+        b.staged = false;
+    }
+    b.stage_ids.clear();
+}
+
+// the staged detail is dropped once no launched batch reads it and the
+// batch being formed has promised none of it
+void release_detail(csv_server *s) {
+    if (!s->split || s->stage_planned == 0 || s->staged_inflight != 0) return;
+    if (s->forming && !s->forming->stage_ids.empty()) return;
+    if (csv_pool_release_detail(s->pool, s->batches[0].stream) != CSV_OK) {
+        s->n_launch_err++;
+        s->error = CSV_EHIP;
+    }
+    s->stage_planned = 0;
+    s->n_releases++;
 }
 
 // one request: true if handled (completed, joined or admitted), false if it
@@ -378,6 +415,19 @@ bool admit(csv_server *s, const Pending &p, uint64_t t_now) {
         return true;
     }
     const uint64_t bytes = class_bytes(r.lod);
+    // a full-LOD miss on a brick with its detail in host memory takes its
+    // share of the staging buffer until the next release
+    uint32_t det = 0;
+    if (s->split && r.lod == 0 && csv_pool_detail_bytes(s->pool, r.brick_id, &det, nullptr) == CSV_OK && det) {
+        if (det > s->stage_cap) {  // can never be staged
+            complete(s, p.idx, nullptr, CSV_EDETAIL, false, t_now);
+            return true;
+        }
+        if (s->stage_planned + det > s->stage_cap) {
+            s->stall[3]++;
+            return false;
+        }
+    }
     // decodes in flight hold cache slots: keep them within a quarter of the cache
     const uint64_t budget = std::min(s->opts.inflight_bytes, s->opts.cache_bytes / 4);
     if (s->inflight + bytes > budget && s->inflight > 0) {
@@ -418,6 +468,11 @@ bool admit(csv_server *s, const Pending &p, uint64_t t_now) {
     s->index[key] = (int32_t)nid;
     s->forming->entries.push_back(nid);
     s->forming->bytes += bytes;
+    if (det) {
+        s->forming->stage_ids.push_back(r.brick_id);
+        s->stage_planned += det;
+        s->n_staged_bytes += det;
+    }
     s->inflight += bytes;
     s->d_miss++;
     if (s->forming->entries.size() >= s->opts.max_batch) {
@@ -464,6 +519,7 @@ void worker_main(csv_server *s) {
                 work = true;
             }
         }
+        release_detail(s);
         // entries pinned by completions the client has released
         {
             std::vector<uint32_t> rel;
@@ -532,8 +588,7 @@ int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out
     csv_pool_info info;
     int rc = csv_pool_info_get(pool, &info);
     if (rc) return rc;
-    // a full-LOD miss must not be served (and cached) from level 1
-    if (info.n_bricks == 0 || info.host_bytes) return CSV_EINVAL;
+    if (info.n_bricks == 0) return CSV_EINVAL;
     csv_server *s = new (std::nothrow) csv_server;
     if (!s) return CSV_ENOMEM;
     s->pool = pool;
@@ -541,6 +596,11 @@ int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out
     s->opts.cache_bytes = opts.cache_bytes / kPage * kPage;
     s->device = info.device;
     s->n_bricks = info.n_bricks;
+    s->split = info.host_bytes != 0;
+    if (s->split && csv_pool_detail_bytes(pool, 0, nullptr, &s->stage_cap) != CSV_OK) {
+        delete s;
+        return CSV_EINVAL;
+    }
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
@@ -633,6 +693,9 @@ int csv_server_stats(csv_server *s, csv_stats *st) {
     st->stall_inflight = s->stall[1];
     st->stall_slot = s->stall[2];
     st->skipped = s->n_skip;
+    st->stall_staging = s->stall[3];
+    st->detail_staged_bytes = s->n_staged_bytes;
+    st->detail_releases = s->n_releases;
     return CSV_OK;
 }
 
@@ -644,7 +707,8 @@ int csv_server_reset_stats(csv_server *s) {
     s->n_req = s->n_hit = s->n_miss = s->n_join = s->n_batches = s->n_evict = s->n_rebuild = 0;
     s->decoded_bytes = 0;
     s->busy_ns = s->launch_ns = 0;
-    s->stall[0] = s->stall[1] = s->stall[2] = 0;
+    s->stall[0] = s->stall[1] = s->stall[2] = s->stall[3] = 0;
+    s->n_staged_bytes = s->n_releases = 0;
     s->n_skip = 0;
     return CSV_OK;
 }

@@ -214,8 +214,60 @@ def test_split_then_ordinary_volume(csvlib, orc, volumes):
         np.testing.assert_array_equal(got, orc.decode_bricks(b, ids, lods))
 
 
-def test_server_refuses_host_detail(csvlib, volumes):
-    pool, _ = split_pool(csvlib, volumes[:1], detail=(True,))
-    with pytest.raises(csvlib.CsvError) as e:
-        csvlib.Server(pool, cache_bytes=16 << 20)
-    assert e.value.code == csvlib.CSV_EINVAL
+def wait_all(server, n, timeout=60.0):
+    import time
+    got, t0 = 0, time.time()
+    while got < n:
+        c = server.poll()
+        if len(c):
+            got += len(c)
+            yield c
+        elif time.time() - t0 > timeout:
+            raise TimeoutError("server completed %d of %d" % (got, n))
+        else:
+            time.sleep(0.0005)
+
+
+@pytest.mark.parametrize("staging", [8 << 20, 16 << 10, 4096])
+def test_server_stages_detail(csvlib, orc, volumes, staging):
+    # the serving loop over a pool with level-0 detail in host memory: every
+    # full-LOD brick is decoded exactly (its detail staged for its batch),
+    # except bricks whose detail exceeds the staging buffer (CSV_EDETAIL)
+    pool = csvlib.Pool()
+    f_plain = pool.add_volume(volumes[0])
+    f_cells = pool.add_volume(volumes[2], detail_host=True)
+    f_edge = pool.add_volume(volumes[1], detail_host=True)
+    blobs = {f_plain: volumes[0], f_cells: volumes[2], f_edge: volumes[1]}
+    det = np.concatenate([np.zeros(8, np.int64), split_plan(orc, volumes[2]), split_plan(orc, volumes[1])])
+    det16 = (det + 15) & ~15
+    assert pool.info()["host_bytes"] == int(det.sum())
+    pool.set_detail_staging(staging)
+    n_b = len(det)
+    rng = np.random.default_rng(staging % 1000 + 3)
+    n = 2500
+    ids = rng.integers(0, n_b, n).astype(np.uint32)
+    lods = rng.choice([0, 0, 0, 1, 2, 5], n).astype(np.uint32)
+    srv = csvlib.Server(pool, cache_bytes=64 << 20, inflight_bytes=1 << 20, max_batch=64, streams=3)
+    log("serving a split pool, staging %d bytes, %d requests" % (staging, n))
+    for k in range(0, n, 500):
+        srv.submit(srv.requests(ids[k:k + 500], lods[k:k + 500], tags=np.arange(k, min(n, k + 500))))
+    seen = edetail = 0
+    for comp in wait_all(srv, n):
+        for c in comp:
+            b, t = int(c["brick_id"]), int(c["lod"])
+            first = max(f for f in blobs if f <= b)
+            if t == 0 and det16[b] > staging:
+                assert c["status"] == csvlib.CSV_EDETAIL, (b, c["status"])
+                edetail += 1
+            else:
+                assert c["status"] == 0, (b, t, c["status"])
+                np.testing.assert_array_equal(srv.read(c), orc.decode_brick(blobs[first], b - first, t).ravel())
+            seen += 1
+    st = srv.stats()
+    srv.close()
+    log("stats %s" % {k: st[k] for k in ("hits", "misses", "stall_staging", "detail_staged_bytes",
+                                         "detail_releases", "p99_us")})
+    assert seen == n and st["error"] == 0
+    assert st["detail_staged_bytes"] > 0 and st["detail_releases"] > 0
+    assert (edetail > 0) == bool((det16[ids[lods == 0]] > staging).any())
+    assert pool.last_error() == (0, 0)
