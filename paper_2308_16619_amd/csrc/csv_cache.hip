@@ -95,7 +95,6 @@ __global__ void evict_kernel(CacheDev c) {
 // rebuild that gives every distinct key of the frame a block from an empty
 // cache; the decode list
 __global__ __launch_bounds__(1024) void assign_kernel(CacheDev c) {
-    __shared__ uint64_t s_need;
     __shared__ uint32_t s_rebuild;
     const uint32_t tid = threadIdx.x;
     FrameState *st = c.st;
@@ -105,7 +104,6 @@ __global__ __launch_bounds__(1024) void assign_kernel(CacheDev c) {
             const uint32_t m = st->n_miss[t], avail = st->stack_top[t];
             if (m > avail) need += (uint64_t)(m - avail) * block_elems(t);
         }
-        s_need = need;
         s_rebuild = st->top + need > c.cap_elems ? 1u : 0u;
     }
     __syncthreads();

@@ -28,6 +28,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "csv.h"
@@ -780,7 +781,16 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
         return CSV_EHIP;
     uint8_t *out = static_cast<uint8_t *>(std::malloc(total));
     if (!out) return CSV_ENOMEM;
-    std::memcpy(out, ec->h_pin, total);
+    // into fresh host pages: several threads share the page faults and the copy
+    const unsigned nt = total >= (8u << 20) ? 8u : 1u;
+    const size_t chunk = (total + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (unsigned k = 1; k < nt; k++) {
+        const size_t o = k * chunk, len = o < total ? std::min(chunk, total - o) : 0;
+        if (len) th.emplace_back([=] { std::memcpy(out + o, ec->h_pin + o, len); });
+    }
+    std::memcpy(out, ec->h_pin, std::min(chunk, total));
+    for (auto &x : th) x.join();
     csv::VolumeHeader h;
     std::memset(&h, 0, sizeof(h));
     h.magic = csv::kMagic;
