@@ -43,7 +43,7 @@ namespace {
 
 constexpr int kN = 5;
 constexpr uint32_t kThreads = 256;
-constexpr uint32_t kPer = 4;                  // child slots per thread per chunk
+constexpr uint32_t kPer = 3;                  // child slots per thread per chunk
 constexpr uint32_t kChunk = kThreads * kPer;
 constexpr uint32_t kNone = 0xFFFFFFFFu;       // no slot
 constexpr uint32_t kNodes = 4681;           // levels 1..5 of a 32^3 brick
@@ -205,9 +205,10 @@ __device__ __forceinline__ uint32_t mode8(const uint32_t ch[8], bool &same) {
 
 // Pyramid, operations and palette of one brick per workgroup; the symbol
 // stream and palette go to the arena for the rANS kernel.
-__global__ __launch_bounds__(kThreads) void symbols_kernel(EncArgs a) {
+// (LDS under 32 KB and 5 waves per SIMD: five workgroups per CU)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void symbols_kernel(EncArgs a) {
     __shared__ uint32_t lab[kNodes];
-    __shared__ uint8_t cst[kNodes];
+    __shared__ uint32_t cstb[(kNodes + 31) / 32];  // constant-subtree flags, one bit per node
     __shared__ uint16_t expl[4096];
     __shared__ uint32_t c_lab[kChunk];
     __shared__ uint8_t c_op[kChunk];
@@ -230,8 +231,9 @@ __global__ __launch_bounds__(kThreads) void symbols_kernel(EncArgs a) {
         b.x0 = (id % a.nbx) * 32;
         b.y0 = ((id / a.nbx) % a.nby) * 32;
         b.z0 = (id / ((uint64_t)a.nbx * a.nby)) * 32;
+        for (uint32_t i = t; i < (kNodes + 31) / 32; i += kThreads) cstb[i] = 0;
+        __syncthreads();
         // level 1 from the volume (every level-0 node is a constant subtree)
-#pragma unroll 2
         for (uint32_t q = t; q < 4096; q += kThreads) {
             const uint32_t x = 2 * compact3(q), y = 2 * compact3(q >> 1), z = 2 * compact3(q >> 2);
             uint32_t ch[8];
@@ -239,22 +241,34 @@ __global__ __launch_bounds__(kThreads) void symbols_kernel(EncArgs a) {
             for (int k = 0; k < 8; k++) ch[k] = voxel(a, b, x + (k & 1), y + ((k >> 1) & 1), z + (k >> 2));
             bool same;
             lab[q] = mode8(ch, same);
-            cst[q] = same ? 1 : 0;
+            // a wavefront's 64 nodes are one aligned pair of flag words
+            const uint64_t bm = __ballot(same);
+            if (L == 0) {
+                cstb[q >> 5] = (uint32_t)bm;
+                cstb[(q >> 5) + 1] = (uint32_t)(bm >> 32);
+            }
         }
         __syncthreads();
         for (int l = 2; l <= kN; l++) {
             const uint32_t n = 1u << (3 * (kN - l)), lo = lvl_off(l - 1), hi = lvl_off(l);
             for (uint32_t q = t; q < n; q += kThreads) {
                 uint32_t ch[8];
-                bool allc = true;
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
-                    ch[k] = lab[lo + 8 * q + k];
-                    allc &= cst[lo + 8 * q + k] != 0;
-                }
+                for (int k = 0; k < 8; k++) ch[k] = lab[lo + 8 * q + k];
+                // the 8 children's flags: one byte of a word (lo and 8q are multiples of 8)
+                const uint32_t c8 = lo + 8 * q;
+                const bool allc = ((cstb[c8 >> 5] >> (c8 & 31)) & 0xFFu) == 0xFFu;
                 bool same;
                 lab[hi + q] = mode8(ch, same);
-                cst[hi + q] = (same && allc) ? 1 : 0;
+                if (n >= 64) {  // levels 2, 3: as level 1 (their offsets are multiples of 64)
+                    const uint64_t bm = __ballot(same && allc);
+                    if (L == 0) {
+                        cstb[(hi + q) >> 5] = (uint32_t)bm;
+                        cstb[((hi + q) >> 5) + 1] = (uint32_t)(bm >> 32);
+                    }
+                } else if (same && allc) {  // levels 4, 5 share a word
+                    atomicOr(&cstb[(hi + q) >> 5], 1u << ((hi + q) & 31));
+                }
             }
             __syncthreads();
         }
@@ -272,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void symbols_kernel(EncArgs a) {
             uint32_t E = 0;
             for (uint32_t q0 = 0; q0 < np; q0 += kThreads) {
                 const uint32_t q = q0 + t;
-                const bool f = q < np && !cst[lvl_off(l) + q];
+                const bool f = q < np && !((cstb[(lvl_off(l) + q) >> 5] >> ((lvl_off(l) + q) & 31)) & 1u);
                 uint32_t tot;
                 const uint32_t r = wg_rank(f, tot, wcnt);
                 if (f) expl[E + r] = (uint16_t)q;
@@ -319,7 +333,8 @@ __global__ __launch_bounds__(kThreads) void symbols_kernel(EncArgs a) {
                                                ? csv::kRx
                                                : (nok[1] && nv[1] == lbl ? csv::kRy
                                                                          : (nok[2] && nv[2] == lbl ? csv::kRz : csv::kPa)));
-                        const uint32_t stop = (m >= 1 && cst[lvl_off(m) + j]) ? 1u : 0u;
+                        const uint32_t stop =
+                            (m >= 1 && ((cstb[(lvl_off(m) + j) >> 5] >> ((lvl_off(m) + j) & 31)) & 1u)) ? 1u : 0u;
                         op |= stop << 8;
                     }
                     opv[u] = op;
@@ -671,7 +686,7 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1) cu = 1;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(B64, (uint64_t)cu * 4);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(B64, (uint64_t)cu * 5);  // symbols kernel: 5 workgroups per CU
     const uint64_t raw = (uint64_t)nx * ny * nz * 4;
     uint64_t cap = std::max<uint64_t>(16ull << 20, raw / 8);
     EncCache *ec = cache_for(device);
