@@ -125,3 +125,11 @@ def test_gpu_encoder_input_forms_and_errors(csvlib, orc):
         csvlib.encode_volume_gpu(d, brick_log2=4)
     with pytest.raises(csvlib.CsvError):
         csvlib.encode_volume_gpu(d, lane_max=48)
+
+
+def test_gpu_encoder_full_size_workload(csvlib, orc):
+    # the benchmark's 512^3 cells volume (4096 bricks), in the launch
+    # configuration the benchmark times, against the oracle's container
+    vol = synth.cells(n=512, grid=37, p_noise=0.5, seed=2)
+    blob = check(csvlib, orc, "cells512", vol)
+    assert csvlib.blob_info(blob)["n_bricks"] == 4096
