@@ -1,13 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark: GPU decode throughput of compressed segmentation volumes.
 
-Workload (one step): decode all 4096 bricks of a 512^3 uint32 'cells'
-volume (jittered-grid Voronoi of 50,653 labels with 1-voxel boundary
-noise, seeded synthetic data) at full level of detail, in one launch of the
-HIP decoder, compressed pool and output resident in HBM.
+Workload (one step): decode all 32,768 bricks of a 1024^3 uint32
+neurite-like volume (20,000 labels, random-walk branching tubes of radius
+2-8 voxels, Zipf-distributed sizes, about 45 % background; seeded synthetic
+data) at full level of detail in one decode call of the HIP decoder, the
+compressed pool and the 4.3 GB output resident in HBM.
 
 Prints one JSON line: decoded GB/s (uint32 labels), the HBM roofline of the
-decode kernel, the one-launch-per-brick baseline and the CPU oracle.
+decode call, the same volume at half LOD, 16,384 uneven mixed-LOD requests
+over three volumes, a 512^3 cells volume, the one-launch-per-brick
+baseline, the CPU oracle (all host threads and one), detail separation,
+the GPU compressor and the serving loop.
 """
 from __future__ import annotations
 
@@ -25,12 +29,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# HBM bytes of one decode call on this workload (front + leaf kernel), from
-# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same
-# counters read for a plain 256 MiB device copy; see
-# profiles/decode_cells512_hbm_traffic.md.  Valid only for the decoder source
-# the counters were taken on (at the launch shape named here).
-TRAFFIC = {"decoder_sha256_16": "0a361a2a6bff5fcb", "shape": (16, 3, 0, 0), "bytes": 655371445}
+# HBM bytes of one decode call on the headline workload (front + leaf
+# kernel), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
+# what the same counters read for a plain 256 MiB device copy; see
+# profiles/decode_neurite1024_hbm_traffic.md.  Valid only for the decoder
+# source the counters were taken on (at the launch shape named here).
+TRAFFIC = {"decoder_sha256_16": None, "shape": None, "bytes": None}
+PAPER_GBS = {"cells": 9.9, "fiber": 10.4, "cortex": 9.3}  # Table 3, RTX 3070 Ti (context only)
 
 
 def log(msg):
@@ -45,14 +50,55 @@ def decoder_hash():
     return h.hexdigest()[:16]
 
 
-def record_bytes(blob: bytes, ids, lod: int) -> int:
-    """Algorithmic compressed bytes a decode at `lod` must read: record
-    header, palette, lane states and the words of the decoded prefix (all
-    words for full LOD)."""
+def record_sizes(blob: bytes) -> np.ndarray:
     B = int(np.frombuffer(blob, np.uint32, 1, 36)[0])
     idx = np.frombuffer(blob, np.uint64, B + 1, 128)
-    sizes = np.diff(idx).astype(np.int64)
-    return int(sizes[np.asarray(ids)].sum())
+    return np.diff(idx).astype(np.int64)
+
+
+def record_bytes(blob: bytes, ids) -> int:
+    """Compressed bytes a full-LOD decode of `ids` must read: each whole
+    record (header, palette, lane states, all words)."""
+    return int(record_sizes(blob)[np.asarray(ids)].sum())
+
+
+def prefix_record_bytes(csv, blob: bytes) -> tuple:
+    """Per brick, the bytes a decode to level 1 must read: header, palette,
+    lane states and the words of the level-1 prefix (rounded up to a dword).
+    The pool's detail separation finds that prefix (it decodes every brick to
+    level 1 once and keeps exactly those bytes on the device); a brick whose
+    record is all prefix keeps its whole record."""
+    p = csv.Pool(0)
+    p.add_volume(blob, detail_host=True)
+    sizes = record_sizes(blob)
+    host = p.info()["host_bytes"]
+    p.close()
+    return sizes, int(sizes.sum()) - int(host)
+
+
+def timed_calls(torch, fn, steps, warmup):
+    """ms per call of fn() over `steps` calls (HIP events on the current stream)."""
+    for _ in range(warmup):
+        fn()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def frame_cache_leg(csv, torch, pool, ids, lods, t_ns, fps=60):
@@ -269,21 +315,32 @@ def encoder_leg(csv, torch, vol, blob, host_s, host_threads, reps=3):
             "identical_bytes": True, "raw_bytes": raw, "compressed_bytes": len(blob)}
 
 
+def config4_requests(n=16384, seed=5):
+    """16,384 requests over three volumes (64^3 Voronoi, 512^3 cells, 512^3
+    smooth blobs): source uniform, brick uniform within it, LOD uniform in
+    {0, 1, 2}."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, 3, n)
+    return rng, src
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="CPU oracle time on all host threads")
     ap.add_argument("--plain-bricks", type=int, default=1024, help="bricks in the per-brick-launch baseline")
+    ap.add_argument("--legs", choices=["all", "headline"], default="all",
+                    help="headline: only the timed full-LOD decode of the 1024^3 volume (for profiler runs)")
     ap.add_argument("--serving", choices=["full", "none"], default="full",
                     help="serving leg: the 2048x2048x1024 neurite pool with camera-path traces (full) or none")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="measured trace length per serving run")
     ap.add_argument("--detail", choices=["full", "none"], default="full",
-                    help="detail-separation leg (a second pool of the volume with level-0 detail in host memory)")
+                    help="detail-separation leg (the 512^3 cells volume with level-0 detail in host memory)")
     ap.add_argument("--encoder", choices=["full", "none"], default="full",
-                    help="GPU compressor leg (the same volume compressed on the device)")
+                    help="GPU compressor leg (the 512^3 cells volume compressed on the device)")
     ap.add_argument("--shape", default="", help="fixed launch shape 'waves,groups,queue,lpt' instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for hardware byte counters)")
@@ -300,41 +357,41 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     dev = torch.device("cuda:0")
     csv.lib()
+    headline_only = args.legs == "headline"
+    fixed = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
 
-    log("generating 512^3 cells volume")
+    def pick_shape(pool, ids, out, **kw):
+        """The launch shape: fixed by --shape, else the autotuner's on this request set."""
+        if fixed:
+            pool.set_shape(fixed)
+            return fixed, None
+        shape, tune_ms = pool.autotune(ids, out, reps=3, **kw)
+        torch.cuda.synchronize()
+        assert pool.last_error()[0] == 0
+        return shape, tune_ms
+
+    # ---- headline: the 1024^3 neurite volume, every brick at full LOD ----
+    log("generating the 1024^3 neurite volume")
     t0 = time.time()
-    vol = synth.cells(n=512, grid=37, p_noise=0.5, seed=2)
+    vol3 = synth.neurite(1024, 1024, 1024, labels=20000, seed=3)
     log("generated in %.1fs; encoding" % (time.time() - t0))
     host_threads = 16
     t0 = time.perf_counter()
-    blob = csv.encode_volume(vol, threads=host_threads)
-    host_s = time.perf_counter() - t0
-    info = csv.blob_info(blob)
-    log("encoded in %.1fs: %d bytes, CR %.3f%%" % (host_s, len(blob), 100.0 * len(blob) / vol.nbytes))
-
-    pool = csv.Pool(0)
-    pool.add_volume(blob)
-    B = info["n_bricks"]
-    lod = 0
-    ids_np = np.arange(B, dtype=np.uint32)
-    ids = torch.from_numpy(ids_np.view(np.int32)).to(dev)
-    elems = B * 32 ** 3
-    out = torch.empty(elems, dtype=torch.int32, device=dev)
-    out_bytes = elems * 4
-    in_bytes = record_bytes(blob, ids_np, lod)
-
-    stream = torch.cuda.current_stream()
-    if args.shape:
-        # a fixed launch shape (profiling runs that must compare like with like)
-        shape = tuple(int(v) for v in args.shape.split(","))
-        pool.set_shape(shape)
-        log("fixed shape %s" % (shape,))
-    else:
-        # the launch shape is picked on this request set by the autotuner
-        shape, tune_ms = pool.autotune(ids, out, lod=lod, reps=3)
-        torch.cuda.synchronize()
-        assert pool.last_error()[0] == 0
-        log("autotuned shape %s: %.4f ms" % (shape, tune_ms))
+    blob3 = csv.encode_volume(vol3, threads=host_threads)
+    enc3_s = time.perf_counter() - t0
+    info3 = csv.blob_info(blob3)
+    log("encoded in %.1fs: %d bytes, CR %.3f%%" % (enc3_s, len(blob3), 100.0 * len(blob3) / vol3.nbytes))
+    B3 = info3["n_bricks"]
+    pool3 = csv.Pool(0)
+    pool3.add_volume(blob3)
+    ids3_np = np.arange(B3, dtype=np.uint32)
+    ids3 = torch.from_numpy(ids3_np.view(np.int32)).to(dev)
+    elems3 = B3 * 32 ** 3
+    out3 = torch.empty(elems3, dtype=torch.int32, device=dev)
+    out3_bytes = elems3 * 4
+    in3_bytes = record_bytes(blob3, ids3_np)
+    shape3, tune3 = pick_shape(pool3, ids3, out3, lod=0)
+    log("shape %s (autotuned: %s ms)" % (shape3, tune3))
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -342,108 +399,189 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        pool.decode(ids, out, lod=lod)
+        pool3.decode(ids3, out3, lod=0)
     torch.cuda.synchronize()
-    code, who = pool.last_error()
+    code, who = pool3.last_error()
     assert code == 0, ("decode error", code, who)
     # spot check against the input volume (full LOD is lossless)
-    got = out.view(B, 32, 32, 32)
-    for bid in (0, 1234, B - 1):
-        bx, by, bz = bid % 16, (bid // 16) % 16, bid // 256
-        ref = torch.from_numpy(vol[bz * 32:(bz + 1) * 32, by * 32:(by + 1) * 32, bx * 32:(bx + 1) * 32].astype(np.int64))
+    got = out3.view(B3, 32, 32, 32)
+    for bid in (0, 12345, 20000, B3 - 1):
+        bx, by, bz = bid % 32, (bid // 32) % 32, bid // 1024
+        ref = torch.from_numpy(vol3[bz * 32:(bz + 1) * 32, by * 32:(by + 1) * 32, bx * 32:(bx + 1) * 32].astype(np.int64))
         assert torch.equal(got[bid].cpu().to(torch.int64) & 0xFFFFFFFF, ref), bid
+    del got
 
     log("timing %d steps" % args.steps)
+    stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        pool.decode(ids, out, lod=lod)
+        pool3.decode(ids3, out3, lod=0)
     ev1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms = ev0.elapsed_time(ev1) / args.steps
-    gbs = out_bytes / (ms * 1e-3) / 1e9
-    code, who = pool.last_error()
+    gbs = out3_bytes / (ms * 1e-3) / 1e9
+    code, who = pool3.last_error()
     assert code == 0, ("decode error", code, who)
-
-
-    # per-call time: one decode call (front + leaf kernel) per step, so the event time per step
-    achieved = (in_bytes + out_bytes) / (ms * 1e-3) / 1e9
+    # one decode call (front + leaf kernel) per step: the event time per step
+    achieved = (in3_bytes + out3_bytes) / (ms * 1e-3) / 1e9
     src_hash = decoder_hash()
-    # counters taken on this decoder source (at the launch shape TRAFFIC names), else none
-    traffic = TRAFFIC["bytes"] if src_hash == TRAFFIC["decoder_sha256_16"] else None
+    # counters taken on this decoder source at this launch shape, else none
+    traffic = TRAFFIC["bytes"] if (src_hash == TRAFFIC["decoder_sha256_16"] and
+                                   tuple(shape3) == tuple(TRAFFIC["shape"] or ())) else None
+    del vol3
 
-    # empty-space test (Sec. 4) of the same requests under a transfer
-    # function that shows a seeded 1 in 200 of the labels (a brick holds
-    # about 100, so the test splits the bricks)
-    n_lab = int(vol.max()) + 1
-    show = np.random.default_rng(11).random(n_lab) < 0.005
-    words = np.zeros((n_lab + 31) // 32, np.uint32)
-    nzl = np.nonzero(show)[0].astype(np.uint64)
-    np.bitwise_or.at(words, (nzl >> 5).astype(np.int64), (np.uint64(1) << (nzl & np.uint64(31))).astype(np.uint32))
-    d_words = torch.from_numpy(words.view(np.int32)).to(dev)
-    vmask = torch.empty(B, dtype=torch.uint8, device=dev)
-    for _ in range(3):
-        pool.visible(ids, d_words, n_lab, out=vmask)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(20):
-        pool.visible(ids, d_words, n_lab, out=vmask)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    vis_us = ev0.elapsed_time(ev1) / 20 * 1e3
-    assert pool.last_error()[0] == 0
-    visibility = {"bricks": B, "us_per_call": round(vis_us, 2), "bricks_per_s": round(B / (vis_us * 1e-6), 1),
-                  "visible_frac": round(float(vmask.float().mean().item()), 4),
-                  "transfer_function": "a seeded 1 in 200 of the %d labels visible" % n_lab}
+    extra = {}
+    plain = visibility = detail = encoder = cpu = serving = None
+    if not headline_only:
+        # ---- the same volume at half LOD (16^3 per brick) ----
+        out_h = torch.empty(B3 * 16 ** 3, dtype=torch.int32, device=dev)
+        sh_h, _ = pick_shape(pool3, ids3, out_h, lod=1)
+        ms_h = timed_calls(torch, lambda: pool3.decode(ids3, out_h, lod=1, shape=sh_h), args.steps, args.warmup)
+        assert pool3.last_error()[0] == 0
+        _, in_h = prefix_record_bytes(csv, blob3)
+        ob_h = B3 * 16 ** 3 * 4
+        extra["neurite1024_half_lod"] = {
+            "bricks": B3, "lod": 1, "ms_per_call": round(ms_h, 4), "gbs": round(ob_h / (ms_h * 1e-3) / 1e9, 2),
+            "voxels_per_s": round(B3 * 16 ** 3 / (ms_h * 1e-3), 1), "read_bytes": in_h, "write_bytes": ob_h,
+            "frac": round((in_h + ob_h) / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "shape": list(sh_h)}
+        log("half LOD %s" % extra["neurite1024_half_lod"])
+        del out_h
 
-    # baseline: one launch per brick
-    nb = min(args.plain_bricks, B)
-    pids = ids[:nb].contiguous()
-    pout = out[:nb * 32 ** 3]
-    pool.decode(pids, pout, lod=lod, plain=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    pool.decode(pids, pout, lod=lod, plain=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = ev0.elapsed_time(ev1)
-    plain_gbs = nb * 32 ** 3 * 4 / (plain_ms * 1e-3) / 1e9
-    assert pool.last_error()[0] == 0
+        # ---- baseline: one launch per brick ----
+        nb = min(args.plain_bricks, B3)
+        pids = ids3[:nb].contiguous()
+        pout = out3[:nb * 32 ** 3]
+        plain_ms = timed_calls(torch, lambda: pool3.decode(pids, pout, lod=0, plain=True), 1, 1)
+        assert pool3.last_error()[0] == 0
+        plain = {"value": round(nb * 32 ** 3 * 4 / (plain_ms * 1e-3) / 1e9, 3), "unit": "GB/s", "bricks": nb,
+                 "ms": round(plain_ms, 3)}
 
-    detail = None
-    if args.detail == "full":
-        log("detail separation leg")
-        detail = detail_leg(csv, torch, blob, ids_np, ids, out, shape, pool)
+        # ---- empty-space test (Sec. 4) of the same requests: a transfer
+        # function showing a seeded 1 in 200 of the labels ----
+        n_lab = 20001
+        show = np.random.default_rng(11).random(n_lab) < 0.005
+        words = np.zeros((n_lab + 31) // 32, np.uint32)
+        nzl = np.nonzero(show)[0].astype(np.uint64)
+        np.bitwise_or.at(words, (nzl >> 5).astype(np.int64), (np.uint64(1) << (nzl & np.uint64(31))).astype(np.uint32))
+        d_words = torch.from_numpy(words.view(np.int32)).to(dev)
+        vmask = torch.empty(B3, dtype=torch.uint8, device=dev)
+        vis_ms = timed_calls(torch, lambda: pool3.visible(ids3, d_words, n_lab, out=vmask), 20, 3)
+        assert pool3.last_error()[0] == 0
+        visibility = {"bricks": B3, "us_per_call": round(vis_ms * 1e3, 2),
+                      "bricks_per_s": round(B3 / (vis_ms * 1e-3), 1),
+                      "visible_frac": round(float(vmask.float().mean().item()), 4),
+                      "transfer_function": "a seeded 1 in 200 of the 20,000 labels visible"}
 
-    encoder = None
-    if args.encoder == "full":
-        log("GPU compressor leg")
-        encoder = encoder_leg(csv, torch, vol, blob, host_s, host_threads)
+        # ---- the 512^3 cells volume (full LOD, 4096 bricks) ----
+        log("generating the 512^3 cells volume")
+        vol2 = synth.cells(n=512, grid=37, p_noise=0.5, seed=2)
+        t0 = time.perf_counter()
+        blob2 = csv.encode_volume(vol2, threads=host_threads)
+        enc2_s = time.perf_counter() - t0
+        pool2 = csv.Pool(0)
+        pool2.add_volume(blob2)
+        B2 = 4096
+        ids2_np = np.arange(B2, dtype=np.uint32)
+        ids2 = torch.from_numpy(ids2_np.view(np.int32)).to(dev)
+        out2 = out3[:B2 * 32 ** 3]
+        sh2, _ = pick_shape(pool2, ids2, out2, lod=0)
+        ms2 = timed_calls(torch, lambda: pool2.decode(ids2, out2, lod=0, shape=sh2), args.steps, args.warmup)
+        assert pool2.last_error()[0] == 0
+        in2 = record_bytes(blob2, ids2_np)
+        ob2 = B2 * 32 ** 3 * 4
+        extra["cells512_full_lod"] = {
+            "bricks": B2, "lod": 0, "ms_per_call": round(ms2, 4), "gbs": round(ob2 / (ms2 * 1e-3) / 1e9, 2),
+            "voxels_per_s": round(B2 * 32 ** 3 / (ms2 * 1e-3), 1), "read_bytes": in2, "write_bytes": ob2,
+            "frac": round((in2 + ob2) / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "shape": list(sh2),
+            "compressed_bytes": len(blob2), "compression_ratio_pct": round(100.0 * len(blob2) / vol2.nbytes, 4)}
+        log("cells %s" % extra["cells512_full_lod"])
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        oracle._load()
-        log("CPU oracle baseline (~%.0fs)" % args.cpu_seconds)
-        reps, t0 = 0, time.perf_counter()
-        lods = np.zeros(B, np.uint8)
-        while True:
-            oracle.decode_bricks(blob, ids_np, lods)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds or reps >= 200:
-                break
-        cpu = {"value": round(reps * out_bytes / el / 1e9, 4), "unit": "GB/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": "%d full passes over the same 4096 bricks at full LOD (%.1f s)" % (reps, el)}
+        # ---- 16,384 uneven mixed-LOD requests over three volumes, one persistent launch ----
+        log("mixed requests over three volumes")
+        vol1 = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+        volb = synth.blobs(n=512, sites=50, amp=24.0, seed=4)
+        blobs4 = [csv.encode_volume(vol1), blob2, csv.encode_volume(volb, threads=host_threads)]
+        del volb
+        pool4 = csv.Pool(0)
+        first = [pool4.add_volume(b) for b in blobs4]
+        counts = [len(record_sizes(b)) for b in blobs4]
+        rng, src = config4_requests()
+        n4 = len(src)
+        local = np.array([rng.integers(0, counts[k]) for k in src], dtype=np.uint32)
+        ids4_np = (np.array(first, dtype=np.uint32)[src] + local).astype(np.uint32)
+        lods4 = rng.integers(0, 3, n4).astype(np.uint8)
+        off4, tot4 = csv.output_offsets(lods4)
+        d_ids4 = torch.from_numpy(ids4_np.view(np.int32)).to(dev)
+        d_lods4 = torch.from_numpy(lods4.copy()).to(dev)
+        d_off4 = torch.from_numpy(off4.view(np.int64)).to(dev)
+        out4 = out3[:tot4]
+        sh4, tune4 = pick_shape(pool4, d_ids4, out4, lods=d_lods4, out_offsets=d_off4)
+        ms4 = timed_calls(torch, lambda: pool4.decode(d_ids4, out4, lods=d_lods4, out_offsets=d_off4, shape=sh4),
+                          args.steps, args.warmup)
+        assert pool4.last_error()[0] == 0
+        # reads: whole records at full LOD, the level-1 prefix at LODs 1 and 2 (an upper bound at LOD 2)
+        full_rec = np.concatenate([record_sizes(b) for b in blobs4])
+        pre_rec = []
+        for b in blobs4:
+            sizes, dev_bytes = prefix_record_bytes(csv, b)
+            pre_rec.append(sizes * (dev_bytes / max(int(sizes.sum()), 1)))
+        pre_rec = np.concatenate(pre_rec)
+        in4 = int(np.where(lods4 == 0, full_rec[ids4_np], pre_rec[ids4_np]).sum())
+        ob4 = tot4 * 4
+        sizes4 = full_rec[ids4_np]
+        extra["mixed_16384"] = {
+            "requests": n4, "lod_counts": [int((lods4 == t).sum()) for t in range(3)],
+            "record_bytes_min_max": [int(sizes4.min()), int(sizes4.max())], "ms_per_call": round(ms4, 4),
+            "gbs": round(ob4 / (ms4 * 1e-3) / 1e9, 2), "voxels_per_s": round(tot4 / (ms4 * 1e-3), 1),
+            "read_bytes": in4, "write_bytes": ob4,
+            "frac": round((in4 + ob4) / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "shape": list(sh4),
+            "autotune_ms": tune4}
+        log("mixed %s" % extra["mixed_16384"])
+        del pool4
 
-    serving = None
-    if args.serving == "full":
-        serving = serving_leg(csv, synth, args.serve_seconds)
+        if args.detail == "full":
+            log("detail separation leg")
+            detail = detail_leg(csv, torch, blob2, ids2_np, ids2, out2, sh2, pool2)
+        if args.encoder == "full":
+            log("GPU compressor leg")
+            encoder = encoder_leg(csv, torch, vol2, blob2, enc2_s, host_threads)
+        del vol2
+
+        if not args.no_cpu:
+            import oracle
+            oracle._load()
+            runs = []
+            n_all = oracle.num_threads()
+            # the same workload's first 2048 bricks, whole passes until the time is up
+            sample = ids3_np[:2048]
+            lods0 = np.zeros(len(sample), np.uint8)
+            for threads, secs in ((n_all, args.cpu_seconds), (1, args.cpu_seconds / 2)):
+                oracle.set_threads(threads)
+                log("CPU oracle on %d threads (~%.0fs)" % (threads, secs))
+                reps, t0 = 0, time.perf_counter()
+                while True:
+                    oracle.decode_bricks(blob3, sample[:len(sample) if threads > 1 else 256],
+                                         lods0[:len(sample) if threads > 1 else 256])
+                    reps += 1
+                    el = time.perf_counter() - t0
+                    if el >= secs or reps >= 500:
+                        break
+                nbk = len(sample) if threads > 1 else 256
+                runs.append({"threads": threads, "gbs": round(reps * nbk * 32768 * 4 / el / 1e9, 4),
+                             "sample": "%d passes over bricks 0..%d of the 1024^3 volume at full LOD (%.1f s)" %
+                                       (reps, nbk - 1, el)})
+            oracle.set_threads(n_all)
+            cpu = {"value": runs[0]["gbs"], "unit": "GB/s", "cores": runs[0]["threads"], "kind": "oracle",
+                   "sample": runs[0]["sample"], "single_thread": runs[1], "host_cpu": cpu_model(),
+                   "host_logical_cpus": os.cpu_count()}
+
+        if args.serving == "full":
+            serving = serving_leg(csv, synth, args.serve_seconds)
 
     res = {
         "metric": "decoded GB/s (uint32 labels) + % HBM roofline; p50/p99 brick latency",
@@ -458,19 +596,22 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "512^3 uint32 cells volume (50,653 labels, jittered-grid Voronoi with 1-voxel "
-                               "boundary noise), 4096 bricks of 32^3 decoded at full LOD in one launch",
-                   "bricks": B, "lod": lod, "compressed_bytes": len(blob),
-                   "compression_ratio_pct": round(100.0 * len(blob) / vol.nbytes, 4)},
-        "voxels_per_s": round(elems / (ms * 1e-3), 1),
+        "config": {"workload": "1024^3 uint32 neurite-like volume (20,000 labels, random-walk branching tubes of "
+                               "radius 2-8, Zipf sizes, ~45% background), 32,768 bricks of 32^3 decoded at full "
+                               "LOD in one decode call",
+                   "bricks": B3, "lod": 0, "compressed_bytes": len(blob3),
+                   "compression_ratio_pct": round(100.0 * len(blob3) / (elems3 * 4), 4)},
+        "voxels_per_s": round(elems3 / (ms * 1e-3), 1),
         "wall_s": round(t_wall, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "traffic_shape": list(TRAFFIC["shape"]) if traffic is not None else None,
-                     "traffic_unit": "bytes per decode call", "algorithmic_bytes_per_launch": in_bytes + out_bytes,
-                     "kernel": "csv_decode_bricks = front_kernel + leaf_kernel", "shape": list(shape),
+                     "traffic_unit": "bytes per decode call", "algorithmic_bytes_per_launch": in3_bytes + out3_bytes,
+                     "kernel": "csv_decode_bricks = front_kernel + leaf_kernel", "shape": list(shape3),
                      "decoder_sha256_16": src_hash},
-        "plain_per_brick_launch": {"value": round(plain_gbs, 3), "unit": "GB/s", "bricks": nb},
+        "paper_context": {"gbs": PAPER_GBS, "hardware": "NVIDIA RTX 3070 Ti (Table 3; decoded bytes)"},
+        "extra_workloads": extra,
+        "plain_per_brick_launch": plain,
         "visibility_test": visibility,
         "detail_separation": detail,
         "encoder": encoder,

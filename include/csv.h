@@ -56,7 +56,7 @@ const char *csv_strerror(int code);
 /* ------------------------------------------------------------------ */
 typedef struct {
     uint32_t brick_log2;    /* log2 of the brick edge; 5 (32^3) is what the GPU decodes; 1..6 */
-    uint32_t scale_bits;    /* rANS table precision: frequencies sum to 2^scale_bits; 8..11 */
+    uint32_t scale_bits;    /* rANS table precision: frequencies sum to 2^scale_bits; 8..12 */
     uint32_t lane_k;        /* interleaving rule: W = largest power of two <= min(lane_max, n_symbols / lane_k) */
     uint32_t lane_max;      /* at most this many interleaved rANS states per brick (power of two <= 64) */
     uint32_t sample_stride; /* frequency-table prepass samples every sample_stride-th brick; 0 = 512,
@@ -91,7 +91,7 @@ void csv_free(void *p);
  * runs on `stream` (NULL: the null stream) and the call returns when the
  * blob is in host memory (*blob, release with csv_free).  Only 32^3 bricks
  * (opts->brick_log2 5); opts->threads is ignored.  The call keeps its device
- * buffers (about 430 KiB per workgroup, 4 workgroups per CU, plus the
+ * buffers (about 430 KiB per workgroup, 5 workgroups per CU, plus the
  * records and the container) and a pinned host buffer of the container's
  * size for later calls on the same device, until csv_encode_gpu_release;
  * calls on one device run one at a time.  Errors: CSV_EINVAL (null
@@ -114,16 +114,35 @@ typedef struct {
 /* Parse and validate a container header (host memory). */
 int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info);
 
+/*
+ * Validate the header and every record of a container (host memory, no
+ * device needed): record offsets 4-byte aligned and increasing, each record
+ * holding its header; per record P >= 1 (P = 1 exactly when the brick has no
+ * symbols), W a power of two <= 64 and zero exactly when there are no
+ * symbols, cumulative symbol counts non-increasing from the finest child
+ * level and at most two per node, and header + palette + states + words
+ * within the record (sums in 64 bits).  csv_pool_add_volume runs it before
+ * anything reaches the device.  Errors: as csv_blob_info, CSV_ECORRUPT
+ * with *first_bad (may be NULL) set to the first bad brick.
+ */
+int csv_blob_check(const uint8_t *blob, size_t blob_bytes, uint32_t *first_bad);
+
 /* ------------------------------------------------------------------ */
 /* Device pool: compressed volumes resident in HBM (Sec. 4)            */
 /* ------------------------------------------------------------------ */
 typedef struct csv_pool csv_pool;
 
 /* Create an empty pool on HIP device `device`.  Decodes only read the pool,
- * so csv_decode_* may run concurrently on several streams (each launch takes
- * one of 256 device work counters in turn, so at most 256 launches may be in
- * flight on one pool); csv_pool_add_volume must not overlap them. */
+ * so csv_decode_* may run concurrently on several streams: each stream gets
+ * its own set of launch buffers (work counters, hand-off slots, lists and,
+ * for pools that need them, global replay arenas), up to 16 sets per pool; a
+ * 17th stream takes over the least recently used set after waiting for the
+ * whole device.  csv_pool_add_volume must not overlap decodes. */
 int csv_pool_create(csv_pool **pool, int device);
+/* csv_pool_create with a limit on the HBM the pool holds (records, tables,
+ * launch buffers, staging; csv_pool_info's device_bytes): adding a volume or
+ * growing launch buffers past it fails with CSV_ENOMEM.  0: no limit. */
+int csv_pool_create_budget(csv_pool **pool, int device, uint64_t hbm_budget_bytes);
 void csv_pool_destroy(csv_pool *pool);
 
 /*
@@ -131,8 +150,12 @@ void csv_pool_destroy(csv_pool *pool);
  * its own copy, so the blob may be freed afterwards.  Its bricks get the
  * global ids first_brick_id .. first_brick_id + n_bricks - 1 (volumes are
  * numbered in the order they are added; each keeps its own table pair).
- * Only 32^3 bricks (brick_log2 5) and scale_bits <= 11 are accepted.
- * Synchronous.  Errors: CSV_EINVAL, CSV_ECORRUPT, CSV_ENOMEM, CSV_EHIP.
+ * Only 32^3 bricks (brick_log2 5) are accepted; every record is checked
+ * first (csv_blob_check).  Synchronous, with no stream argument: the pool's
+ * per-brick arrays and decode tables are re-uploaded, so the call waits for
+ * every decode on the device that may read the old ones.  Errors:
+ * CSV_EINVAL, CSV_ECORRUPT, CSV_ENOMEM (also past the pool's HBM budget),
+ * CSV_EHIP.
  */
 int csv_pool_add_volume(csv_pool *pool, const uint8_t *blob, size_t blob_bytes, uint32_t *first_brick_id);
 
@@ -191,6 +214,8 @@ int csv_pool_info_get(const csv_pool *pool, csv_pool_info *info);
  * *total the number of uint32 elements of that packing.
  */
 int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total);
+/* The same packing in bytes (offsets[i] and *total are 4x the element figures). */
+int csv_output_bytes(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total);
 
 /*
  * THE HOT PATH: decode n bricks on the GPU, asynchronously on `stream`.
@@ -222,6 +247,16 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
  */
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                       const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream);
+
+/* csv_decode_bricks that also reports errors per request: status is
+ * device-accessible int32[n] (device memory, or mapped pinned host memory)
+ * that the caller fills with 0 beforehand; a request that fails gets its
+ * CSV_E* code in status[i] (CSV_EDETAIL for a level-1 fallback), the
+ * others are left untouched.  The pool's error word is set as well.
+ * Errors as csv_decode_bricks. */
+int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
+                             uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
+                             void *stream, int32_t *status);
 
 /* Baseline: the same kernels launched once per brick (a grid of one
  * wavefront, then a grid of one workgroup: 2n launches on `stream`, 3n for
@@ -357,6 +392,8 @@ typedef struct {
     uint64_t stall_staging;    /* admission rounds stopped by a full detail staging buffer */
     uint64_t detail_staged_bytes; /* level-0 detail promised to full-LOD misses (staging granules) */
     uint64_t detail_releases;  /* times the staged detail was dropped */
+    uint64_t failed;           /* decodes that failed on the device (their requests completed with the
+                                  kernel's error code, nothing cached); `error` holds the last code */
 } csv_stats;
 
 /* Clock of arrival and completion times (steady, nanoseconds). */
@@ -382,6 +419,9 @@ int csv_server_stats(csv_server *server, csv_stats *stats);
 /* Copy a completion's brick to host memory (elems uint32); valid until the
  * next csv_server_poll, like the completion itself. */
 int csv_server_read(csv_server *server, const csv_completion *completion, uint32_t *host_dst);
+/* Device address of the server's decoded-brick cache (a completion's data
+ * lies at a byte offset below opts.cache_bytes from it); NULL for NULL. */
+const uint32_t *csv_server_cache_data(const csv_server *server);
 int csv_server_reset_stats(csv_server *server);
 /* Empty-space skipping in serving (Sec. 4): with a visibility table set, a
  * request for a brick whose byte is 0 completes at once without a decode

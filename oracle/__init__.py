@@ -67,6 +67,7 @@ def _load():
         L.orc_rans_decode.argtypes = [vp, u32, vp, u32, u32, vp, u32, u32, vp, vp]
         L.orc_free.argtypes = [vp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -90,6 +91,11 @@ def _chk(rc):
 def num_threads() -> int:
     """Host threads the oracle's parallel loops (over bricks) use."""
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Host threads for the oracle's later parallel loops."""
+    _load().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- volume --

@@ -503,6 +503,15 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* set the number of host threads of later parallel loops (n >= 1) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 uint32_t orc_abi_version(void) { return 1; }
 
 /*

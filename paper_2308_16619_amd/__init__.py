@@ -73,7 +73,7 @@ class Stats(ctypes.Structure):
         ("error", ctypes.c_int32), ("pad", ctypes.c_int32), ("worker_busy_ns", ctypes.c_uint64),
         ("worker_launch_ns", ctypes.c_uint64), ("stall_batch", ctypes.c_uint64), ("stall_inflight", ctypes.c_uint64),
         ("stall_slot", ctypes.c_uint64), ("skipped", ctypes.c_uint64), ("stall_staging", ctypes.c_uint64),
-        ("detail_staged_bytes", ctypes.c_uint64), ("detail_releases", ctypes.c_uint64)]
+        ("detail_staged_bytes", ctypes.c_uint64), ("detail_releases", ctypes.c_uint64), ("failed", ctypes.c_uint64)]
 
 
 class PoolInfo(ctypes.Structure):
@@ -101,7 +101,9 @@ def lib():
         L.csv_encode_gpu_release.argtypes = [i32]
         L.csv_free.argtypes = [vp]
         L.csv_blob_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(VolumeInfo)]
+        L.csv_blob_check.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(u32)]
         L.csv_pool_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.csv_pool_create_budget.argtypes = [ctypes.POINTER(vp), i32, u64]
         L.csv_pool_destroy.argtypes = [vp]
         L.csv_pool_add_volume.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(u32)]
         L.csv_pool_add_volume_ex.argtypes = [vp, vp, ctypes.c_size_t, u32, ctypes.POINTER(u32)]
@@ -110,6 +112,8 @@ def lib():
         L.csv_pool_set_detail_staging.argtypes = [vp, u64]
         L.csv_pool_info_get.argtypes = [vp, ctypes.POINTER(PoolInfo)]
         L.csv_output_elems.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
+        L.csv_output_bytes.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
+        L.csv_decode_bricks_status.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, vp]
         for f in ("csv_decode_bricks", "csv_decode_bricks_plain"):
             getattr(L, f).argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
         L.csv_decode_bricks_shaped.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(Shape)]
@@ -130,6 +134,8 @@ def lib():
         L.csv_server_set_visible.argtypes = [vp, vp, u32]
         L.csv_server_reset_stats.argtypes = [vp]
         L.csv_server_read.argtypes = [vp, vp, vp]
+        L.csv_server_cache_data.restype = vp
+        L.csv_server_cache_data.argtypes = [vp]
         L.csv_server_run_trace.argtypes = [vp, vp, u32, vp, u64, ctypes.POINTER(u32)]
         L.csv_server_destroy.argtypes = [vp]
         L.csv_frame_cache_create.argtypes = [vp, u64, u32, ctypes.POINTER(vp)]
@@ -208,6 +214,14 @@ def blob_info(blob: bytes) -> dict:
     return d
 
 
+def blob_check(blob: bytes) -> tuple:
+    """Validate every record of a container on the host: (CSV_OK or
+    CSV_ECORRUPT / header error, first bad brick or None)."""
+    bad = ctypes.c_uint32(0xFFFFFFFF)
+    rc = lib().csv_blob_check(blob, len(blob), ctypes.byref(bad))
+    return rc, (bad.value if rc == CSV_ECORRUPT and bad.value != 0xFFFFFFFF else None)
+
+
 def output_offsets(lods) -> tuple:
     """Element offsets of requests packed back to back, and the total."""
     lods = np.ascontiguousarray(lods, dtype=np.uint8)
@@ -227,9 +241,9 @@ def _stream_handle(stream):
 class Pool:
     """Compressed volumes resident in HBM (one GPU)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
         self._p = ctypes.c_void_p()
-        _chk(lib().csv_pool_create(ctypes.byref(self._p), device), "csv_pool_create")
+        _chk(lib().csv_pool_create_budget(ctypes.byref(self._p), device, int(hbm_budget)), "csv_pool_create_budget")
         self.device = device
 
     def close(self):
@@ -278,15 +292,20 @@ class Pool:
                 lod, ctypes.c_void_p(out_offsets.data_ptr() if out_offsets is not None else 0), int(ids.numel()),
                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)]
 
-    def decode(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None, plain: bool = False, shape=None):
+    def decode(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None, plain: bool = False, shape=None,
+               status=None):
         """Decode bricks `ids` (int32 cuda tensor) into `out` (int32 cuda
         tensor viewed as uint32).  `lods`: uint8 cuda tensor or None (all at
         `lod`); `out_offsets`: int64 cuda tensor of element offsets (needed
         with `lods`) or None (request i at i * (32 >> lod)^3).  `plain`: one
         launch per brick.  `shape`: (waves_per_group, groups_per_cu,
-        use_queue[, lpt_order]) launch shape; default: the pool's shape."""
+        use_queue[, lpt_order]) launch shape; default: the pool's shape.
+        `status`: int32 cuda tensor of ids.numel() zeros; failed requests
+        get their error code (csv_decode_bricks_status)."""
         args = self._args(ids, out, lods, lod, out_offsets, stream)
-        if shape is not None:
+        if status is not None:
+            _chk(lib().csv_decode_bricks_status(*args, ctypes.c_void_p(status.data_ptr())), "csv_decode_bricks_status")
+        elif shape is not None:
             sh = Shape(int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3]) if len(shape) > 3 else 0, 0.0)
             _chk(lib().csv_decode_bricks_shaped(*args, ctypes.byref(sh)), "csv_decode_bricks_shaped")
         elif plain:
@@ -399,6 +418,10 @@ class Server:
         out = np.zeros(int(c["elems"][0]), dtype=np.uint32)
         _chk(lib().csv_server_read(self._s, _np_ptr(c), _np_ptr(out)), "csv_server_read")
         return out
+
+    def cache_ptr(self) -> int:
+        """Device address of the decoded-brick cache (completions point into it)."""
+        return int(lib().csv_server_cache_data(self._s) or 0)
 
     def run_trace(self, reqs: np.ndarray, collect: bool = False, timeout_s: float = 10.0):
         reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)

@@ -47,10 +47,10 @@
 namespace {
 
 constexpr int kLog2 = 5;                 // 32^3 bricks
-constexpr int kLutMaxBits = 11;          // largest supported table precision
+constexpr int kLutMaxBits = 12;          // largest supported table precision
 constexpr uint32_t kMaxSym = 2 * 37448;  // every node an operation plus a delta nibble
 constexpr uint32_t kLdsBytes = 160 * 1024;
-constexpr uint32_t kLutLdsCap = 24 * 1024;  // decode tables kept in LDS when they fit
+constexpr uint32_t kLutLdsCap = 32 * 1024;  // decode tables kept in LDS when they fit (two 2^12 tables)
 constexpr uint32_t kPalFast = 252;       // u8 indices 0..251; 252 marks an invalid reference, 253..255 open ones
 constexpr uint32_t kRingWords = 1024;    // word ring of the entropy decoder
 constexpr int kWavesLeaf = 8;            // waves of a leaf workgroup (LDS arena)
@@ -97,6 +97,9 @@ struct DecodeArgs {
     // device address of the staged remaining dwords (0: not staged)
     const uint32_t *pfx_dw;
     const uint64_t *sfx;
+    // per-request status (else nullptr): a failed request rq gets its error
+    // code in req_err[rq]; successful requests leave their entry untouched
+    int *req_err;
 };
 
 struct LaunchA {
@@ -170,6 +173,11 @@ __device__ __forceinline__ void wsync() {
 
 __device__ __forceinline__ void report(int *err, int code, uint32_t who) {
     if (atomicCAS(err, 0, code) == 0) atomicExch(err + 1, (int)who);
+}
+// request rq failed: the launch's error word (first error wins) and the request's status
+__device__ __forceinline__ void fail(const DecodeArgs &a, uint32_t rq, int code, uint32_t who) {
+    report(a.err, code, who);
+    if (a.req_err) a.req_err[rq] = code;
 }
 
 // Per-brick phase clocks, only in builds with CSV_PHASE_TIMING: entry i of
@@ -321,7 +329,7 @@ __device__ __forceinline__ ReqKind load_request(const DecodeArgs &a, uint32_t rq
     const uint32_t hdr = csv::record_header_words(kLog2);
     // the record holds its words up to pdw dwords (the rest is staged)
     bool ok = h.P >= 1 && h.W <= 64 && (h.W & (h.W - 1)) == 0 && ((h.c0 > 0) == (h.W > 0)) && h.c0 <= kMaxSym &&
-              (uint64_t)4 * (hdr + h.P + h.W) + std::min<uint64_t>(2ull * h.nw, 4ull * h.pdw) <= size;
+              4ull * ((uint64_t)hdr + h.P + h.W) + std::min<uint64_t>(2ull * h.nw, 4ull * h.pdw) <= size;
     ok = ok && h.c0 >= h.c1 && h.c1 >= h.c2 && h.c2 >= h.c3 && h.c3 >= h.c4;
     if (ok) ok = (h.c0 == 0) ? (h.P == 1) : (h.P >= 2);
     if (!ok) return kReqCorrupt;
@@ -1053,21 +1061,21 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             continue;
         }
         if (kind == kReqBadLod) {
-            if (L == 0) report(a.err, CSV_ERANGE, rq);
+            if (L == 0) fail(a, rq, CSV_ERANGE, rq);
             continue;
         }
         if (kind != kReqDecode) {
-            if (kind != kReqFill && L == 0) report(a.err, kind == kReqBadId ? CSV_ERANGE : CSV_ECORRUPT,
-                                                   kind == kReqBadId ? rq : h.id);
+            if (kind != kReqFill && L == 0) fail(a, rq, kind == kReqBadId ? CSV_ERANGE : CSV_ECORRUPT,
+                                                 kind == kReqBadId ? rq : h.id);
             fill_labels<64>(dst, count, kind == kReqFill ? fill : 0u, L);
             continue;
         }
-        if (h.up && L == 0) report(a.err, CSV_EDETAIL, h.id);
+        if (h.up && L == 0) fail(a, rq, CSV_EDETAIL, h.id);
         const uint32_t n = h.c(h.t);
         uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
         uint32_t *nib = reinterpret_cast<uint32_t *>(slot);
         if (n + 16 > 8 * l.slot_dw) {  // the slots are sized for the pool's largest brick
-            if (L == 0) report(a.err, CSV_EINVAL, h.id);
+            if (L == 0) fail(a, rq, CSV_EINVAL, h.id);
             if (l.words_out) {
                 if (L == 0) l.words_out[rq] = 0xFFFFFFFFu;
             } else {
@@ -1093,7 +1101,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
         if (ok) ok = h.P <= kPalFast ? front_replay<uint8_t, false>(h, l, nib, slot, wl, dst)
                                      : front_replay<uint16_t, true>(h, l, nib, slot, wl, dst);
         if (!ok) {
-            if (L == 0) report(a.err, CSV_ECORRUPT, h.id);
+            if (L == 0) fail(a, rq, CSV_ECORRUPT, h.id);
             fill_labels<64>(dst, count, 0u, L);
         }
         phase_mark(rq, 2);
@@ -1517,7 +1525,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
         }
         __syncthreads();
         if (done && !ok) {
-            if (tid == 0) report(a.err, !kSlow || gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
+            if (tid == 0) fail(a, rq, !kSlow || gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
             fill_labels<NT>(dst, count, 0u, tid);
         }
         __syncthreads();
@@ -1605,7 +1613,7 @@ __global__ __launch_bounds__(256) void visible_kernel(const uint64_t *rec_ptr, c
         }
         const uint32_t *rec = rec_at(ld_s(rec_ptr + id));
         const uint32_t P = ld_s(rec);
-        if (P == 0 || (uint64_t)4 * (hdr + P) > ld_s(rec_size + id)) {
+        if (P == 0 || 4ull * ((uint64_t)hdr + P) > ld_s(rec_size + id)) {
             if (L == 0) {
                 out[r] = 0;
                 report(err, CSV_ECORRUPT, id);
@@ -1638,22 +1646,41 @@ struct LaunchBufs {
     uint32_t *leaf_list = nullptr; // requests for the leaf kernel
     uint32_t *slow_list = nullptr; // ... of them for its global-arena variant
     uint32_t *small = nullptr;     // [0, 64): order bins; [64, 72): the launch counters
+    uint8_t *arenas = nullptr;     // global arenas of the global-arena leaf kernel, one per workgroup
+    uint32_t arena_groups = 0;     // workgroups they serve
+    bool owned = true;             // false: a view of memory the library does not allocate
     bool dirty = false;            // counters left non-zero by a failed launch
     uint32_t slot_dw = 0;
     uint32_t cap_n = 0;
     uint32_t slot_bytes() const { return 4 * slot_dw + kSlotExtra; }
     void release() {
-        (void)hipFree(slots);
-        (void)hipFree(order);
-        (void)hipFree(leaf_list);
-        (void)hipFree(slow_list);
-        (void)hipFree(small);
+        if (owned) {
+            (void)hipFree(slots);
+            (void)hipFree(order);
+            (void)hipFree(leaf_list);
+            (void)hipFree(slow_list);
+            (void)hipFree(small);
+            (void)hipFree(arenas);
+        }
         slots = nullptr;
         order = nullptr;
         leaf_list = nullptr;
         slow_list = nullptr;
         small = nullptr;
+        arenas = nullptr;
+        arena_groups = 0;
         cap_n = 0;
+    }
+    // global arenas for `groups` workgroups (kept once allocated)
+    int reserve_arenas(uint32_t groups) {
+        if (arenas && arena_groups >= groups) return CSV_OK;
+        if (!owned) return CSV_EINVAL;
+        (void)hipFree(arenas);
+        arenas = nullptr;
+        arena_groups = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&arenas), (size_t)groups * kArenaBytes) != hipSuccess) return CSV_ENOMEM;
+        arena_groups = groups;
+        return CSV_OK;
     }
     // room for n requests with slot_dw nibble dwords each
     int reserve(uint32_t n, uint32_t dw) {
@@ -1673,7 +1700,9 @@ struct LaunchBufs {
         cap_n = cap;
         return CSV_OK;
     }
-    uint64_t bytes() const { return slots ? ((uint64_t)cap_n * (slot_bytes() + 12) + 4 * 72) : 0; }
+    // HBM of the slots, lists and counters for cap requests of dw nibble dwords
+    static uint64_t sized(uint32_t cap, uint32_t dw) { return (uint64_t)cap * (4ull * dw + kSlotExtra + 12) + 4 * 72; }
+    uint64_t bytes() const { return (slots ? sized(cap_n, slot_dw) : 0) + (uint64_t)arena_groups * kArenaBytes; }
 };
 constexpr size_t kMaxStreamBufs = 16;
 
@@ -1698,12 +1727,10 @@ struct csv_pool {
     int *d_err = nullptr;
     std::vector<LaunchBufs> bufs;             // per stream, at most kMaxStreamBufs
     uint64_t use_clock = 0;
-    uint8_t *d_scratch = nullptr;             // global replay arenas
-    uint32_t slot_bytes = 0;
-    uint32_t n_slots = 0;
     uint32_t max_c0 = 0;                      // most symbols of any brick in the pool
     uint32_t max_fast_bytes = 0;              // largest LDS arena a brick of the pool needs
     bool any_big_palette = false;
+    uint64_t hbm_budget = 0;                  // HBM the pool may hold (0: no limit)
     uint32_t generation = 0;                  // bumped when device tables move
     csv_shape shape{16, 3, 1, 0, 0.f};        // launch shape of csv_decode_bricks
     uint64_t record_bytes = 0;
@@ -1797,9 +1824,22 @@ constexpr uint32_t kMaxGroupsB = 8;
 // per workgroup: LDS is allocated in granules, and a workgroup that rounds
 // up past its share would leave room for one fewer)
 uint32_t arena_b(uint32_t groups) { return ((kLdsBytes / groups) & ~4095u) - kSmallB; }
-uint32_t min_arena_b() { return arena_b(kMaxGroupsB); }
+// workgroups of the global-arena leaf kernel (4 per CU), each with its own arena
+uint32_t slow_groups(uint32_t cu) { return 4 * cu; }
 
 // the buffers of stream s, sized for n requests (pool->mu held)
+// HBM held by the pool: records, per-brick arrays, tables, launch buffers, staging
+uint64_t pool_device_bytes(const csv_pool *p) {
+    uint64_t lb = 0;
+    for (const auto &b : p->bufs) lb += b.bytes();
+    return p->record_bytes + p->rec_ptr.size() * (8 + 4 + 2) + p->luts.size() * 4 + lb +
+           (p->any_split ? p->rec_ptr.size() * (4 + 8) + p->stage_alloc : 0);
+}
+// would `more` bytes of HBM exceed the pool's budget?
+bool over_budget(const csv_pool *p, uint64_t more) {
+    return p->hbm_budget && pool_device_bytes(p) + more > p->hbm_budget;
+}
+
 int stream_bufs(csv_pool *pool, hipStream_t s, uint32_t n, LaunchBufs **out) {
     LaunchBufs *b = nullptr;
     for (auto &e : pool->bufs)
@@ -1823,6 +1863,9 @@ int stream_bufs(csv_pool *pool, hipStream_t s, uint32_t n, LaunchBufs **out) {
     if (!b->slots || n > b->cap_n || dw != b->slot_dw) {
         if (cap) return CSV_EBUSY;  // buffers cannot be re-sized inside a capture
         if (b->slots && hipStreamSynchronize(s) != hipSuccess) return CSV_EHIP;
+        const uint64_t now = b->slots ? LaunchBufs::sized(b->cap_n, b->slot_dw) : 0;
+        const uint64_t want = LaunchBufs::sized(std::max(n, 1024u), dw);
+        if (want > now && over_budget(pool, want - now)) return CSV_ENOMEM;
         const int rc = b->reserve(n, dw);
         if (rc) return rc;
     }
@@ -1866,7 +1909,7 @@ uint32_t ref_list_cap() {
 
 int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
            uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
-           bool lpt, LaunchBufs *fixed = nullptr, uint32_t *words_out = nullptr) {
+           bool lpt, LaunchBufs *fixed = nullptr, uint32_t *words_out = nullptr, int *req_err = nullptr) {
     if (!pool || (n && (!ids || !out))) return CSV_EINVAL;
     if (!lods && lod_scalar > (uint32_t)kLog2) return CSV_ERANGE;
     if (lods && !out_off) return CSV_EINVAL;
@@ -1905,6 +1948,20 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     a.err = pool->d_err;
     a.pfx_dw = pool->any_split ? pool->d_pfx_dw : nullptr;
     a.sfx = pool->any_split ? pool->d_sfx : nullptr;
+    a.req_err = req_err;
+    const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
+    // the global-arena variant runs only for pools with bricks that may not fit the LDS arena;
+    // its arenas belong to this buffer set, so launches on other streams never share them
+    const bool slow = pool->any_big_palette || pool->max_fast_bytes > arena_b(groups_b);
+    // buffers the library allocates get one arena per global-arena workgroup; a view of
+    // memory it does not allocate brings its own, fewer ones
+    const uint32_t grid_g = std::min(B->owned ? slow_groups(cu) : B->arena_groups, n);
+    if (slow && (!B->arenas || B->arena_groups < grid_g)) {
+        if (!B->owned || capturing(s)) return CSV_EBUSY;  // fixed buffers cannot grow
+        if (over_budget(pool, (uint64_t)slow_groups(cu) * kArenaBytes)) return CSV_ENOMEM;
+        const int rc = B->reserve_arenas(slow_groups(cu));
+        if (rc) return rc;
+    }
     // counters: 0 front queue, 1 leaf queue, 2 leaf count, 3 slow count,
     // 4 slow queue, 5 and 6 finished leaf / slow workgroups.  They are zero
     // when a launch starts: zeroed at allocation, then by the last
@@ -1936,16 +1993,13 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     lb.slots = B->slots;
     lb.slot_bytes = B->slot_bytes();
     lb.slot_dw = B->slot_dw;
-    lb.scratch = pool->d_scratch;
+    lb.scratch = slow ? B->arenas : nullptr;
     lb.scratch_bytes = kArenaBytes;
     lb.ref_cap = ref_list_cap();
     lb.ctr = ctr;
     const size_t lds_b = kSmallB + (size_t)lb.arena_bytes;
-    // the global-arena variant runs only for pools with bricks that may not fit the LDS arena
-    const bool slow = pool->any_big_palette || pool->max_fast_bytes > lb.arena_bytes;
     const size_t lds_g = kSmallB;
     lb.slow_list = slow ? B->slow_list : nullptr;
-    const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
     // a small batch takes smaller front workgroups, so that its bricks spread over the CUs
     while (waves_a > 4 && (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a < cu) waves_a /= 2;
     // front kernel: as many workgroups as a CU's LDS and 32 wave slots allow
@@ -1978,7 +2032,6 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
         go_a(a, la, grid_a);
         hipLaunchKernelGGL((leaf_kernel<kWavesLeaf, false>), dim3(grid_b), dim3(64 * kWavesLeaf), lds_b, s, a, lb);
         if (slow) {
-            const uint32_t grid_g = std::min(std::min(cu * 4, n), std::max(pool->n_slots, 1u));
             hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(grid_g), dim3(64 * kWavesLeafG), lds_g, s, a, lb);
         }
     }
@@ -1998,7 +2051,9 @@ bool valid_shape(const csv_shape &sh) {
 
 extern "C" {
 
-int csv_pool_create(csv_pool **pool, int device) {
+int csv_pool_create(csv_pool **pool, int device) { return csv_pool_create_budget(pool, device, 0); }
+
+int csv_pool_create_budget(csv_pool **pool, int device, uint64_t hbm_budget_bytes) {
     if (!pool) return CSV_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CSV_EINVAL;
@@ -2012,7 +2067,7 @@ int csv_pool_create(csv_pool **pool, int device) {
         return CSV_EHIP;
     }
     p->n_cu = prop.multiProcessorCount;
-    p->n_slots = (uint32_t)p->n_cu * kMaxGroupsB;  // one global replay arena per replay workgroup
+    p->hbm_budget = hbm_budget_bytes;
     if (hipMalloc(reinterpret_cast<void **>(&p->d_err), 2 * sizeof(int)) != hipSuccess ||
         hipMemset(p->d_err, 0, 2 * sizeof(int)) != hipSuccess) {
         (void)hipFree(p->d_err);
@@ -2035,7 +2090,6 @@ void csv_pool_destroy(csv_pool *p) {
     (void)hipFree(p->d_lut_off);
     (void)hipFree(p->d_bits);
     (void)hipFree(p->d_err);
-    (void)hipFree(p->d_scratch);
     (void)hipFree(p->d_pfx_dw);
     (void)hipFree(p->d_sfx);
     (void)hipFree(p->d_stage);
@@ -2053,21 +2107,19 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     int rc = csv_blob_info(blob, blob_bytes, &info);
     if (rc) return rc;
     if (info.brick_log2 != (uint32_t)kLog2 || info.scale_bits > (uint32_t)kLutMaxBits) return CSV_EINVAL;
+    // every record is checked on the host before anything reaches the device
+    if ((rc = csv_blob_check(blob, blob_bytes, nullptr))) return rc;
     if ((uint64_t)p->rec_ptr.size() + info.n_bricks >= (1ull << 32) || p->bits.size() >= 65535) return CSV_ERANGE;
     std::lock_guard<std::mutex> lk(p->mu);
     DeviceGuard g(p->device);
     const uint64_t rs = csv::record_area_offset(info.n_bricks);
     const uint64_t *index = reinterpret_cast<const uint64_t *>(blob + csv::kHeaderBytes);
-    const uint32_t hdr = csv::record_header_words(kLog2);
-    // every record must hold its header; offsets are 4-byte aligned and increasing
     uint32_t max_fast = p->max_fast_bytes, max_c0 = p->max_c0;
     bool big = p->any_big_palette;
     for (uint32_t i = 0; i < info.n_bricks; i++) {
-        if (index[i + 1] < index[i] + 4 * hdr || (index[i] & 3)) return CSV_ECORRUPT;
         const uint32_t *w = reinterpret_cast<const uint32_t *>(blob + rs + index[i]);
         const uint32_t P = w[0], c0 = w[3], c1 = w[4];
         if (c0 == 0) continue;
-        if (c1 > c0 || c0 > kMaxSym) return CSV_ECORRUPT;
         big |= P > kPalFast;
         max_c0 = std::max(max_c0, c0);
         const uint32_t e1 = std::min((c0 - c1) / 8, 4096u), nb0 = (c1 >> 5) << 2;
@@ -2076,6 +2128,7 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     // the kernels run to the end of a record; 64 bytes of slack cover their last vector loads
     void *buf = nullptr;
     const size_t rb = std::max<uint64_t>(info.record_bytes, 4) + 64;
+    if (over_budget(p, rb + 14ull * info.n_bricks + 4ull * 2 * (1u << info.scale_bits))) return CSV_ENOMEM;
     if (hipMalloc(&buf, rb) != hipSuccess) return CSV_ENOMEM;
     if (hipMemcpy(buf, blob + rs, info.record_bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(buf);
@@ -2083,15 +2136,6 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     }
     // all work that may read the tables about to move must be done
     (void)hipDeviceSynchronize();
-    // a global replay arena per replay workgroup when some brick may not fit an LDS arena
-    if ((big || max_fast > min_arena_b()) && !p->d_scratch) {
-        p->slot_bytes = kArenaBytes;
-        if (hipMalloc(reinterpret_cast<void **>(&p->d_scratch), (size_t)p->slot_bytes * p->n_slots) != hipSuccess) {
-            (void)hipFree(buf);
-            p->slot_bytes = 0;
-            return CSV_ENOMEM;
-        }
-    }
     p->max_c0 = max_c0;
     p->max_fast_bytes = max_fast;
     p->any_big_palette = big;
@@ -2328,11 +2372,7 @@ int csv_pool_info_get(const csv_pool *p, csv_pool_info *info) {
     info->n_bricks = (uint32_t)p->rec_ptr.size();
     info->device = p->device;
     info->pad = 0;
-    uint64_t lb = 0;
-    for (const auto &b : p->bufs) lb += b.bytes();
-    info->device_bytes = p->record_bytes + p->rec_ptr.size() * (8 + 4 + 2) + p->luts.size() * 4 +
-                         (uint64_t)p->slot_bytes * (p->d_scratch ? p->n_slots : 0) + lb +
-                         (p->any_split ? p->rec_ptr.size() * (4 + 8) + p->stage_alloc : 0);
+    info->device_bytes = pool_device_bytes(p);
     info->host_bytes = p->host_bytes;
     return CSV_OK;
 }
@@ -2348,6 +2388,23 @@ int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
     }
     *total = o;
     return CSV_OK;
+}
+
+int csv_output_bytes(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total) {
+    const int rc = csv_output_elems(lods_host, n, offsets, total);
+    if (rc) return rc;
+    for (uint32_t i = 0; offsets && i < n; i++) offsets[i] *= 4;
+    *total *= 4;
+    return CSV_OK;
+}
+
+int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
+                             const uint64_t *out_off, uint32_t n, uint32_t *out, void *stream, int32_t *status) {
+    if (!pool || (n && !status)) return CSV_EINVAL;
+    const csv_shape sh = pool->shape;
+    return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
+                  sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr,
+                  nullptr, status);
 }
 
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
@@ -2486,6 +2543,8 @@ int csv_graph_create(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, u
         std::lock_guard<std::mutex> lk(pool->mu);
         G->generation = pool->generation;
         rc = G->bufs.reserve(n, slot_dw(pool));
+        if (!rc && (pool->any_big_palette || pool->max_fast_bytes > arena_b((uint32_t)sh.groups_per_cu)))
+            rc = G->bufs.reserve_arenas(slow_groups((uint32_t)std::max(1, pool->n_cu)));
     }
     if (!rc && hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = CSV_EHIP;
     if (!rc) {

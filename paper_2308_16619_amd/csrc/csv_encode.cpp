@@ -451,4 +451,36 @@ int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info)
     return CSV_OK;
 }
 
+int csv_blob_check(const uint8_t *blob, size_t blob_bytes, uint32_t *first_bad) {
+    csv_volume_info info;
+    const int rc = csv_blob_info(blob, blob_bytes, &info);
+    if (rc) return rc;
+    const int N = (int)info.brick_log2;
+    const uint64_t hdr = record_header_words(N);
+    // every node below the root carries at most one operation and one delta nibble
+    uint64_t nodes = 0;
+    for (int m = 1; m <= N; m++) nodes += 1ull << (3 * m);
+    const uint64_t max_sym = 2 * nodes;
+    const uint64_t rs = record_area_offset(info.n_bricks);
+    const uint64_t *index = reinterpret_cast<const uint64_t *>(blob + kHeaderBytes);
+    for (uint32_t i = 0; i < info.n_bricks; i++) {
+        const uint64_t a = index[i], e = index[i + 1];
+        bool ok = (a & 3) == 0 && e >= a + 4 * hdr && e <= info.record_bytes && e - a < (1ull << 32);
+        if (ok) {
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(blob + rs + a);
+            const uint64_t P = w[0], W = w[1], nw = w[2];
+            uint32_t c[kMaxLog2 + 1] = {};
+            for (int m = 0; m < N; m++) c[m] = w[3 + m];
+            ok = P >= 1 && W <= 64 && (W & (W - 1)) == 0 && ((c[0] > 0) == (W > 0)) && c[0] <= max_sym &&
+                 (c[0] == 0 ? P == 1 : P >= 2) && 4 * (hdr + P + W) + 2 * nw <= e - a;
+            for (int m = 1; ok && m < N; m++) ok = c[m] <= c[m - 1];
+        }
+        if (!ok) {
+            if (first_bad) *first_bad = i;
+            return CSV_ECORRUPT;
+        }
+    }
+    return CSV_OK;
+}
+
 }  // extern "C"

@@ -69,13 +69,15 @@ struct Pending {
 struct Batch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    // a batch's requests, u64 offsets[n], u32 ids[n], u8 lods[n], in pinned
-    // host memory that the decode kernels read directly (d_buf: its device address)
+    // a batch's requests, u64 offsets[n], u32 ids[n], i32 status[n], u8 lods[n],
+    // in pinned host memory that the decode kernels read (and, for failed
+    // requests, write) directly (d_buf: its device address)
     uint8_t *h_buf = nullptr;
     uint8_t *d_buf = nullptr;
     std::vector<uint32_t> entries;  // entry ids decoded by this batch
     uint64_t bytes = 0;
     bool busy = false;
+    int launch_rc = CSV_OK;         // the launch itself failed: every entry fails with it
     // full-LOD bricks whose level-0 detail is in host memory: staged before the decode
     std::vector<uint32_t> stage_ids;
     bool staged = false;
@@ -125,7 +127,7 @@ struct csv_server {
     std::mutex st_mu;
     std::deque<float> lat_all, lat_miss;  // a deque grows without copying what it holds
     uint64_t n_req = 0, n_hit = 0, n_miss = 0, n_join = 0, n_batches = 0, n_evict = 0, n_rebuild = 0,
-             decoded_bytes = 0, n_launch_err = 0, busy_ns = 0, launch_ns = 0, n_skip = 0;
+             decoded_bytes = 0, n_launch_err = 0, busy_ns = 0, launch_ns = 0, n_skip = 0, n_failed = 0;
     uint64_t stall[4] = {0, 0, 0, 0};  // admission stopped: no free batch, in-flight budget, no slot, staging
     // detail separation (Sec. 4.2): bytes of the staging buffer promised to
     // admitted full-LOD misses since the last release, launched batches that
@@ -316,16 +318,19 @@ void launch_batch(csv_server *s, Batch *b) {
     const uint32_t n = (uint32_t)b->entries.size();
     uint64_t *h_off = reinterpret_cast<uint64_t *>(b->h_buf);
     uint32_t *h_ids = reinterpret_cast<uint32_t *>(h_off + n);
-    uint8_t *h_lods = reinterpret_cast<uint8_t *>(h_ids + n);
+    int32_t *h_status = reinterpret_cast<int32_t *>(h_ids + n);
+    uint8_t *h_lods = reinterpret_cast<uint8_t *>(h_status + n);
     for (uint32_t i = 0; i < n; i++) {
         const Entry &e = s->entries[b->entries[i]];
         h_ids[i] = e.brick;
         h_lods[i] = e.lod;
         h_off[i] = e.slot / 4;
+        h_status[i] = CSV_OK;
     }
     const uint64_t *d_off = reinterpret_cast<const uint64_t *>(b->d_buf);
     const uint32_t *d_ids = reinterpret_cast<const uint32_t *>(d_off + n);
-    const uint8_t *d_lods = reinterpret_cast<const uint8_t *>(d_ids + n);
+    int32_t *d_status = reinterpret_cast<int32_t *>(const_cast<uint32_t *>(d_ids + n));
+    const uint8_t *d_lods = reinterpret_cast<const uint8_t *>(d_status + n);
     int rc = CSV_OK;
     if (!b->stage_ids.empty()) {
         // the level-0 detail of the batch's full-LOD bricks, on the batch's stream
@@ -336,9 +341,10 @@ void launch_batch(csv_server *s, Batch *b) {
         s->staged_inflight++;
     }
     if (!rc)
-        rc = csv_decode_bricks(s->pool, d_ids, d_lods, 0, d_off, n, reinterpret_cast<uint32_t *>(s->d_cache),
-                               b->stream);
-    if (!rc && hipEventRecord(b->done, b->stream) != hipSuccess) rc = CSV_EHIP;
+        rc = csv_decode_bricks_status(s->pool, d_ids, d_lods, 0, d_off, n, reinterpret_cast<uint32_t *>(s->d_cache),
+                                      b->stream, d_status);
+    if (hipEventRecord(b->done, b->stream) != hipSuccess && !rc) rc = CSV_EHIP;
+    b->launch_rc = rc;
     if (rc) {
         s->n_launch_err++;
         s->error = rc;
@@ -349,18 +355,36 @@ void launch_batch(csv_server *s, Batch *b) {
 }
 
 void retire(csv_server *s, Batch &b, uint64_t t) {
-    for (uint32_t id : b.entries) {
+    const uint32_t n = (uint32_t)b.entries.size();
+    const int32_t *h_status = reinterpret_cast<const int32_t *>(b.h_buf + 12ull * n);
+    for (uint32_t i = 0; i < n; i++) {
+        const uint32_t id = b.entries[i];
         Entry &e = s->entries[id];
-        e.state = kValid;
-        lru_touch(s, id);
+        // the kernels wrote the code of each failed request into the batch's status array
+        const int code = b.launch_rc ? b.launch_rc : h_status[i];
         int32_t w = e.waiters;
         e.waiters = -1;
+        if (code != CSV_OK) {  // not cached: the slot goes back to its class, waiters get the code
+            s->free_slots[e.lod].push_back(e.slot);
+            drop_entry(s, id);
+            s->n_failed++;
+            s->error = code;
+            while (w >= 0) {
+                const int32_t nx = s->req_next[(size_t)w];
+                complete(s, (uint32_t)w, nullptr, code, false, t);
+                w = nx;
+            }
+            continue;
+        }
+        e.state = kValid;
+        lru_touch(s, id);
         while (w >= 0) {
             const int32_t nx = s->req_next[(size_t)w];
-            complete(s, (uint32_t)w, &s->entries[id], s->error ? s->error : CSV_OK, false, t);
+            complete(s, (uint32_t)w, &s->entries[id], CSV_OK, false, t);
             w = nx;
         }
     }
+    b.launch_rc = CSV_OK;
     s->decoded_bytes += b.bytes;
     s->inflight -= b.bytes;
     b.entries.clear();
@@ -617,7 +641,7 @@ int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out
         const size_t n = opts.max_batch;
         if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&b.h_buf), 13 * n + 16, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipHostMalloc(reinterpret_cast<void **>(&b.h_buf), 17 * n + 16, hipHostMallocMapped | hipHostMallocCoherent) !=
                 hipSuccess ||
             hipHostGetDevicePointer(reinterpret_cast<void **>(&b.d_buf), b.h_buf, 0) != hipSuccess)
             rc = CSV_ENOMEM;
@@ -696,6 +720,7 @@ int csv_server_stats(csv_server *s, csv_stats *st) {
     st->stall_staging = s->stall[3];
     st->detail_staged_bytes = s->n_staged_bytes;
     st->detail_releases = s->n_releases;
+    st->failed = s->n_failed;
     return CSV_OK;
 }
 
@@ -710,6 +735,7 @@ int csv_server_reset_stats(csv_server *s) {
     s->stall[0] = s->stall[1] = s->stall[2] = s->stall[3] = 0;
     s->n_staged_bytes = s->n_releases = 0;
     s->n_skip = 0;
+    s->n_failed = 0;
     return CSV_OK;
 }
 
@@ -745,6 +771,10 @@ void csv_server_destroy(csv_server *s) {
     (void)hipFree(s->d_cache);
     (void)hipSetDevice(prev);
     delete s;
+}
+
+const uint32_t *csv_server_cache_data(const csv_server *s) {
+    return s ? reinterpret_cast<const uint32_t *>(s->d_cache) : nullptr;
 }
 
 int csv_server_read(csv_server *s, const csv_completion *c, uint32_t *host_dst) {

@@ -136,3 +136,40 @@ def test_output_offsets():
     assert tot == 32768 + 512 + 4096 + 1 + 64
     with pytest.raises(csv.CsvError):
         csv.output_offsets([6])
+
+
+def _corrupt(blob, brick, word, value):
+    """The container with u32 `word` of brick `brick`'s record replaced."""
+    nb = int(np.frombuffer(blob, np.uint32, 1, 36)[0])
+    idx = np.frombuffer(blob, np.uint64, nb + 1, 128)
+    rs = (128 + 8 * (nb + 1) + 15) & ~15
+    b = bytearray(blob)
+    at = rs + int(idx[brick]) + 4 * word
+    b[at:at + 4] = int(value).to_bytes(4, "little")
+    return bytes(b)
+
+
+def test_blob_check_accepts_encoder_output_and_rejects_bad_records():
+    import paper_2308_16619_amd as csv
+    vol = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
+    blob = csv.encode_volume(vol)
+    assert csv.blob_check(blob) == (csv.CSV_OK, None)
+    # a palette size whose 32-bit sum with the header and states would wrap
+    assert csv.blob_check(_corrupt(blob, 3, 0, 0xFFFFFFF8)) == (csv.CSV_ECORRUPT, 3)
+    assert csv.blob_check(_corrupt(blob, 5, 1, 3)) == (csv.CSV_ECORRUPT, 5)            # W not a power of two
+    assert csv.blob_check(_corrupt(blob, 6, 1, 128)) == (csv.CSV_ECORRUPT, 6)          # W above 64
+    assert csv.blob_check(_corrupt(blob, 1, 2, 0x7FFFFFFF)) == (csv.CSV_ECORRUPT, 1)   # words past the record
+    assert csv.blob_check(_corrupt(blob, 2, 4, 0xFFFFFF)) == (csv.CSV_ECORRUPT, 2)     # cum[1] above cum[0]
+    assert csv.blob_check(_corrupt(blob, 7, 3, 80000)) == (csv.CSV_ECORRUPT, 7)        # more symbols than nodes allow
+    assert csv.blob_check(blob[:200])[0] != csv.CSV_OK
+
+
+def test_output_bytes_are_four_times_the_elements():
+    import paper_2308_16619_amd as csv
+    L = csv.lib()
+    lods = np.array([0, 2, 1, 5, 3], np.uint8)
+    off = np.zeros(5, np.uint64)
+    tot = ctypes.c_uint64()
+    assert L.csv_output_bytes(lods.ctypes.data, 5, off.ctypes.data, ctypes.byref(tot)) == 0
+    e_off, e_tot = csv.output_offsets(lods)
+    assert list(off) == [4 * int(v) for v in e_off] and tot.value == 4 * e_tot

@@ -87,7 +87,8 @@ def test_edge_bricks(csvlib, orc):
         np.testing.assert_array_equal(got[i], vol[:, :, 32 * i:32 * (i + 1)])
 
 
-@pytest.mark.parametrize("scale_bits,lane_k,lane_max", [(8, 1, 64), (11, 1000000, 64), (10, 16, 8), (11, 64, 1)])
+@pytest.mark.parametrize("scale_bits,lane_k,lane_max", [(8, 1, 64), (11, 1000000, 64), (10, 16, 8), (11, 64, 1),
+                                                        (12, 64, 64), (12, 256, 16)])
 def test_format_parameters(csvlib, orc, scale_bits, lane_k, lane_max):
     vol = synth.voronoi_bg(n=64, sites=300, bg=0.2, seed=scale_bits + lane_k)
     blob = orc.encode_volume(vol, scale_bits=scale_bits, lane_k=lane_k, lane_max=lane_max)
@@ -97,6 +98,31 @@ def test_format_parameters(csvlib, orc, scale_bits, lane_k, lane_max):
         log("format S=%d K=%d Wmax=%d lod %d" % (scale_bits, lane_k, lane_max, t))
         got = gpu_decode_uniform(pool, np.arange(8), t)
         np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(8), [t] * 8))
+
+
+def test_twelve_bit_tables_in_lds_and_in_global_memory(csvlib, orc, cfg1):
+    # one 12-bit volume: its two tables (32 KiB) are copied to LDS; with a
+    # 10-bit volume beside it the tables no longer fit and are read from
+    # global memory.  Both decode to the oracle's bytes.
+    vol, blob = cfg1
+    v12 = synth.cells(n=128, grid=9, seed=8)
+    b12 = orc.encode_volume(v12, scale_bits=12, lane_k=64)
+    solo = csvlib.Pool()
+    solo.add_volume(b12)
+    log("12-bit tables, LDS")
+    for t in (0, 1):
+        got = gpu_decode_uniform(solo, np.arange(64), t)
+        np.testing.assert_array_equal(got, orc.decode_bricks(b12, np.arange(64), [t] * 64))
+    both = csvlib.Pool()
+    assert both.add_volume(b12) == 0 and both.add_volume(blob) == 64
+    rng = np.random.default_rng(12)
+    ids = rng.integers(0, 72, 400)
+    lods = rng.integers(0, 4, 400)
+    log("12-bit and 10-bit tables, global memory")
+    got, _ = gpu_decode(both, ids, lods)
+    want = [orc.decode_brick(b12, int(i), int(t)) if i < 64 else orc.decode_brick(blob, int(i) - 64, int(t))
+            for i, t in zip(ids, lods)]
+    np.testing.assert_array_equal(got, np.concatenate([w.ravel() for w in want]))
 
 
 def test_plain_per_brick_launch_matches(csvlib, orc, cfg1):
@@ -140,6 +166,36 @@ def test_out_of_range_request_is_reported(csvlib, orc, cfg1):
     np.testing.assert_array_equal(got[:32768], orc.decode_brick(blob, 1, 0).ravel())
     np.testing.assert_array_equal(got[65536:], orc.decode_brick(blob, 2, 0).ravel())
     assert pool.last_error() == (0, 0)
+
+
+def test_status_names_each_failed_request(csvlib, orc, cfg1):
+    # csv_decode_bricks_status: an unknown id, a bad LOD and a corrupt
+    # record each mark their own request; the others stay 0 and decode
+    torch = torch_cuda()
+    vol, blob = cfg1
+    info = orc.volume_info(blob)
+    B = info["n_bricks"]
+    idx = np.frombuffer(blob, np.uint64, B + 1, 128)
+    rs = (128 + 8 * (B + 1) + 15) & ~15
+    w = np.frombuffer(blob, np.uint32, 8, rs + int(idx[6]))
+    bad = bytearray(blob)
+    bad[rs + int(idx[6]) + 4 * (8 + int(w[0]) + int(w[1])) + 2 * (int(w[2]) // 2)] ^= 0x10
+    pool = csvlib.Pool()
+    pool.add_volume(bytes(bad))
+    ids = np.array([2, 77, 6, 3, 1], np.uint32)
+    lods = np.array([0, 0, 0, 9, 1], np.uint8)
+    off, tot = csvlib.output_offsets(np.minimum(lods, 5))
+    status = torch.zeros(5, dtype=torch.int32, device="cuda")
+    out = torch.full((tot,), -1, dtype=torch.int32, device="cuda")
+    log("per-request status")
+    pool.decode(torch.from_numpy(ids.view(np.int32)).cuda(), out, lods=torch.from_numpy(lods).cuda(),
+                out_offsets=torch.from_numpy(off.view(np.int64)).cuda(), status=status)
+    torch.cuda.synchronize()
+    assert pool.last_error()[0] != 0
+    assert status.cpu().tolist() == [0, csvlib.CSV_ERANGE, csvlib.CSV_ECORRUPT, csvlib.CSV_ERANGE, 0]
+    got = out.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got[:32768], orc.decode_brick(blob, 2, 0).ravel())
+    np.testing.assert_array_equal(got[int(off[4]):int(off[4]) + 4096], orc.decode_brick(blob, 1, 1).ravel())
 
 
 def test_corrupt_record_is_reported(csvlib, orc, cfg1):

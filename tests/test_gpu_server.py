@@ -156,3 +156,69 @@ def test_trace_replay(setup, orc):
     st = srv.stats()
     log("trace p50 %.1f us p99 %.1f us" % (st["p50_us"], st["p99_us"]))
     srv.close()
+
+
+def test_big_palette_bricks_on_four_streams(orc):
+    # most bricks have palettes above 252 entries and take the leaf kernel's
+    # global-memory arenas; small batches on 4 streams overlap on the GPU
+    # (each stream has arenas of its own), and a 6 MiB cache evicts and
+    # decodes again.  Every completion equals the oracle's decode.
+    torch_cuda()
+    import paper_2308_16619_amd as csv
+    rng = np.random.default_rng(21)
+    noisy = rng.integers(1, 4000, size=(64, 64, 192)).astype(np.uint32)  # P about 3000
+    vol = np.ascontiguousarray(np.concatenate([noisy, synth.voronoi_bg(n=64, sites=60, seed=2)], axis=2))
+    blob = orc.encode_volume(vol, scale_bits=10, lane_k=64)
+    pool = csv.Pool()
+    pool.add_volume(blob)
+    nb = 4 * 8
+    n = 1200
+    ids = rng.integers(0, nb, n).astype(np.uint32)
+    lods = rng.choice([0, 0, 0, 1, 2], n).astype(np.uint32)
+    srv = csv.Server(pool, cache_bytes=6 << 20, inflight_bytes=1 << 20, max_batch=2, streams=4)
+    log("big palettes, 4 streams, %d requests" % n)
+    for k in range(0, n, 100):
+        srv.submit(srv.requests(ids[k:k + 100], lods[k:k + 100], tags=np.arange(k, min(n, k + 100))))
+    seen = 0
+    want = {}
+    for comp in wait_all(srv, n, timeout=120):
+        for c in comp:
+            assert c["status"] == 0
+            key = (int(c["brick_id"]), int(c["lod"]))
+            if key not in want:
+                want[key] = orc.decode_brick(blob, key[0], key[1]).ravel()
+            np.testing.assert_array_equal(srv.read(c), want[key])
+            seen += 1
+    st = srv.stats()
+    log("stats %s" % {k: st[k] for k in ("misses", "batches", "evictions", "rebuilds")})
+    assert seen == n and st["batches"] > 20 and st["failed"] == 0
+    srv.close()
+
+
+def test_failed_decode_is_reported_and_not_cached(setup, orc):
+    # a record with a flipped word-stream bit fails on the device: its
+    # requests complete with CSV_ECORRUPT every time (nothing is cached),
+    # the other bricks of the same batches decode to the oracle's bytes
+    csv, b1, b2 = setup
+    B = 8
+    idx = np.frombuffer(b1, np.uint64, B + 1, 128)
+    rs = (128 + 8 * (B + 1) + 15) & ~15
+    w = np.frombuffer(b1, np.uint32, 8, rs + int(idx[4]))
+    bad = bytearray(b1)
+    bad[rs + int(idx[4]) + 4 * (8 + int(w[0]) + int(w[1])) + 2 * (int(w[2]) // 2)] ^= 0x10
+    pool = csv.Pool()
+    pool.add_volume(bytes(bad))
+    srv = csv.Server(pool, cache_bytes=64 << 20, max_batch=8)
+    for rnd in range(2):
+        ids = np.array([3, 4, 5, 4, 0], np.uint32)
+        srv.submit(srv.requests(ids, np.zeros(5, np.uint32), tags=np.arange(5)))
+        for comp in wait_all(srv, 5):
+            for c in comp:
+                if c["brick_id"] == 4:
+                    assert c["status"] == csv.CSV_ECORRUPT and c["data"] == 0 and c["hit"] == 0
+                else:
+                    assert c["status"] == 0
+                    np.testing.assert_array_equal(srv.read(c), orc.decode_brick(b1, int(c["brick_id"]), 0).ravel())
+    st = srv.stats()
+    assert st["failed"] >= 2 and st["error"] == csv.CSV_ECORRUPT
+    srv.close()
