@@ -259,7 +259,10 @@ def detail_leg(csv, torch, blob, ids_np, ids, out, shape, whole_pool, reps=10):
     assert dpool.last_error()[0] == 0 and whole_pool.last_error()[0] == 0
     assert torch.equal(o1, w1), "level 1 of the split pool differs"
     del o1, w1
-    # frames: stage, decode at full LOD, release
+    # frames: stage, decode at full LOD, release; the reference is the
+    # whole-record pool's decode, taken here (the caller's buffer is shared
+    # with other legs)
+    whole_pool.decode(ids, out, lod=0)
     out2 = torch.empty_like(out)
     st, dec, wall, done = [], [], [], 0
     for r in range(reps + 2):
