@@ -258,6 +258,28 @@ int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *brick_ids, co
                              uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
                              void *stream, int32_t *status);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): csv_decode_bricks
+ * with the same arguments, results and errors, that allocates nothing.  Its
+ * intermediate buffers (launch counters, request lists, the per-request
+ * slots that carry level 1 and the leaf symbols from the entropy decoder to
+ * the leaf kernel, and 32 global arenas for bricks too large for LDS) live
+ * in one fixed device array of 64 MiB that the library holds on every GPU
+ * it runs on until the process ends.  The requests are decoded in
+ * consecutive chunks of as many as that array holds (about
+ * (64 MiB - 2.6 MiB) / (slot + 12 bytes), where a slot is about half a byte
+ * per symbol of the pool's largest brick plus 10 KB: some 2,600 requests of
+ * a dense 32^3 volume), each chunk one launch pair in stream order.
+ * CSV_ERANGE if a single request's slot would not fit the array.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (several
+ * streams or host threads at once) race and corrupt each other's output;
+ * serialise them.  Each call clears the counters it needs (with a kernel).
+ * Uses the pool's launch shape (csv_pool_set_shape, csv_autotune).  The
+ * caller still owns and passes the inputs and the output. */
+int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
+                              uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
+                              void *stream);
+
 /* Baseline: the same kernels launched once per brick (a grid of one
  * wavefront, then a grid of one workgroup: 2n launches on `stream`, 3n for
  * pools that need the global-memory leaf kernel).  Same arguments and

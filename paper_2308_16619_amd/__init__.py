@@ -116,6 +116,7 @@ def lib():
         L.csv_decode_bricks_status.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, vp]
         for f in ("csv_decode_bricks", "csv_decode_bricks_plain"):
             getattr(L, f).argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
+        L.csv_decode_bricks_noalloc.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
         L.csv_decode_bricks_shaped.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(Shape)]
         L.csv_pool_set_shape.argtypes = [vp, ctypes.POINTER(Shape)]
         L.csv_pool_get_shape.argtypes = [vp, ctypes.POINTER(Shape)]
@@ -312,6 +313,13 @@ class Pool:
             _chk(lib().csv_decode_bricks_plain(*args), "csv_decode_bricks_plain")
         else:
             _chk(lib().csv_decode_bricks(*args), "csv_decode_bricks")
+
+    def decode_noalloc(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None):
+        """decode() through csv_decode_bricks_noalloc: no device allocation;
+        the library's fixed scratch array on the device is shared by every
+        call on that GPU, so calls must not overlap."""
+        _chk(lib().csv_decode_bricks_noalloc(*self._args(ids, out, lods, lod, out_offsets, stream)),
+             "csv_decode_bricks_noalloc")
 
     def visible(self, ids, visible_bits, n_label_bits: int, out=None, stream=None):
         """Empty-space test: out[i] = 1 if some label of brick ids[i] has its

@@ -1706,7 +1706,20 @@ struct LaunchBufs {
 };
 constexpr size_t kMaxStreamBufs = 16;
 
+// csv_decode_bricks_noalloc: the launch buffers of one decode (counters and
+// order bins, global arenas, order and leaf lists, per-request slots) carved
+// out of one fixed device array instead of allocated memory
+constexpr size_t kNoAllocBytes = 64ull << 20;
+constexpr uint32_t kNoAllocArenas = 32;
+constexpr size_t kNoAllocHead = 512 + (size_t)kNoAllocArenas * kArenaBytes;  // counters, then arenas
+static_assert(kNoAllocHead % 256 == 0, "arena layout");
+
 }  // namespace
+
+// Scratch of csv_decode_bricks_noalloc: one copy per GPU, held until the
+// process ends.  In host code this name is not a device address: host code
+// uses the address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
 
 struct csv_pool {
     int device = 0;
@@ -1838,6 +1851,24 @@ uint64_t pool_device_bytes(const csv_pool *p) {
 // would `more` bytes of HBM exceed the pool's budget?
 bool over_budget(const csv_pool *p, uint64_t more) {
     return p->hbm_budget && pool_device_bytes(p) + more > p->hbm_budget;
+}
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (each GPU holds the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_at[kMaxDevices] = {};
+int scratch_address(int dev, uint8_t **out) {
+    if (dev < 0 || dev >= kMaxDevices) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        DeviceGuard g(dev);
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CSV_EHIP;
+        g_scratch_at[dev] = static_cast<uint8_t *>(ptr);
+    }
+    *out = g_scratch_at[dev];
+    return CSV_OK;
 }
 
 int stream_bufs(csv_pool *pool, hipStream_t s, uint32_t n, LaunchBufs **out) {
@@ -2068,6 +2099,11 @@ int csv_pool_create_budget(csv_pool **pool, int device, uint64_t hbm_budget_byte
     }
     p->n_cu = prop.multiProcessorCount;
     p->hbm_budget = hbm_budget_bytes;
+    uint8_t *scr = nullptr;  // set-up of this device's scratch address
+    if (scratch_address(device, &scr) != CSV_OK) {
+        delete p;
+        return CSV_EHIP;
+    }
     if (hipMalloc(reinterpret_cast<void **>(&p->d_err), 2 * sizeof(int)) != hipSuccess ||
         hipMemset(p->d_err, 0, 2 * sizeof(int)) != hipSuccess) {
         (void)hipFree(p->d_err);
@@ -2413,6 +2449,57 @@ int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *
     const csv_shape sh = pool->shape;
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0);
+}
+
+int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
+                              const uint64_t *out_off, uint32_t n, uint32_t *out, void *stream) {
+    if (!pool || (n && (!ids || !out))) return CSV_EINVAL;
+    if (!lods && lod_scalar > (uint32_t)kLog2) return CSV_ERANGE;
+    if (lods && !out_off) return CSV_EINVAL;
+    if (n == 0) return CSV_OK;
+    csv_pool *p = const_cast<csv_pool *>(pool);
+    uint8_t *base = nullptr;
+    int rc = scratch_address(p->device, &base);
+    if (rc) return rc;
+    LaunchBufs v;
+    v.owned = false;
+    v.stream = reinterpret_cast<hipStream_t>(stream);
+    csv_shape sh;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (p->rec_ptr.empty() || !p->d_err) return CSV_EINVAL;
+        v.slot_dw = slot_dw(p);
+        sh = p->shape;
+    }
+    // requests per launch pair: after the counters and arenas, 12 bytes of
+    // order and leaf lists plus one slot each (slots 256-byte aligned)
+    const uint64_t per = (uint64_t)v.slot_bytes() + 12;
+    const uint64_t fit = (kNoAllocBytes - kNoAllocHead - 256) / per;
+    if (fit == 0) return CSV_ERANGE;  // one request's slot exceeds the scratch
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(fit, n);
+    v.small = reinterpret_cast<uint32_t *>(base);
+    v.arenas = base + 512;
+    v.arena_groups = kNoAllocArenas;
+    v.order = reinterpret_cast<uint32_t *>(base + kNoAllocHead);
+    v.leaf_list = v.order + chunk;
+    v.slow_list = v.leaf_list + chunk;
+    const size_t lists_end = kNoAllocHead + 12ull * chunk;
+    v.slots = base + ((lists_end + 255) & ~(size_t)255);
+    v.cap_n = chunk;
+    // the previous call's counters and order bins may be left non-zero (a
+    // failed launch): clear them with a kernel, in stream order
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, v.stream, v.small, 72u);
+    if (hipGetLastError() != hipSuccess) return CSV_EHIP;
+    const uint64_t g = 32u >> lod_scalar;
+    for (uint32_t at = 0; at < n; at += chunk) {
+        const uint32_t m = std::min(chunk, n - at);
+        uint32_t *o = out_off ? out : out + (uint64_t)at * g * g * g;
+        rc = launch(p, ids + at, lods ? lods + at : nullptr, lod_scalar, out_off ? out_off + at : nullptr, m, o,
+                    stream, false, sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0,
+                    sh.lpt_order != 0, &v);
+        if (rc) return rc;
+    }
+    return CSV_OK;
 }
 
 int csv_bricks_visible(const csv_pool *pool, const uint32_t *ids, uint32_t n, const uint32_t *visible_bits,
