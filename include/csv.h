@@ -45,7 +45,7 @@ enum {
                           written upsampled 2x */
 };
 
-#define CSV_ABI_VERSION 1u
+#define CSV_ABI_VERSION 2u
 uint32_t csv_abi_version(void);
 
 /* Human-readable name of a CSV_E* code (static string). */
@@ -235,9 +235,13 @@ int csv_output_bytes(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
  * leaf-level replay and output (an 8-wavefront workgroup per brick; Alg. 1),
  * plus a third launch for pools holding bricks whose leaf arrays may not
  * fit that workgroup's LDS.
+ * Large batches are split into chunks that alternate between `stream` and
+ * a second stream the pool creates for it (csv_shape.chunks); the call is
+ * still one ordered operation on `stream`.
  * Each stream has its own intermediate buffers (up to 16 streams per pool
- * at once; a 17th waits for all work on the device), so decodes on
- * different streams may overlap; decodes on one stream run in order.  The
+ * at once, second streams included; a 17th waits for all work on the
+ * device), so decodes on different streams may overlap; decodes on one
+ * stream run in order.  The
  * buffers grow on demand, which synchronises the stream, and cannot grow
  * inside a stream capture (CSV_EBUSY): capture with csv_graph_create.
  * Argument errors are returned synchronously.  Errors found on the device
@@ -299,6 +303,12 @@ typedef struct {
                                0: static round robin */
     int lpt_order;          /* 1: requests are first ordered longest-first (binned by log2 of their
                                symbols + output voxels / 8; one small kernel before the decode) */
+    uint32_t chunks;        /* 1..64: the requests are split into this many consecutive chunks that
+                               alternate between the caller's stream and a second stream the pool
+                               keeps for it, so that the entropy decode of one chunk overlaps the
+                               leaf level of the previous one (at most n / 2048 chunks; 1: one
+                               launch pair; graphs, csv_decode_bricks_noalloc and stream captures
+                               use one) */
     float ms;               /* csv_autotune: the measured time per launch of this shape */
 } csv_shape;
 
@@ -307,7 +317,7 @@ int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *brick_ids, co
                              uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
                              void *stream, const csv_shape *shape);
 
-/* The shape csv_decode_bricks uses (default {16, 3, 1, 0}). */
+/* The shape csv_decode_bricks uses (default {16, 3, 0, 0, 4}). */
 int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape);
 int csv_pool_get_shape(const csv_pool *pool, csv_shape *shape);
 
@@ -333,12 +343,13 @@ int csv_bricks_visible(const csv_pool *pool, const uint32_t *brick_ids, uint32_t
                        uint32_t n_label_bits, uint8_t *visible, void *stream);
 
 /* Autotuner: decodes the given request set (same arguments as
- * csv_decode_bricks; `out` is overwritten) with every candidate shape
- * (front waves {8, 16} x leaf groups {2, 3, 4, 5} x queue {0, 1} x order
- * {0, 1}), one
- * warm-up and `reps` timed launches each (HIP events on `stream`), makes
- * the fastest the pool's shape and returns it in *best (may be NULL).
- * Synchronous.  Not allowed while `stream` is being captured. */
+ * csv_decode_bricks; `out` is overwritten) with candidate shapes, one
+ * coordinate at a time: front waves {8, 16} x leaf groups {2, 3, 4} (static
+ * order, min(4, n / 2048) chunks), then the chunk count {1, 2, 4, 8}, then
+ * work counters and longest-first order; one warm-up and `reps` timed
+ * launches each (HIP events on `stream`).  Makes the fastest the pool's
+ * shape and returns it in *best (may be NULL).  Synchronous.  Not allowed
+ * while `stream` is being captured. */
 int csv_autotune(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                  const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream, uint32_t reps,
                  csv_shape *best);

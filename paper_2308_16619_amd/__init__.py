@@ -42,10 +42,16 @@ class VolumeInfo(ctypes.Structure):
 
 class Shape(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int), ("groups_per_cu", ctypes.c_uint32), ("use_queue", ctypes.c_int),
-                ("lpt_order", ctypes.c_int), ("ms", ctypes.c_float)]
+                ("lpt_order", ctypes.c_int), ("chunks", ctypes.c_uint32), ("ms", ctypes.c_float)]
 
     def as_tuple(self):
-        return (self.waves_per_group, self.groups_per_cu, self.use_queue, self.lpt_order)
+        return (self.waves_per_group, self.groups_per_cu, self.use_queue, self.lpt_order, self.chunks)
+
+    @classmethod
+    def of(cls, shape):
+        """(waves, groups, queue[, lpt[, chunks]]); lpt 0 and 1 chunk by default."""
+        v = [int(x) for x in shape] + [0, 1][len(shape) - 3:] if len(shape) < 5 else [int(x) for x in shape]
+        return cls(v[0], v[1], v[2], v[3], v[4], 0.0)
 
 
 REQUEST_DTYPE = np.dtype([("brick_id", "<u4"), ("lod", "<u4"), ("tag", "<u8"), ("t_arrival_ns", "<u8")])
@@ -145,7 +151,7 @@ def lib():
         L.csv_frame_cache_data.argtypes = [vp]
         L.csv_frame_cache_read.argtypes = [vp, u64, u64, vp]
         L.csv_frame_cache_destroy.argtypes = [vp]
-        if L.csv_abi_version() != 1:
+        if L.csv_abi_version() != 2:
             raise RuntimeError("libcsv.so ABI mismatch")
         _lib = L
     return _lib
@@ -307,7 +313,7 @@ class Pool:
         if status is not None:
             _chk(lib().csv_decode_bricks_status(*args, ctypes.c_void_p(status.data_ptr())), "csv_decode_bricks_status")
         elif shape is not None:
-            sh = Shape(int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3]) if len(shape) > 3 else 0, 0.0)
+            sh = Shape.of(shape)
             _chk(lib().csv_decode_bricks_shaped(*args, ctypes.byref(sh)), "csv_decode_bricks_shaped")
         elif plain:
             _chk(lib().csv_decode_bricks_plain(*args), "csv_decode_bricks_plain")
@@ -337,7 +343,7 @@ class Pool:
         return out
 
     def set_shape(self, shape):
-        sh = Shape(int(shape[0]), int(shape[1]), int(shape[2]), int(shape[3]) if len(shape) > 3 else 0, 0.0)
+        sh = Shape.of(shape)
         _chk(lib().csv_pool_set_shape(self._p, ctypes.byref(sh)), "csv_pool_set_shape")
 
     def get_shape(self):

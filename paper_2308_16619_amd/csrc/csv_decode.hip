@@ -74,8 +74,8 @@ constexpr uint32_t kWDeltaDw = (kWaveLds - kWPal) / 4;  // the palette area hold
 // then the levels (u16 levels 1..4 for big palettes; else u8 L_1 only, in
 // Morton order), the expansion bits of levels 1..4 (L_1 first) and
 // {E_1, P_a operations above L_0}.
-constexpr uint32_t kSlotLv = 9376, kSlotBm = 608, kSlotMeta = 16;
-constexpr uint32_t kSlotExtra = kSlotLv + kSlotBm + kSlotMeta;
+constexpr uint32_t kSlotLv = 9376, kSlotBm = 608;
+constexpr uint32_t kSlotExtra = kSlotLv + kSlotBm;
 
 struct DecodeArgs {
     const uint64_t *rec_ptr;
@@ -100,7 +100,19 @@ struct DecodeArgs {
     // per-request status (else nullptr): a failed request rq gets its error
     // code in req_err[rq]; successful requests leave their entry untouched
     int *req_err;
+    uint32_t rq_base;  // index of request 0 in the caller's whole batch (errors name requests by it)
 };
+
+// What the leaf kernel needs of a full-LOD request, written by the front
+// kernel when it hands the request over (so that the leaf kernel reaches
+// every address with one load)
+struct LeafDesc {
+    uint32_t rq, id, P, c0;
+    uint32_t c1, E1, ipl, pad;
+    uint64_t rec;  // record address
+    uint64_t dst;  // output address
+};
+static_assert(sizeof(LeafDesc) == 48, "leaf descriptor");
 
 struct LaunchA {
     uint32_t lut_lds_words;  // decode-table words in LDS (0: tables read from global memory)
@@ -109,7 +121,7 @@ struct LaunchA {
     uint8_t *slots;          // slot_bytes per request
     uint32_t slot_bytes;
     uint32_t slot_dw;        // nibble dwords at the start of a slot
-    uint32_t *leaf_list;     // requests left for the leaf kernel
+    LeafDesc *leaf_list;     // requests left for the leaf kernel
     uint32_t *leaf_count;
     uint32_t base;           // first request index
     uint32_t *words_out;     // prefix pass (else nullptr): per request the words the decode of its
@@ -120,9 +132,9 @@ struct LaunchA {
 struct LaunchB {
     uint32_t arena_bytes;    // LDS arena per workgroup
     uint32_t *queue;         // work counter over the leaf list (nullptr: static round robin)
-    const uint32_t *leaf_list;
+    const LeafDesc *leaf_list;
     const uint32_t *leaf_count;
-    uint32_t *slow_list;     // leaf requests that do not fit the LDS arena
+    LeafDesc *slow_list;     // leaf requests that do not fit the LDS arena
     uint32_t *slow_count;
     uint32_t *slow_queue;
     const uint8_t *slots;
@@ -995,7 +1007,6 @@ __device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, con
     const uint32_t hdr = csv::record_header_words(kLog2);
     uint8_t *slv = slot + 4 * l.slot_dw;
     uint8_t *sbm = slv + kSlotLv;
-    uint32_t *smeta = reinterpret_cast<uint32_t *>(sbm + kSlotBm);
     IdxT *lv = kG ? reinterpret_cast<IdxT *>(slv) : reinterpret_cast<IdxT *>(wl + kWLv);
     uint8_t *bm = wl + kWBm;
     uint16_t *lst = reinterpret_cast<uint16_t *>(wl + kWLst);
@@ -1020,10 +1031,13 @@ __device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, con
         for (int q = 0; q < 4; q++) reinterpret_cast<uint4 *>(slv)[L + 64 * q] = src[L + 64 * q];
     }
     if (L < 32) reinterpret_cast<uint4 *>(sbm)[L] = reinterpret_cast<const uint4 *>(bm)[L];
-    if (L == 0) *reinterpret_cast<uint4 *>(smeta) = make_uint4(E1, ipl, 0u, 0u);
     if (L == 0) {
         const uint32_t at = atomicAdd(l.leaf_count, 1u);
-        l.leaf_list[at] = h.rq;
+        uint4 *d = reinterpret_cast<uint4 *>(l.leaf_list + at);
+        const uint64_t ra = reinterpret_cast<uintptr_t>(h.rec), da = reinterpret_cast<uintptr_t>(dst);
+        d[0] = make_uint4(h.rq, h.id, h.P, h.c0);
+        d[1] = make_uint4(h.c1, E1, ipl, 0u);
+        d[2] = make_uint4((uint32_t)ra, (uint32_t)(ra >> 32), (uint32_t)da, (uint32_t)(da >> 32));
     }
     return true;
 }
@@ -1061,12 +1075,12 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             continue;
         }
         if (kind == kReqBadLod) {
-            if (L == 0) fail(a, rq, CSV_ERANGE, rq);
+            if (L == 0) fail(a, rq, CSV_ERANGE, a.rq_base + rq);
             continue;
         }
         if (kind != kReqDecode) {
             if (kind != kReqFill && L == 0) fail(a, rq, kind == kReqBadId ? CSV_ERANGE : CSV_ECORRUPT,
-                                                 kind == kReqBadId ? rq : h.id);
+                                                 kind == kReqBadId ? a.rq_base + rq : h.id);
             fill_labels<64>(dst, count, kind == kReqFill ? fill : 0u, L);
             continue;
         }
@@ -1461,25 +1475,31 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
     const uint32_t tid = threadIdx.x;
     const uint32_t hdr = csv::record_header_words(kLog2);
     const uint32_t n_items = *glob(kSlow ? l.slow_count : l.leaf_count);
-    const uint32_t *list = kSlow ? l.slow_list : l.leaf_list;
+    const LeafDesc *list = kSlow ? l.slow_list : l.leaf_list;
     uint32_t *queue = kSlow ? l.slow_queue : l.queue;
     for (uint32_t k = 0;; k++) {
         if (tid == 0) sm->req = queue ? atomicAdd(queue, 1u) : blockIdx.x + k * gridDim.x;
         __syncthreads();
         const uint32_t item = uniform(sm->req);
         if (item >= n_items) break;
-        const uint32_t rq = ld_s(list + item);
+        // a request at t = 0 the front kernel has checked and decoded down to level 1
+        const LeafDesc *ds = list + item;
+        const uint32_t rq = ld_s(&ds->rq);
         Hdr h;
-        uint32_t *dst, count, fill;
-        (void)load_request(a, rq, h, dst, count, fill);  // a decode at t = 0: checked by the front kernel
+        h.rq = rq;
+        h.id = ld_s(&ds->id);
+        h.P = ld_s(&ds->P);
+        h.c0 = ld_s(&ds->c0);
+        h.c1 = ld_s(&ds->c1);
+        h.rec = rec_at(ld_s(&ds->rec));
+        uint32_t *dst = reinterpret_cast<uint32_t *>(ld_s(&ds->dst));
+        const uint32_t count = 32768u;
+        const uint32_t E1 = ld_s(&ds->E1), ipl = ld_s(&ds->ipl);
         phase_mark(rq, 6);
         const uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
         const uint32_t *gnib = reinterpret_cast<const uint32_t *>(slot);
         const uint8_t *slv = slot + 4 * l.slot_dw;
         const uint8_t *sbm = slv + kSlotLv;
-        const uint32_t *meta = rec_at(reinterpret_cast<uintptr_t>(l.slots) + (size_t)rq * l.slot_bytes +
-                                      4 * l.slot_dw + kSlotLv + kSlotBm);
-        const uint32_t E1 = ld_s(meta), ipl = ld_s(meta + 1);
         const uint32_t E1c = E1 < 4096 ? E1 : 4096u;
         if (tid == 0) {
             sm->err = 0;
@@ -1490,7 +1510,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
             // nibbles from the delta segment of L_0 on, from a 16-byte boundary
             const uint32_t nb0 = (h.c1 >> 5) << 2, nib4 = (((h.c0 + 7) >> 3) + 2 - nb0 + 3) / 4;
             const LayoutL fast = make_layout_l(true, h.P, nib4, E1c, 1);
-            if (h.P <= kPalFast && fast.total <= l.arena_bytes) {
+            // without its nibbles staged (they are read from the slot)
+            const LayoutL lean = make_layout_l(true, h.P, 0, E1c, 1);
+            if (h.P <= kPalFast && fast.total > l.arena_bytes && lean.total <= l.arena_bytes) {
+                for (uint32_t e = tid; e < h.P; e += NT) reinterpret_cast<uint32_t *>(arena + lean.pal)[e] = h.rec[hdr + e];
+                if (tid < 32) reinterpret_cast<uint4 *>(arena + lean.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
+                const uint4 l1q = tid < 256 ? reinterpret_cast<const uint4 *>(slv)[tid] : make_uint4(0u, 0u, 0u, 0u);
+                __syncthreads();
+                ok = leaf_replay<uint8_t, false, NW>(h, E1, ipl, gnib, 0, slv,
+                                                     reinterpret_cast<const uint64_t *>(arena + lean.bm1),
+                                                     reinterpret_cast<const uint32_t *>(arena + lean.pal), arena, lean,
+                                                     sm, dst, reinterpret_cast<uint16_t *>(arena + lean.total),
+                                                     min((l.arena_bytes - lean.total) / 2, l.ref_cap), &l1q);
+            } else if (h.P <= kPalFast && fast.total <= l.arena_bytes) {
                 for (uint32_t e = tid; e < h.P; e += NT) reinterpret_cast<uint32_t *>(arena + fast.pal)[e] = h.rec[hdr + e];
                 for (uint32_t e = tid; e < nib4; e += NT)
                     reinterpret_cast<uint4 *>(arena + fast.nib)[e] = reinterpret_cast<const uint4 *>(gnib + nb0)[e];
@@ -1505,7 +1537,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
                                                      min((l.arena_bytes - fast.total) / 2, l.ref_cap), &l1q);
             } else if (l.slow_list) {  // the slow kernel takes it
                 done = false;
-                if (tid == 0) l.slow_list[atomicAdd(l.slow_count, 1u)] = rq;
+                if (tid == 0) {
+                    const uint4 *src = reinterpret_cast<const uint4 *>(glob(ds));
+                    uint4 *to = reinterpret_cast<uint4 *>(l.slow_list + atomicAdd(l.slow_count, 1u));
+                    to[0] = src[0];
+                    to[1] = src[1];
+                    to[2] = src[2];
+                }
             } else {  // the pool's bounds say every brick fits: a corrupt record
                 ok = false;
             }
@@ -1643,8 +1681,8 @@ struct LaunchBufs {
     uint64_t last_use = 0;
     uint8_t *slots = nullptr;      // slot_bytes per request
     uint32_t *order = nullptr;     // longest-first order
-    uint32_t *leaf_list = nullptr; // requests for the leaf kernel
-    uint32_t *slow_list = nullptr; // ... of them for its global-arena variant
+    LeafDesc *leaf_list = nullptr; // requests for the leaf kernel
+    LeafDesc *slow_list = nullptr; // ... of them for its global-arena variant
     uint32_t *small = nullptr;     // [0, 64): order bins; [64, 72): the launch counters
     uint8_t *arenas = nullptr;     // global arenas of the global-arena leaf kernel, one per workgroup
     uint32_t arena_groups = 0;     // workgroups they serve
@@ -1690,18 +1728,22 @@ struct LaunchBufs {
         slot_dw = dw;
         if (hipMalloc(reinterpret_cast<void **>(&slots), (size_t)cap * slot_bytes()) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&order), 4ull * cap) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&leaf_list), 4ull * cap) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&slow_list), 4ull * cap) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&small), 4 * 72) != hipSuccess ||
-            hipMemset(small, 0, 4 * 72) != hipSuccess) {
+            hipMalloc(reinterpret_cast<void **>(&leaf_list), sizeof(LeafDesc) * cap) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&slow_list), sizeof(LeafDesc) * cap) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&small), 4 * 72) != hipSuccess) {
             release();
             return CSV_ENOMEM;
         }
         cap_n = cap;
+        // the counters are cleared by a kernel on the stream that uses them
+        // (a memset on another stream would not be ordered with its work)
+        dirty = true;
         return CSV_OK;
     }
     // HBM of the slots, lists and counters for cap requests of dw nibble dwords
-    static uint64_t sized(uint32_t cap, uint32_t dw) { return (uint64_t)cap * (4ull * dw + kSlotExtra + 12) + 4 * 72; }
+    static uint64_t sized(uint32_t cap, uint32_t dw) {
+        return (uint64_t)cap * (4ull * dw + kSlotExtra + 4 + 2 * sizeof(LeafDesc)) + 4 * 72;
+    }
     uint64_t bytes() const { return (slots ? sized(cap_n, slot_dw) : 0) + (uint64_t)arena_groups * kArenaBytes; }
 };
 constexpr size_t kMaxStreamBufs = 16;
@@ -1741,11 +1783,11 @@ struct csv_pool {
     std::vector<LaunchBufs> bufs;             // per stream, at most kMaxStreamBufs
     uint64_t use_clock = 0;
     uint32_t max_c0 = 0;                      // most symbols of any brick in the pool
-    uint32_t max_fast_bytes = 0;              // largest LDS arena a brick of the pool needs
+    uint32_t max_fast_bytes = 0;              // largest LDS arena a brick of the pool needs (nibbles not staged)
     bool any_big_palette = false;
     uint64_t hbm_budget = 0;                  // HBM the pool may hold (0: no limit)
     uint32_t generation = 0;                  // bumped when device tables move
-    csv_shape shape{16, 3, 1, 0, 0.f};        // launch shape of csv_decode_bricks
+    csv_shape shape{16, 3, 0, 0, 4, 0.f};     // launch shape of csv_decode_bricks
     uint64_t record_bytes = 0;
     // level-0 detail in host memory (csv_pool_add_volume_ex, CSV_DETAIL_HOST)
     bool any_split = false;
@@ -1762,6 +1804,14 @@ struct csv_pool {
     uint8_t *d_stage = nullptr, *h_stage = nullptr;  // staging buffer and its pinned host image
     uint64_t stage_cap = 8ull << 20, stage_used = 0, stage_alloc = 0;
     hipEvent_t stage_ev = nullptr;           // the last staging copies
+    // pipelined decodes: per caller stream, a second stream that takes every
+    // other chunk of requests, and the events that fork it from the caller's
+    // stream and join it back
+    struct Companion {
+        hipStream_t caller = nullptr, own = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+    };
+    std::vector<Companion> companions;       // reserved once: entries never move
     std::mutex mu;
 };
 
@@ -1938,9 +1988,9 @@ uint32_t ref_list_cap() {
     return (end && *end == 0) ? (uint32_t)std::min<unsigned long>(v, 0xFFFFFFFFul) : 0xFFFFFFFFu;
 }
 
-int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
-           uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
-           bool lpt, LaunchBufs *fixed = nullptr, uint32_t *words_out = nullptr, int *req_err = nullptr) {
+int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
+               uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
+               bool lpt, LaunchBufs *fixed, uint32_t *words_out, int *req_err, uint32_t rq_base = 0) {
     if (!pool || (n && (!ids || !out))) return CSV_EINVAL;
     if (!lods && lod_scalar > (uint32_t)kLog2) return CSV_ERANGE;
     if (lods && !out_off) return CSV_EINVAL;
@@ -1980,6 +2030,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     a.pfx_dw = pool->any_split ? pool->d_pfx_dw : nullptr;
     a.sfx = pool->any_split ? pool->d_sfx : nullptr;
     a.req_err = req_err;
+    a.rq_base = rq_base;
     const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
     // the global-arena variant runs only for pools with bricks that may not fit the LDS arena;
     // its arenas belong to this buffer set, so launches on other streams never share them
@@ -1999,8 +2050,8 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     // workgroup of the leaf kernels (0, 1, 2, 5) and of the global-arena
     // kernel (3, 4, 6), which only runs when the leaf kernel may defer to it.
     uint32_t *ctr = B->small + 2 * kBins;
-    if (B->dirty) {  // a launch failed part way: start from zero (a kernel, so that graphs may hold it)
-        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, ctr, 8u);
+    if (B->dirty) {  // new buffers, or a launch failed part way: start from zero (a kernel, in stream order)
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, B->small, 72u);
         B->dirty = false;
     }
     LaunchA la;
@@ -2073,9 +2124,80 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     return CSV_OK;
 }
 
+// Requests per chunk below which a decode is not split (a chunk should
+// still fill the machine for a while).
+constexpr uint32_t kMinChunk = 2048;
+constexpr size_t kMaxCompanions = kMaxStreamBufs / 2;
+
+// The companion stream of caller stream s, created on first use (nullptr
+// when the pool already serves kMaxCompanions callers).  pool->mu held.
+csv_pool::Companion *companion(csv_pool *pool, hipStream_t s) {
+    for (auto &c : pool->companions)
+        if (c.caller == s) return &c;
+    if (pool->companions.size() >= kMaxCompanions) return nullptr;
+    pool->companions.reserve(kMaxCompanions);
+    csv_pool::Companion c;
+    c.caller = s;
+    if (hipStreamCreateWithFlags(&c.own, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&c.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c.join, hipEventDisableTiming) != hipSuccess) {
+        if (c.fork) (void)hipEventDestroy(c.fork);
+        (void)hipStreamDestroy(c.own);
+        return nullptr;
+    }
+    pool->companions.push_back(c);
+    return &pool->companions.back();
+}
+
+// A decode of n requests.  With chunks > 1 the requests are split into that
+// many consecutive chunks that alternate between the caller's stream and
+// its companion stream: the entropy decode of one chunk overlaps the leaf
+// level of the previous one.  The companion waits for the caller's stream
+// before its first chunk, and the caller's stream waits for the companion
+// after its last, so the call stays ordered on `stream` as one operation.
+// Fixed buffers (graphs), prefix passes, per-brick launches, stream
+// captures and small batches run as one launch pair.
+int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
+           uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
+           bool lpt, LaunchBufs *fixed = nullptr, uint32_t *words_out = nullptr, int *req_err = nullptr,
+           uint32_t chunks = 1) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    chunks = std::min(chunks, n / kMinChunk);
+    if (chunks <= 1 || !pool || plain || fixed || words_out || !ids || !out || (lods && !out_off) ||
+        (!lods && lod_scalar > (uint32_t)kLog2) || capturing(s))
+        return launch_one(pool, ids, lods, lod_scalar, out_off, n, out, stream, plain, waves_a, groups_b, queue,
+                          lpt, fixed, words_out, req_err);
+    csv_pool::Companion *c = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        DeviceGuard g(pool->device);
+        c = companion(pool, s);
+    }
+    if (!c)
+        return launch_one(pool, ids, lods, lod_scalar, out_off, n, out, stream, plain, waves_a, groups_b, queue,
+                          lpt, fixed, words_out, req_err);
+    DeviceGuard g(pool->device);
+    if (hipEventRecord(c->fork, s) != hipSuccess || hipStreamWaitEvent(c->own, c->fork, 0) != hipSuccess)
+        return CSV_EHIP;
+    const uint32_t per = (n + chunks - 1) / chunks;
+    const uint64_t G = 32u >> (lods ? 0u : lod_scalar);
+    const uint64_t cnt = lods ? 0 : G * G * G;
+    int rc = CSV_OK;
+    for (uint32_t k = 0, at = 0; at < n && rc == CSV_OK; k++, at += per) {
+        const uint32_t m = std::min(per, n - at);
+        rc = launch_one(pool, ids + at, lods ? lods + at : nullptr, lod_scalar, out_off ? out_off + at : nullptr, m,
+                        out_off ? out : out + (uint64_t)at * cnt, (k & 1) ? (void *)c->own : stream, false, waves_a,
+                        groups_b, queue, lpt, nullptr, nullptr, req_err ? req_err + at : nullptr, at);
+    }
+    // joined back in every case, so that nothing of the call runs unordered
+    if (hipEventRecord(c->join, c->own) != hipSuccess || hipStreamWaitEvent(s, c->join, 0) != hipSuccess)
+        rc = rc ? rc : CSV_EHIP;
+    return rc;
+}
+
 bool valid_shape(const csv_shape &sh) {
     return (sh.waves_per_group == 4 || sh.waves_per_group == 8 || sh.waves_per_group == 16) &&
-           sh.groups_per_cu >= 1 && sh.groups_per_cu <= kMaxGroupsB;
+           sh.groups_per_cu >= 1 && sh.groups_per_cu <= kMaxGroupsB && sh.chunks >= 1 && sh.chunks <= 64;
 }
 
 }  // namespace
@@ -2105,7 +2227,7 @@ int csv_pool_create_budget(csv_pool **pool, int device, uint64_t hbm_budget_byte
         return CSV_EHIP;
     }
     if (hipMalloc(reinterpret_cast<void **>(&p->d_err), 2 * sizeof(int)) != hipSuccess ||
-        hipMemset(p->d_err, 0, 2 * sizeof(int)) != hipSuccess) {
+        hipMemset(p->d_err, 0, 2 * sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(p->d_err);
         delete p;
         return CSV_ENOMEM;
@@ -2134,6 +2256,11 @@ void csv_pool_destroy(csv_pool *p) {
     for (void *b : p->host_bufs) (void)hipHostFree(b);
     if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
     for (auto &b : p->bufs) b.release();
+    for (auto &c : p->companions) {
+        (void)hipEventDestroy(c.fork);
+        (void)hipEventDestroy(c.join);
+        (void)hipStreamDestroy(c.own);
+    }
     delete p;
 }
 
@@ -2158,8 +2285,9 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
         if (c0 == 0) continue;
         big |= P > kPalFast;
         max_c0 = std::max(max_c0, c0);
-        const uint32_t e1 = std::min((c0 - c1) / 8, 4096u), nb0 = (c1 >> 5) << 2;
-        max_fast = std::max(max_fast, make_layout_l(true, P, (((c0 + 7) >> 3) + 2 - nb0 + 3) / 4, e1, 1).total);
+        const uint32_t e1 = std::min((c0 - c1) / 8, 4096u);
+        // a brick whose staged nibbles do not fit reads them from its slot
+        max_fast = std::max(max_fast, make_layout_l(true, P, 0, e1, 1).total);
     }
     // the kernels run to the end of a record; 64 bytes of slack cover their last vector loads
     void *buf = nullptr;
@@ -2440,7 +2568,7 @@ int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *ids, const ui
     const csv_shape sh = pool->shape;
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr,
-                  nullptr, status);
+                  nullptr, status, sh.chunks);
 }
 
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
@@ -2448,7 +2576,8 @@ int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *
     if (!pool) return CSV_EINVAL;
     const csv_shape sh = pool->shape;
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
-                  sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0);
+                  sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr,
+                  nullptr, nullptr, sh.chunks);
 }
 
 int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
@@ -2471,19 +2600,20 @@ int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const u
         v.slot_dw = slot_dw(p);
         sh = p->shape;
     }
-    // requests per launch pair: after the counters and arenas, 12 bytes of
-    // order and leaf lists plus one slot each (slots 256-byte aligned)
-    const uint64_t per = (uint64_t)v.slot_bytes() + 12;
-    const uint64_t fit = (kNoAllocBytes - kNoAllocHead - 256) / per;
+    // requests per launch pair: after the counters and arenas, 4 bytes of
+    // order list and two 48-byte leaf descriptors plus one slot each (the
+    // descriptors 16-byte, the slots 256-byte aligned: 512 bytes of slack)
+    const uint64_t per = (uint64_t)v.slot_bytes() + 4 + 2 * sizeof(LeafDesc);
+    const uint64_t fit = (kNoAllocBytes - kNoAllocHead - 512) / per;
     if (fit == 0) return CSV_ERANGE;  // one request's slot exceeds the scratch
     const uint32_t chunk = (uint32_t)std::min<uint64_t>(fit, n);
     v.small = reinterpret_cast<uint32_t *>(base);
     v.arenas = base + 512;
     v.arena_groups = kNoAllocArenas;
     v.order = reinterpret_cast<uint32_t *>(base + kNoAllocHead);
-    v.leaf_list = v.order + chunk;
+    v.leaf_list = reinterpret_cast<LeafDesc *>(base + kNoAllocHead + ((4ull * chunk + 15) & ~15ull));
     v.slow_list = v.leaf_list + chunk;
-    const size_t lists_end = kNoAllocHead + 12ull * chunk;
+    const size_t lists_end = kNoAllocHead + ((4ull * chunk + 15) & ~15ull) + 2 * sizeof(LeafDesc) * chunk;
     v.slots = base + ((lists_end + 255) & ~(size_t)255);
     v.cap_n = chunk;
     // the previous call's counters and order bins may be left non-zero (a
@@ -2494,9 +2624,9 @@ int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const u
     for (uint32_t at = 0; at < n; at += chunk) {
         const uint32_t m = std::min(chunk, n - at);
         uint32_t *o = out_off ? out : out + (uint64_t)at * g * g * g;
-        rc = launch(p, ids + at, lods ? lods + at : nullptr, lod_scalar, out_off ? out_off + at : nullptr, m, o,
-                    stream, false, sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0,
-                    sh.lpt_order != 0, &v);
+        rc = launch_one(p, ids + at, lods ? lods + at : nullptr, lod_scalar, out_off ? out_off + at : nullptr, m, o,
+                        stream, false, sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0,
+                        sh.lpt_order != 0, &v, nullptr, nullptr, at);
         if (rc) return rc;
     }
     return CSV_OK;
@@ -2530,7 +2660,7 @@ int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *ids, const ui
     if (!pool || !shape || !valid_shape(*shape)) return CSV_EINVAL;
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   shape->waves_per_group, (uint32_t)shape->groups_per_cu, shape->use_queue != 0,
-                  shape->lpt_order != 0);
+                  shape->lpt_order != 0, nullptr, nullptr, nullptr, shape->chunks);
 }
 
 int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape) {
@@ -2552,31 +2682,59 @@ int csv_autotune(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint3
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (capturing(s)) return CSV_EINVAL;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CSV_EHIP;
-    const int waves[2] = {8, 16};
-    const uint32_t groups[4] = {2, 3, 4, 5};
+    if (hipEventCreate(&e0) != hipSuccess) return CSV_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CSV_EHIP;
+    }
+    int rc = CSV_OK;
+    // time of one shape: one warm-up launch, then reps timed launches
+    auto time_shape = [&](csv_shape &sh) {
+        rc = launch(pool, ids, lods, lod_scalar, out_off, n, out, stream, false, sh.waves_per_group,
+                    (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr, nullptr, nullptr,
+                    sh.chunks);
+        if (rc) return;
+        (void)hipEventRecord(e0, s);
+        for (uint32_t r = 0; r < reps && !rc; r++)
+            rc = launch(pool, ids, lods, lod_scalar, out_off, n, out, stream, false, sh.waves_per_group,
+                        (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr, nullptr, nullptr,
+                        sh.chunks);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess && !rc) rc = CSV_EHIP;
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = CSV_EHIP;
+        sh.ms = ms / (float)reps;
+    };
     csv_shape win{};
     win.ms = 1e30f;
-    int rc = CSV_OK;
-    for (int wi = 0; wi < 2 && !rc; wi++)
-        for (int gi = 0; gi < 4 && !rc; gi++)
-            for (int q = 0; q < 2 && !rc; q++)
-                for (int o = 0; o < 2 && !rc; o++) {
-                csv_shape sh{waves[wi], groups[gi], q, o, 0.f};
-                // one warm-up launch, then reps timed launches
-                rc = launch(pool, ids, lods, lod_scalar, out_off, n, out, stream, false, sh.waves_per_group,
-                            (uint32_t)sh.groups_per_cu, q != 0, o != 0);
-                if (rc) break;
-                (void)hipEventRecord(e0, s);
-                for (uint32_t r = 0; r < reps && !rc; r++)
-                    rc = launch(pool, ids, lods, lod_scalar, out_off, n, out, stream, false, sh.waves_per_group,
-                                (uint32_t)sh.groups_per_cu, q != 0, o != 0);
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) rc = CSV_EHIP;
-                float ms = 0.f;
-                if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = CSV_EHIP;
-                sh.ms = ms / (float)reps;
-                if (!rc && sh.ms < win.ms) win = sh;
+    auto consider = [&](csv_shape sh) {
+        if (rc) return;
+        time_shape(sh);
+        if (!rc && sh.ms < win.ms) win = sh;
+    };
+    // one coordinate at a time: the two kernels' shapes with the requests
+    // split in up to four chunks, then the chunk count, then the work
+    // counters and the longest-first order
+    const uint32_t c0 = std::max(1u, std::min(4u, n / kMinChunk));
+    const int waves[2] = {8, 16};
+    const uint32_t groups[3] = {2, 3, 4};
+    for (int wi = 0; wi < 2; wi++)
+        for (int gi = 0; gi < 3; gi++) consider(csv_shape{waves[wi], groups[gi], 0, 0, c0, 0.f});
+    const csv_shape base = win;
+    for (uint32_t c : {1u, 2u, 4u, 8u})
+        if (c != c0 && (c == 1 || c <= n / kMinChunk)) {
+            csv_shape sh = base;
+            sh.chunks = c;
+            consider(sh);
+        }
+    const csv_shape base2 = win;
+    for (int q = 0; q < 2; q++)
+        for (int o = 0; o < 2; o++)
+            if (q || o) {
+                csv_shape sh = base2;
+                sh.use_queue = q;
+                sh.lpt_order = o;
+                consider(sh);
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2678,7 +2836,8 @@ int csv_pool_last_error(csv_pool *p, int *code, uint32_t *brick_id) {
     int h[2] = {0, 0};
     if (hipDeviceSynchronize() != hipSuccess) return CSV_EHIP;
     if (hipMemcpy(h, p->d_err, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return CSV_EHIP;
-    if (hipMemset(p->d_err, 0, sizeof(h)) != hipSuccess) return CSV_EHIP;
+    // cleared before any later work on any stream can report into it
+    if (hipMemset(p->d_err, 0, sizeof(h)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CSV_EHIP;
     *code = h[0];
     if (brick_id) *brick_id = (uint32_t)h[1];
     return CSV_OK;

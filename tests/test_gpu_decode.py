@@ -224,11 +224,11 @@ def cfg2(orc):
     return vol, orc.encode_volume(vol, scale_bits=10, lane_k=64)
 
 
-def test_config2_full_lod_one_launch(csvlib, orc, cfg2):
+def test_config2_full_lod(csvlib, orc, cfg2):
     vol, blob = cfg2
     pool = csvlib.Pool()
     pool.add_volume(blob)
-    log("cfg2 full LOD, 4096 bricks, one launch")
+    log("cfg2 full LOD, 4096 bricks")
     got = gpu_decode_uniform(pool, np.arange(4096), 0)
     want = orc.decode_bricks(blob, np.arange(4096), [0] * 4096)
     np.testing.assert_array_equal(got, want)
@@ -278,6 +278,43 @@ def test_launch_shapes_agree(csvlib, orc, cfg2, shape):
     assert pool.last_error() == (0, 0)
     want = orc.decode_bricks(blob, ids, [0] * len(ids))
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
+
+
+@pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (16, 3, 0, 0, 2), (8, 2, 1, 1, 4), (16, 4, 0, 0, 8)])
+def test_pipelined_chunks_agree(csvlib, orc, cfg1, cfg2, shape):
+    # the requests split into chunks that alternate between the caller's
+    # stream and the pool's second stream: mixed LODs over two volumes with
+    # per-request offsets and statuses (one unknown id late in the batch),
+    # then every brick of the cells volume at full LOD packed back to back
+    torch = torch_cuda()
+    pool = csvlib.Pool()
+    pool.add_volume(cfg1[1])
+    pool.add_volume(cfg2[1])
+    ids, lods = mixed_requests(23, 9000, 8 + 4096)
+    ids[8500] = 10 ** 6
+    off, tot = csvlib.output_offsets(lods)
+    want = np.concatenate([np.zeros((32 >> int(t)) ** 3, np.uint32) if i >= 8 + 4096 else
+                           orc.decode_brick(cfg1[1], int(i), int(t)).ravel() if i < 8 else
+                           orc.decode_brick(cfg2[1], int(i) - 8, int(t)).ravel() for i, t in zip(ids, lods)])
+    out = torch.full((tot,), -1, dtype=torch.int32, device="cuda")
+    status = torch.zeros(len(ids), dtype=torch.int32, device="cuda")
+    log("pipelined mixed %s" % (shape,))
+    pool.set_shape(shape)
+    pool.decode(torch.from_numpy(ids.view(np.int32)).cuda(), out, lods=torch.from_numpy(lods.copy()).cuda(),
+                out_offsets=torch.from_numpy(off.view(np.int64)).cuda(), status=status)
+    torch.cuda.synchronize()
+    assert pool.last_error() == (csvlib.CSV_ERANGE, 8500)
+    st = status.cpu().numpy()
+    assert st[8500] == csvlib.CSV_ERANGE and np.count_nonzero(st) == 1
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
+    log("pipelined full LOD %s" % (shape,))
+    d_ids = torch.arange(8, 8 + 4096, dtype=torch.int32, device="cuda")
+    out = torch.full((4096 * 32768,), -1, dtype=torch.int32, device="cuda")
+    pool.decode(d_ids, out, lod=0)
+    torch.cuda.synchronize()
+    assert pool.last_error() == (0, 0)
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32),
+                                  orc.decode_bricks(cfg2[1], np.arange(4096), [0] * 4096))
 
 
 def mixed_requests(seed, n, n_bricks):
