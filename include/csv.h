@@ -348,11 +348,33 @@ int csv_bricks_visible(const csv_pool *pool, const uint32_t *brick_ids, uint32_t
  * order, min(4, n / 2048) chunks), then the chunk count {1, 2, 4, 8}, then
  * work counters and longest-first order; one warm-up and `reps` timed
  * launches each (HIP events on `stream`).  Makes the fastest the pool's
- * shape and returns it in *best (may be NULL).  Synchronous.  Not allowed
- * while `stream` is being captured. */
+ * shape and the tuned shape of this request set's class (below), and
+ * returns it in *best (may be NULL).  Synchronous.  Not allowed while
+ * `stream` is being captured. */
 int csv_autotune(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods, uint32_t lod_scalar,
                  const uint64_t *out_offsets, uint32_t n, uint32_t *out, void *stream, uint32_t reps,
                  csv_shape *best);
+
+/* Tuned shapes are kept per class of request set: the bit length of n,
+ * how the levels of detail are given (all full LOD; all one coarser LOD;
+ * per request) and the bit length of the pool's mean record size.
+ * csv_decode_bricks, _status and _noalloc use the shape tuned for the
+ * class of their request set (else the tuned class of the same kind and
+ * record size with the nearest n, else the pool's shape).
+ * csv_pool_tuning_save writes them to a text file: a first line
+ * "csv-tuning 1 <device architecture name> <compute units>", then one line
+ * per class "<n bits> <lod kind> <record bits> <waves> <groups> <queue>
+ * <lpt> <chunks> <ms>".  csv_pool_tuning_load adds the classes of such a
+ * file to the pool when the device name and compute-unit count match the
+ * pool's device (else none; *n_loaded, may be NULL, is the number added).
+ * CSV_EINVAL if the file cannot be opened, CSV_ECORRUPT if it is malformed
+ * (nothing is added then). */
+int csv_pool_tuning_save(const csv_pool *pool, const char *path);
+/* The shape a decode of n requests would use (lods: only whether it is NULL
+ * matters; lod_scalar when it is). */
+int csv_pool_shape_for(const csv_pool *pool, const uint8_t *lods, uint32_t lod_scalar, uint32_t n,
+                       csv_shape *shape);
+int csv_pool_tuning_load(csv_pool *pool, const char *path, uint32_t *n_loaded);
 
 /* A decode captured once into a HIP graph and replayed.  The graph holds
  * the pointers and n given here and the pool's shape at creation; replays

@@ -14,6 +14,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsv.so")
+# launch shapes tuned on an MI355X (csv_pool_tuning_load)
+TUNING_PATH = os.path.join(HERE, "tuning_gfx950.txt")
 BRICK = 32
 MAX_LOD = 5
 
@@ -125,6 +127,9 @@ def lib():
         L.csv_decode_bricks_noalloc.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
         L.csv_decode_bricks_shaped.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(Shape)]
         L.csv_pool_set_shape.argtypes = [vp, ctypes.POINTER(Shape)]
+        L.csv_pool_tuning_save.argtypes = [vp, ctypes.c_char_p]
+        L.csv_pool_shape_for.argtypes = [vp, vp, u32, u32, ctypes.POINTER(Shape)]
+        L.csv_pool_tuning_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(u32)]
         L.csv_pool_get_shape.argtypes = [vp, ctypes.POINTER(Shape)]
         L.csv_bricks_visible.argtypes = [vp, vp, u32, vp, u32, vp, vp]
         L.csv_autotune.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, u32, ctypes.POINTER(Shape)]
@@ -358,6 +363,25 @@ class Pool:
         _chk(lib().csv_autotune(*self._args(ids, out, lods, lod, out_offsets, stream), reps, ctypes.byref(sh)),
              "csv_autotune")
         return sh.as_tuple(), sh.ms
+
+    def shape_for(self, n: int, lod: int = 0, per_request_lods: bool = False):
+        """The launch shape a decode of n requests would use."""
+        sh = Shape()
+        _chk(lib().csv_pool_shape_for(self._p, ctypes.c_void_p(1 if per_request_lods else 0), lod, n,
+                                      ctypes.byref(sh)), "csv_pool_shape_for")
+        return sh.as_tuple()
+
+    def save_tuning(self, path: str) -> None:
+        """Write the pool's tuned shapes (by request-set class) to a text file."""
+        _chk(lib().csv_pool_tuning_save(self._p, os.fsencode(path)), "csv_pool_tuning_save")
+
+    def load_tuning(self, path: str = None) -> int:
+        """Add the tuned shapes of a file made on the same kind of device
+        (default: the file shipped for gfx950); returns how many were added."""
+        got = ctypes.c_uint32(0)
+        _chk(lib().csv_pool_tuning_load(self._p, os.fsencode(path or TUNING_PATH), ctypes.byref(got)),
+             "csv_pool_tuning_load")
+        return int(got.value)
 
     def graph(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None):
         """Capture this decode into a replayable HIP graph."""

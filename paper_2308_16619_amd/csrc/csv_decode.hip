@@ -35,7 +35,9 @@
 #include <atomic>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <type_traits>
@@ -1787,7 +1789,9 @@ struct csv_pool {
     bool any_big_palette = false;
     uint64_t hbm_budget = 0;                  // HBM the pool may hold (0: no limit)
     uint32_t generation = 0;                  // bumped when device tables move
-    csv_shape shape{16, 3, 0, 0, 4, 0.f};     // launch shape of csv_decode_bricks
+    csv_shape shape{16, 3, 0, 0, 4, 0.f};     // launch shape of csv_decode_bricks (untuned classes)
+    std::map<uint32_t, csv_shape> tuned;      // autotuned shapes by request-set class (tune_key)
+    char device_name[64] = {0};
     uint64_t record_bytes = 0;
     // level-0 detail in host memory (csv_pool_add_volume_ex, CSV_DETAIL_HOST)
     bool any_split = false;
@@ -2195,6 +2199,39 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
     return rc;
 }
 
+// Class of a request set, the key of the tuned shapes: bits 0..7 the bit
+// length of n, bits 8..15 how its levels of detail are given (0: all full
+// LOD, 1: all one coarser LOD, 2: per request), bits 16..23 the bit length
+// of the pool's mean record size.
+uint32_t tune_key(const csv_pool *p, const uint8_t *lods, uint32_t lod_scalar, uint32_t n) {
+    const uint32_t nb = n ? 32u - (uint32_t)__builtin_clz(n) : 0u;
+    const uint32_t lc = lods ? 2u : (lod_scalar == 0 ? 0u : 1u);
+    const uint64_t nr = std::max<uint64_t>(1, p->rec_ptr.size());
+    const uint64_t mean = std::max<uint64_t>(1, p->record_bytes / nr);
+    const uint32_t rb = 64u - (uint32_t)__builtin_clzll(mean);
+    return nb | (lc << 8) | (rb << 16);
+}
+// The shape for a request set: the tuned one of its class, else of the
+// class with the same level-of-detail kind and record size and the nearest
+// n, else the pool's shape.  pool->mu held.
+csv_shape shape_for(const csv_pool *p, const uint8_t *lods, uint32_t lod_scalar, uint32_t n) {
+    if (p->tuned.empty()) return p->shape;
+    const uint32_t key = tune_key(p, lods, lod_scalar, n);
+    const auto it = p->tuned.find(key);
+    if (it != p->tuned.end()) return it->second;
+    const csv_shape *best = nullptr;
+    uint32_t dist = 0xFFFFFFFFu;
+    for (const auto &e : p->tuned)
+        if ((e.first & 0xFFFF00u) == (key & 0xFFFF00u)) {
+            const uint32_t a = e.first & 0xFFu, b = key & 0xFFu, d = a > b ? a - b : b - a;
+            if (d < dist) {
+                dist = d;
+                best = &e.second;
+            }
+        }
+    return best ? *best : p->shape;
+}
+
 bool valid_shape(const csv_shape &sh) {
     return (sh.waves_per_group == 4 || sh.waves_per_group == 8 || sh.waves_per_group == 16) &&
            sh.groups_per_cu >= 1 && sh.groups_per_cu <= kMaxGroupsB && sh.chunks >= 1 && sh.chunks <= 64;
@@ -2220,6 +2257,9 @@ int csv_pool_create_budget(csv_pool **pool, int device, uint64_t hbm_budget_byte
         return CSV_EHIP;
     }
     p->n_cu = prop.multiProcessorCount;
+    std::snprintf(p->device_name, sizeof(p->device_name), "%s", prop.gcnArchName);
+    for (char *c = p->device_name; *c; c++)
+        if (*c == ' ' || *c == '\t' || *c == '\n') *c = '_';
     p->hbm_budget = hbm_budget_bytes;
     uint8_t *scr = nullptr;  // set-up of this device's scratch address
     if (scratch_address(device, &scr) != CSV_OK) {
@@ -2562,10 +2602,17 @@ int csv_output_bytes(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, ui
     return CSV_OK;
 }
 
+// the launch shape a decode of these requests uses
+csv_shape current_shape(const csv_pool *pool, const uint8_t *lods, uint32_t lod_scalar, uint32_t n) {
+    csv_pool *p = const_cast<csv_pool *>(pool);
+    std::lock_guard<std::mutex> lk(p->mu);
+    return shape_for(p, lods, lod_scalar, n);
+}
+
 int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
                              const uint64_t *out_off, uint32_t n, uint32_t *out, void *stream, int32_t *status) {
     if (!pool || (n && !status)) return CSV_EINVAL;
-    const csv_shape sh = pool->shape;
+    const csv_shape sh = current_shape(pool, lods, lod_scalar, n);
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr,
                   nullptr, status, sh.chunks);
@@ -2574,7 +2621,7 @@ int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *ids, const ui
 int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
                       const uint64_t *out_off, uint32_t n, uint32_t *out, void *stream) {
     if (!pool) return CSV_EINVAL;
-    const csv_shape sh = pool->shape;
+    const csv_shape sh = current_shape(pool, lods, lod_scalar, n);
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr,
                   nullptr, nullptr, sh.chunks);
@@ -2598,7 +2645,7 @@ int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const u
         std::lock_guard<std::mutex> lk(p->mu);
         if (p->rec_ptr.empty() || !p->d_err) return CSV_EINVAL;
         v.slot_dw = slot_dw(p);
-        sh = p->shape;
+        sh = shape_for(p, lods, lod_scalar, n);
     }
     // requests per launch pair: after the counters and arenas, 4 bytes of
     // order list and two 48-byte leaf descriptors plus one slot each (the
@@ -2739,8 +2786,77 @@ int csv_autotune(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint3
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    pool->shape = win;
+    {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        pool->shape = win;
+        pool->tuned[tune_key(pool, lods, lod_scalar, n)] = win;
+    }
     if (best) *best = win;
+    return CSV_OK;
+}
+
+int csv_pool_shape_for(const csv_pool *pool, const uint8_t *lods, uint32_t lod_scalar, uint32_t n,
+                       csv_shape *shape) {
+    if (!pool || !shape) return CSV_EINVAL;
+    *shape = current_shape(pool, lods, lod_scalar, n);
+    return CSV_OK;
+}
+
+int csv_pool_tuning_save(const csv_pool *pool, const char *path) {
+    if (!pool || !path) return CSV_EINVAL;
+    csv_pool *p = const_cast<csv_pool *>(pool);
+    std::lock_guard<std::mutex> lk(p->mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return CSV_EINVAL;
+    bool ok = std::fprintf(f, "csv-tuning 1 %s %d\n", p->device_name, p->n_cu) > 0;
+    for (const auto &e : p->tuned) {
+        const csv_shape &sh = e.second;
+        ok = ok && std::fprintf(f, "%u %u %u %d %u %d %d %u %.4f\n", e.first & 0xFFu, (e.first >> 8) & 0xFFu,
+                                (e.first >> 16) & 0xFFu, sh.waves_per_group, sh.groups_per_cu, sh.use_queue,
+                                sh.lpt_order, sh.chunks, (double)sh.ms) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? CSV_OK : CSV_EINVAL;
+}
+
+int csv_pool_tuning_load(csv_pool *pool, const char *path, uint32_t *n_loaded) {
+    if (!pool || !path) return CSV_EINVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return CSV_EINVAL;
+    char name[64] = {0};
+    int ver = 0, cu = 0;
+    std::map<uint32_t, csv_shape> got;
+    int rc = CSV_OK;
+    if (std::fscanf(f, "csv-tuning %d %63s %d", &ver, name, &cu) != 3 || ver != 1) {
+        rc = CSV_ECORRUPT;
+    } else {
+        unsigned nb, lc, rb, groups, chunks;
+        int waves, queue, lpt;
+        double ms;
+        while (std::fscanf(f, "%u %u %u %d %u %d %d %u %lf", &nb, &lc, &rb, &waves, &groups, &queue, &lpt, &chunks,
+                           &ms) == 9) {
+            const csv_shape sh{waves, groups, queue, lpt, chunks, (float)ms};
+            if (nb > 255 || lc > 2 || rb > 255 || !valid_shape(sh)) {
+                rc = CSV_ECORRUPT;
+                break;
+            }
+            got[nb | (lc << 8) | (rb << 16)] = sh;
+        }
+        if (rc == CSV_OK && !std::feof(f)) rc = CSV_ECORRUPT;
+    }
+    std::fclose(f);
+    if (rc) return rc;
+    uint32_t k = 0;
+    {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        // shapes tuned on another kind of device, or another CU count, do not apply
+        if (std::strcmp(name, pool->device_name) == 0 && cu == pool->n_cu)
+            for (const auto &e : got) {
+                pool->tuned[e.first] = e.second;
+                k++;
+            }
+    }
+    if (n_loaded) *n_loaded = k;
     return CSV_OK;
 }
 

@@ -353,6 +353,41 @@ def test_longest_first_order_and_autotune(csvlib, orc, cfg1, cfg2):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
 
 
+def test_tuning_file_round_trip(csvlib, orc, cfg1, cfg2, tmp_path):
+    # a tuned class written to a file and read into a fresh pool; that
+    # pool's decode of the same class uses it and gives the oracle's bytes;
+    # a file from another device adds nothing, a malformed one is refused
+    torch = torch_cuda()
+    pool = csvlib.Pool()
+    pool.add_volume(cfg2[1])
+    ids = np.arange(0, 4096, 2, dtype=np.uint32)
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    out = torch.full((len(ids) * 32768,), -1, dtype=torch.int32, device="cuda")
+    log("tuning save / load")
+    shape, _ = pool.autotune(d_ids, out, lod=0, reps=1)
+    path = str(tmp_path / "tuning.txt")
+    pool.save_tuning(path)
+    lines = open(path).read().splitlines()
+    assert lines[0].startswith("csv-tuning 1 ") and len(lines) == 2
+    fresh = csvlib.Pool()
+    fresh.add_volume(cfg2[1])
+    assert fresh.load_tuning(path) == 1
+    out.fill_(-1)
+    fresh.decode(d_ids, out, lod=0)
+    torch.cuda.synchronize()
+    assert fresh.last_error() == (0, 0)
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), orc.decode_bricks(cfg2[1], ids, [0] * len(ids)))
+    other = str(tmp_path / "other.txt")
+    head = lines[0].split()
+    open(other, "w").write("csv-tuning 1 some-other-gpu %s\n%s\n" % (head[3], lines[1]))
+    assert fresh.load_tuning(other) == 0
+    bad = str(tmp_path / "bad.txt")
+    open(bad, "w").write(lines[0] + "\n12 7 11 16 3 0 0 4 1.0\n")
+    with pytest.raises(csvlib.CsvError) as e:
+        fresh.load_tuning(bad)
+    assert e.value.code == csvlib.CSV_ECORRUPT
+
+
 @pytest.mark.parametrize("shape", [(16, 4, 1, 0), (8, 5, 1, 1)])
 def test_graph_replays(csvlib, orc, cfg2, shape):
     # a captured decode replayed several times, with eager work and
