@@ -165,6 +165,8 @@ def serving_leg(csv, synth, seconds):
     del vol
     pool = csv.Pool(0)
     pool.add_volume(blob)
+    if os.path.exists(csv.TUNING_PATH):
+        pool.load_tuning()
     log("pool: %d bytes compressed (%.3f%% of %d)" % (len(blob), 100.0 * len(blob) / raw, raw))
     runs = []
     for rate in (1e6, 5e6):
@@ -318,6 +320,21 @@ def encoder_leg(csv, torch, vol, blob, host_s, host_threads, reps=3):
             "identical_bytes": True, "raw_bytes": raw, "compressed_bytes": len(blob)}
 
 
+def write_tuning(pools, path):
+    """One tuning file with the classes of several pools (later pools win)."""
+    import tempfile
+    head, lines = None, {}
+    for p in pools:
+        with tempfile.NamedTemporaryFile("r", suffix=".txt") as f:
+            p.save_tuning(f.name)
+            rows = open(f.name).read().splitlines()
+        head = head or rows[0]
+        for r in rows[1:]:
+            lines[tuple(r.split()[:3])] = r
+    with open(path, "w") as f:
+        f.write("\n".join([head] + [lines[k] for k in sorted(lines)]) + "\n")
+
+
 def config4_requests(n=16384, seed=5):
     """16,384 requests over three volumes (64^3 Voronoi, 512^3 cells, 512^3
     smooth blobs): source uniform, brick uniform within it, LOD uniform in
@@ -344,7 +361,11 @@ def main():
                     help="detail-separation leg (the 512^3 cells volume with level-0 detail in host memory)")
     ap.add_argument("--encoder", choices=["full", "none"], default="full",
                     help="GPU compressor leg (the 512^3 cells volume compressed on the device)")
-    ap.add_argument("--shape", default="", help="fixed launch shape 'waves,groups,queue,lpt' instead of the autotuner")
+    ap.add_argument("--shape", default="", help="fixed launch shape 'waves,groups,queue,lpt,chunks' instead of the "
+                                                 "tuned shapes")
+    ap.add_argument("--retune", action="store_true",
+                    help="sweep launch shapes on every workload instead of loading the shipped tuning file")
+    ap.add_argument("--tuning-out", default="", help="write the tuned shapes of every workload to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -363,14 +384,23 @@ def main():
     headline_only = args.legs == "headline"
     fixed = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
 
+    tuned_pools = []
+
     def pick_shape(pool, ids, out, **kw):
-        """The launch shape: fixed by --shape, else the autotuner's on this request set."""
+        """The launch shape: fixed by --shape; else the shipped tuning file's
+        shape for this request set's class (no sweep); else the autotuner's
+        on this request set."""
         if fixed:
             pool.set_shape(fixed)
             return fixed, None
+        if not args.retune and os.path.exists(csv.TUNING_PATH) and pool.load_tuning() > 0:
+            shape, ms = pool.shape_for(int(ids.numel()), kw.get("lod", 0), kw.get("lods") is not None, with_ms=True)
+            if ms > 0:  # a tuned class (the pool's untuned default has no time)
+                return shape, "tuning file"
         shape, tune_ms = pool.autotune(ids, out, reps=3, **kw)
         torch.cuda.synchronize()
         assert pool.last_error()[0] == 0
+        tuned_pools.append(pool)
         return shape, tune_ms
 
     # ---- headline: the 1024^3 neurite volume, every brick at full LOD ----
@@ -610,7 +640,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "traffic_shape": list(TRAFFIC["shape"]) if traffic is not None else None,
                      "traffic_unit": "bytes per decode call", "algorithmic_bytes_per_launch": in3_bytes + out3_bytes,
-                     "kernel": "csv_decode_bricks = front_kernel + leaf_kernel", "shape": list(shape3),
+                     "kernel": "csv_decode_bricks: per chunk of requests front_kernel then leaf_kernel, "
+                               "chunks alternating between two streams", "shape": list(shape3),
                      "decoder_sha256_16": src_hash},
         "paper_context": {"gbs": PAPER_GBS, "hardware": "NVIDIA RTX 3070 Ti (Table 3; decoded bytes)"},
         "extra_workloads": extra,
@@ -621,6 +652,9 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
     }
+    if args.tuning_out and tuned_pools:
+        write_tuning(tuned_pools, args.tuning_out)
+        log("tuned shapes written to %s" % args.tuning_out)
     print(json.dumps(res), flush=True)
 
 
