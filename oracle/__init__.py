@@ -102,7 +102,8 @@ def set_threads(n: int) -> None:
 def encode_volume(vol: np.ndarray, brick_log2: int = 5, scale_bits: int = 12, lane_k: int = 256,
                   lane_max: int = 64, sample_stride: int = 0, return_hist: bool = False, tables: int = 2):
     """Encode a (nz, ny, nx) uint32 volume; returns the container bytes.
-    tables: 2 frequency tables (levels >= 1, L_0) or 1 for all symbols."""
+    tables: 2 frequency tables (levels >= 1, L_0), 1 for all symbols, or 0
+    for no entropy coding (raw nibbles)."""
     vol = np.ascontiguousarray(vol, dtype=np.uint32)
     nz, ny, nx = vol.shape
     blob = ctypes.c_void_p()

@@ -49,6 +49,12 @@
  *       one word stream that the decoder reads in symbol order.
  *   R10 Frequency tables: every nibble value gets count + 1, scaled to the
  *       table total and corrected to sum exactly to it.
+ *   R11 Table 1's variant without rANS: the same symbol stream stored as
+ *       raw nibbles, symbol i in bits 4(i mod 4) .. 4(i mod 4) + 3 of
+ *       16-bit word i / 4, the unused high nibbles of the last word zero.
+ *       The header's coding field (the first reserved word) is 1, the
+ *       record has no states (W = 0), and its two frequency tables are
+ *       uniform (unused).
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -464,6 +470,27 @@ static void extract_brick(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_
 
 typedef struct { uint8_t *bytes; uint32_t size; } rec_buf;
 
+/* a record whose symbols are stored as raw nibbles (R11) */
+static int build_record_raw(const brick_stream *s, int N, rec_buf *r) {
+    uint32_t nw = (s->n + 3) / 4;
+    uint32_t hdr = 3 + (uint32_t)N;
+    uint32_t size = 4 * (hdr + s->pal.np) + 2 * nw;
+    size = (size + 3) & ~3u;
+    uint8_t *b = (uint8_t *)calloc(size, 1);
+    if (!b) return ORC_ENOMEM;
+    uint32_t *w = (uint32_t *)b;
+    w[0] = s->pal.np;
+    w[1] = 0;
+    w[2] = nw;
+    for (int m = 0; m < N; m++) w[3 + m] = s->cum[m];
+    memcpy(w + hdr, s->pal.pal, 4 * s->pal.np);
+    uint16_t *words = (uint16_t *)(b + 4 * (hdr + s->pal.np));
+    for (uint32_t i = 0; i < s->n; i++) words[i / 4] |= (uint16_t)(s->sym[i] << (4 * (i % 4)));
+    r->bytes = b;
+    r->size = size;
+    return ORC_OK;
+}
+
 static int build_record(const brick_stream *s, int N, const rans_tables *t, uint32_t K, uint32_t Wmax, rec_buf *r) {
     uint32_t W = lane_count(s->n, K, Wmax);
     uint32_t states[64];
@@ -520,7 +547,9 @@ uint32_t orc_abi_version(void) { return 1; }
  * sample_stride 0 means: every 512th brick, every 4096th above 2^20
  * bricks (Sec. 3.4).  tables 2: one frequency table for the symbols of
  * levels >= 1 and one for L_0 (the paper's default); 1: a single table
- * from the counts of all symbols, stored twice (Table 1's variant).
+ * from the counts of all symbols, stored twice (Table 1's variant); 0: no
+ * entropy coding, the symbols stored as raw nibbles (R11; Table 1's
+ * variant without rANS).
  */
 int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz, uint32_t brick_log2,
                       uint32_t scale_bits, uint32_t lane_k, uint32_t lane_max, uint32_t sample_stride,
@@ -528,8 +557,9 @@ int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz
     if (!vol || !blob_out || !blob_bytes) return ORC_EINVAL;
     if (brick_log2 < 1 || brick_log2 > MAX_LOG2 || scale_bits < 8 || scale_bits > 12 || lane_k < 1 ||
         lane_max < 1 || lane_max > 64 || (lane_max & (lane_max - 1)) || nx == 0 || ny == 0 || nz == 0 ||
-        (tables != 1 && tables != 2))
+        tables > 2)
         return ORC_EINVAL;
+    const int raw = tables == 0;
     int N = (int)brick_log2;
     uint32_t b = 1u << N;
     uint32_t nbx = (nx + b - 1) / b, nby = (ny + b - 1) / b, nbz = (nz + b - 1) / b;
@@ -566,6 +596,8 @@ int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz
     uint32_t f[2][16];
     if (tables == 1)
         for (int q = 0; q < 16; q++) cnt[0][q] = cnt[1][q] = cnt[0][q] + cnt[1][q];
+    if (raw) /* uniform, unused */
+        for (int q = 0; q < 16; q++) cnt[0][q] = cnt[1][q] = 0;
     normalize_table(cnt[0], 1u << scale_bits, f[0]);
     normalize_table(cnt[1], 1u << scale_bits, f[1]);
     rans_tables t;
@@ -583,7 +615,7 @@ int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz
             extract_brick(vol, nx, ny, nz, (uint32_t)(id % nbx), (uint32_t)((id / nbx) % nby),
                           (uint32_t)(id / ((uint64_t)nbx * nby)), N, brick);
             int r = encode_brick_stream(brick, N, &s);
-            if (!r) r = build_record(&s, N, &t, lane_k, lane_max, &recs[id]);
+            if (!r) r = raw ? build_record_raw(&s, N, &recs[id]) : build_record(&s, N, &t, lane_k, lane_max, &recs[id]);
             for (int q = 0; q < 8; q++) lh[q] += s.op_hist[q];
             bs_free(&s);
             if (r) {
@@ -608,6 +640,7 @@ int orc_encode_volume(const uint32_t *vol, uint32_t nx, uint32_t ny, uint32_t nz
         h.magic = CSV_MAGIC; h.version = 1; h.nx = nx; h.ny = ny; h.nz = nz; h.brick_log2 = brick_log2;
         h.nbx = nbx; h.nby = nby; h.nbz = nbz; h.n_bricks = (uint32_t)B; h.scale_bits = scale_bits;
         h.lane_k = lane_k; h.lane_max = lane_max; h.sample_stride = sample_stride;
+        h.reserved0 = raw ? 1u : 0u; /* coding (R11) */
         for (int k = 0; k < 2; k++) for (int q = 0; q < 16; q++) h.freq[k][q] = (uint16_t)f[k][q];
         memcpy(blob, &h, sizeof(h));
         uint64_t *index = (uint64_t *)(blob + HDR_BYTES);
@@ -641,7 +674,8 @@ static int open_volume(const uint8_t *blob, uint64_t bytes, vol_view *v) {
     if (!blob || bytes < HDR_BYTES) return ORC_EINVAL;
     memcpy(&v->h, blob, sizeof(vol_header));
     if (v->h.magic != CSV_MAGIC || v->h.version != 1) return ORC_ECORRUPT;
-    if (v->h.brick_log2 < 1 || v->h.brick_log2 > MAX_LOG2 || v->h.scale_bits < 8 || v->h.scale_bits > 12)
+    if (v->h.brick_log2 < 1 || v->h.brick_log2 > MAX_LOG2 || v->h.scale_bits < 8 || v->h.scale_bits > 12 ||
+        v->h.reserved0 > 1)
         return ORC_ECORRUPT;
     uint64_t B = v->h.n_bricks;
     uint64_t rec_start = (HDR_BYTES + 8 * (B + 1) + 15) & ~15ull;
@@ -683,8 +717,11 @@ static int decode_one(const vol_view *v, uint32_t id, uint32_t t, uint32_t *out,
     uint32_t cum[MAX_LOG2];
     for (int m = 0; m < N; m++) cum[m] = w[3 + m];
     for (int m = 0; m + 1 < N; m++) if (cum[m] < cum[m + 1]) return ORC_ECORRUPT;
-    if (P == 0 || W > 64 || (W & (W - 1)) || (cum[0] > 0) != (W > 0)) return ORC_ECORRUPT;
-    if ((uint64_t)4 * (hdr + P + W) + 2ull * nw > size) return ORC_ECORRUPT;
+    const int raw = v->h.reserved0 == 1; /* R11 */
+    if (raw ? (W != 0 || nw != (cum[0] + 3) / 4)
+            : (P == 0 || W > 64 || (W & (W - 1)) || (cum[0] > 0) != (W > 0)))
+        return ORC_ECORRUPT;
+    if (P == 0 || (uint64_t)4 * (hdr + P + W) + 2ull * nw > size) return ORC_ECORRUPT;
     const uint32_t *pal = w + hdr;
     uint32_t states[64];
     for (uint32_t j = 0; j < W; j++) states[j] = w[hdr + P + j];
@@ -694,8 +731,14 @@ static int decode_one(const vol_view *v, uint32_t id, uint32_t t, uint32_t *out,
     if (!sym) return ORC_ENOMEM;
     uint32_t cursor = 0;
     int rc = ORC_OK;
-    if (n) rc = rans_decode(states, W, words, nw, cum, N, &v->t, n, sym, &cursor);
-    if (!rc && check_end && t == 0 && cum[0]) {
+    if (raw) {
+        for (uint32_t i = 0; i < n; i++) sym[i] = (uint8_t)((words[i / 4] >> (4 * (i % 4))) & 15u);
+        /* a complete decode finds the last word's unused nibbles zero */
+        if (check_end && t == 0 && cum[0] % 4 && (words[nw - 1] >> (4 * (cum[0] % 4))) != 0) rc = ORC_ECORRUPT;
+    } else if (n) {
+        rc = rans_decode(states, W, words, nw, cum, N, &v->t, n, sym, &cursor);
+    }
+    if (!rc && !raw && check_end && t == 0 && cum[0]) {
         /* a complete decode ends in the encoder's initial states with every word read */
         for (uint32_t j = 0; j < W; j++) if (states[j] != RANS_L) rc = ORC_ECORRUPT;
         if (cursor != nw) rc = ORC_ECORRUPT;
