@@ -65,9 +65,15 @@ typedef struct {
     uint32_t tables;        /* rANS frequency tables: 2 = one for the symbols of levels >= 1 and one for L_0
                                (Sec. 3.3); 1 = one table for all symbols (stored twice; Table 1's variant);
                                0 = 2 */
+    uint32_t coding;        /* 0 = interleaved rANS (Sec. 3.3); 1 = no entropy coding (Table 1's "no rANS"
+                               variant): each record holds its symbols as raw nibbles, symbol i in bits
+                               4 (i mod 4) .. + 3 of 16-bit word i / 4 (unused nibbles zero), no states
+                               (W = 0), and the header's coding word (the first reserved word) is 1;
+                               its frequency tables are uniform and unused */
 } csv_encode_opts;
 
-/* Defaults: brick_log2 5, scale_bits 10, lane_k 64, lane_max 64, sample_stride 0, threads 0, tables 2. */
+/* Defaults: brick_log2 5, scale_bits 10, lane_k 64, lane_max 64, sample_stride 0, threads 0, tables 2,
+ * coding 0. */
 void csv_encode_opts_default(csv_encode_opts *o);
 
 /*
@@ -90,7 +96,8 @@ void csv_free(void *p);
  * labels: device memory of `device`, nx*ny*nz uint32, x fastest; the work
  * runs on `stream` (NULL: the null stream) and the call returns when the
  * blob is in host memory (*blob, release with csv_free).  Only 32^3 bricks
- * (opts->brick_log2 5); opts->threads is ignored.  The call keeps its device
+ * (opts->brick_log2 5) and rANS coding (opts->coding 0); opts->threads is
+ * ignored.  The call keeps its device
  * buffers (about 430 KiB per workgroup, 5 workgroups per CU, plus the
  * records and the container) and a pinned host buffer of the container's
  * size for later calls on the same device, until csv_encode_gpu_release;
@@ -109,6 +116,8 @@ typedef struct {
     uint32_t freq[2][16]; /* interior table (children on levels >= 1), leaf table (children on L_0) */
     uint64_t record_bytes; /* sum of all brick records */
     uint64_t blob_bytes;
+    uint32_t coding;       /* 0 interleaved rANS, 1 raw nibbles (csv_encode_opts.coding) */
+    uint32_t reserved;
 } csv_volume_info;
 
 /* Parse and validate a container header (host memory). */
@@ -119,7 +128,8 @@ int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info)
  * device needed): record offsets 4-byte aligned and increasing, each record
  * holding its header; per record P >= 1 (P = 1 exactly when the brick has no
  * symbols), W a power of two <= 64 and zero exactly when there are no
- * symbols, cumulative symbol counts non-increasing from the finest child
+ * symbols (raw coding: W = 0 and exactly ceil(symbols / 4) words),
+ * cumulative symbol counts non-increasing from the finest child
  * level and at most two per node, and header + palette + states + words
  * within the record (sums in 64 bits).  csv_pool_add_volume runs it before
  * anything reaches the device.  Errors: as csv_blob_info, CSV_ECORRUPT

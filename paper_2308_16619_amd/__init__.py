@@ -33,13 +33,14 @@ class CsvError(RuntimeError):
 
 class EncodeOpts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("brick_log2", "scale_bits", "lane_k", "lane_max", "sample_stride",
-                                              "threads", "tables")]
+                                              "threads", "tables", "coding")]
 
 
 class VolumeInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("nx", "ny", "nz", "brick_log2", "nbx", "nby", "nbz", "n_bricks",
                                               "scale_bits", "lane_k", "lane_max", "sample_stride")] + [
-        ("freq", (ctypes.c_uint32 * 16) * 2), ("record_bytes", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64)]
+        ("freq", (ctypes.c_uint32 * 16) * 2), ("record_bytes", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64),
+        ("coding", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Shape(ctypes.Structure):
@@ -172,13 +173,14 @@ def _np_ptr(a):
 
 
 def encode_volume(vol: np.ndarray, brick_log2: int = 5, scale_bits: int = 10, lane_k: int = 64, lane_max: int = 64,
-                  sample_stride: int = 0, threads: int = 0, tables: int = 2) -> bytes:
+                  sample_stride: int = 0, threads: int = 0, tables: int = 2, coding: int = 0) -> bytes:
     """Compress a (nz, ny, nx) uint32 label volume into a container blob
-    (tables: 2 rANS frequency tables, levels >= 1 and L_0, or 1 for all)."""
+    (tables: 2 rANS frequency tables, levels >= 1 and L_0, or 1 for all;
+    coding: 0 interleaved rANS, 1 raw nibbles)."""
     L = lib()
     vol = np.ascontiguousarray(vol, dtype=np.uint32)
     nz, ny, nx = vol.shape
-    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, threads, tables)
+    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, threads, tables, coding)
     p = ctypes.c_void_p()
     n = ctypes.c_size_t()
     _chk(L.csv_encode_volume(_np_ptr(vol), nx, ny, nz, ctypes.byref(o), ctypes.byref(p), ctypes.byref(n)),
@@ -202,7 +204,7 @@ def encode_volume_gpu(vol, brick_log2: int = 5, scale_bits: int = 10, lane_k: in
         raise ValueError("vol must be a 3-d CUDA tensor of 4-byte labels")
     vol = vol.contiguous()
     nz, ny, nx = vol.shape
-    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, 0, tables)
+    o = EncodeOpts(brick_log2, scale_bits, lane_k, lane_max, sample_stride, 0, tables, 0)
     p = ctypes.c_void_p()
     n = ctypes.c_size_t()
     _chk(L.csv_encode_volume_gpu(ctypes.c_void_p(vol.data_ptr()), nx, ny, nz, ctypes.byref(o), vol.device.index or 0,
@@ -364,12 +366,13 @@ class Pool:
              "csv_autotune")
         return sh.as_tuple(), sh.ms
 
-    def shape_for(self, n: int, lod: int = 0, per_request_lods: bool = False):
-        """The launch shape a decode of n requests would use."""
+    def shape_for(self, n: int, lod: int = 0, per_request_lods: bool = False, with_ms: bool = False):
+        """The launch shape a decode of n requests would use (with_ms: also
+        its tuned time per call, 0 for the pool's untuned shape)."""
         sh = Shape()
         _chk(lib().csv_pool_shape_for(self._p, ctypes.c_void_p(1 if per_request_lods else 0), lod, n,
                                       ctypes.byref(sh)), "csv_pool_shape_for")
-        return sh.as_tuple()
+        return (sh.as_tuple(), sh.ms) if with_ms else sh.as_tuple()
 
     def save_tuning(self, path: str) -> None:
         """Write the pool's tuned shapes (by request-set class) to a text file."""

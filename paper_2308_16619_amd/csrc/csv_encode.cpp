@@ -259,6 +259,28 @@ void build_record(const BrickEncoder &e, const Tables &t, uint32_t K, uint32_t W
     for (uint32_t q = 0; q < nw; q++) wd[q] = out[nw - 1 - q];
 }
 
+// No entropy coding: the symbols as raw nibbles, four to a 16-bit word
+// (Table 1's variant without rANS).
+void build_record_raw(const BrickEncoder &e, std::vector<uint8_t> &rec) {
+    const int N = e.g.N;
+    const uint32_t n = (uint32_t)e.sym.size();
+    const uint32_t hdr = record_header_words(N), P = (uint32_t)e.palette.size(), nw = (n + 3) / 4;
+    const size_t size = ((size_t)4 * (hdr + P) + 2 * (size_t)nw + 3) & ~(size_t)3;
+    rec.assign(size, 0);
+    uint32_t *w = reinterpret_cast<uint32_t *>(rec.data());
+    w[0] = P;
+    w[1] = 0;
+    w[2] = nw;
+    for (int m = 0; m < N; m++) w[3 + m] = e.cum[m];
+    std::memcpy(w + hdr, e.palette.data(), 4 * (size_t)P);
+    uint16_t *wd = reinterpret_cast<uint16_t *>(rec.data() + 4 * ((size_t)hdr + P));
+    for (uint32_t q = 0; q < nw; q++) {
+        uint32_t v = 0;
+        for (uint32_t k = 0; k < 4 && 4 * q + k < n; k++) v |= (uint32_t)e.sym[4 * q + k] << (4 * k);
+        wd[q] = (uint16_t)v;
+    }
+}
+
 template <class F>
 void parallel_for(uint64_t n, unsigned threads, F &&fn) {
     std::atomic<uint64_t> next{0};
@@ -308,6 +330,7 @@ void csv_encode_opts_default(csv_encode_opts *o) {
     o->sample_stride = 0;
     o->threads = 0;
     o->tables = 2;
+    o->coding = 0;
 }
 
 void csv_free(void *p) { std::free(p); }
@@ -319,8 +342,10 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
     csv_encode_opts_default(&o);
     if (opts) o = *opts;
     if (o.brick_log2 < 1 || o.brick_log2 > (uint32_t)kMaxLog2 || o.scale_bits < 8 || o.scale_bits > 12 ||
-        o.lane_k < 1 || o.lane_max < 1 || o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)) || o.tables > 2)
+        o.lane_k < 1 || o.lane_max < 1 || o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)) || o.tables > 2 ||
+        o.coding > 1)
         return CSV_EINVAL;
+    const bool raw = o.coding == 1;
     if (o.tables == 0) o.tables = 2;
     try {
         const int N = (int)o.brick_log2;
@@ -332,8 +357,9 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
         unsigned threads = o.threads ? o.threads : std::max(1u, std::thread::hardware_concurrency());
         Geometry geo(N);
 
-        // prepass: nibble histograms of the sampled bricks
-        const uint64_t n_samples = (B + stride - 1) / stride;
+        // prepass: nibble histograms of the sampled bricks (none without rANS:
+        // the header's tables are then uniform)
+        const uint64_t n_samples = raw ? 0 : (B + stride - 1) / stride;
         std::vector<std::vector<uint64_t>> hist(threads, std::vector<uint64_t>(32, 0));
         {
             std::vector<BrickEncoder *> enc(threads, nullptr);
@@ -371,7 +397,10 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
                 e.load(labels, nx, ny, nz, id, nbx, nby);
                 e.build_pyramid();
                 e.encode();
-                build_record(e, t, o.lane_k, o.lane_max, recs[id]);
+                if (raw)
+                    build_record_raw(e, recs[id]);
+                else
+                    build_record(e, t, o.lane_k, o.lane_max, recs[id]);
             });
             for (auto *p : enc) delete p;
         }
@@ -392,6 +421,7 @@ int csv_encode_volume(const uint32_t *labels, uint32_t nx, uint32_t ny, uint32_t
         h.lane_k = o.lane_k;
         h.lane_max = o.lane_max;
         h.sample_stride = stride;
+        h.reserved0 = raw ? 1u : 0u;  // coding
         for (int k = 0; k < 2; k++)
             for (int s = 0; s < 16; s++) h.freq[k][s] = (uint16_t)t.f[k][s];
         std::memcpy(out, &h, sizeof(h));
@@ -417,7 +447,8 @@ int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info)
     VolumeHeader h;
     std::memcpy(&h, blob, sizeof(h));
     if (h.magic != kMagic || h.version != kVersion) return CSV_ECORRUPT;
-    if (h.brick_log2 < 1 || h.brick_log2 > (uint32_t)kMaxLog2 || h.scale_bits < 8 || h.scale_bits > 12)
+    if (h.brick_log2 < 1 || h.brick_log2 > (uint32_t)kMaxLog2 || h.scale_bits < 8 || h.scale_bits > 12 ||
+        h.reserved0 > 1)
         return CSV_ECORRUPT;
     const uint32_t b = 1u << h.brick_log2;
     if (h.nbx != (h.nx + b - 1) / b || h.nby != (h.ny + b - 1) / b || h.nbz != (h.nz + b - 1) / b ||
@@ -448,6 +479,7 @@ int csv_blob_info(const uint8_t *blob, size_t blob_bytes, csv_volume_info *info)
         for (int q = 0; q < 16; q++) info->freq[k][q] = h.freq[k][q];
     info->record_bytes = index[h.n_bricks];
     info->blob_bytes = rs + index[h.n_bricks];
+    info->coding = h.reserved0;
     return CSV_OK;
 }
 
@@ -471,8 +503,10 @@ int csv_blob_check(const uint8_t *blob, size_t blob_bytes, uint32_t *first_bad) 
             const uint64_t P = w[0], W = w[1], nw = w[2];
             uint32_t c[kMaxLog2 + 1] = {};
             for (int m = 0; m < N; m++) c[m] = w[3 + m];
-            ok = P >= 1 && W <= 64 && (W & (W - 1)) == 0 && ((c[0] > 0) == (W > 0)) && c[0] <= max_sym &&
-                 (c[0] == 0 ? P == 1 : P >= 2) && 4 * (hdr + P + W) + 2 * nw <= e - a;
+            const bool shape_ok = info.coding == 1 ? (W == 0 && nw == (c[0] + 3ull) / 4)
+                                                   : (W <= 64 && (W & (W - 1)) == 0 && ((c[0] > 0) == (W > 0)));
+            ok = P >= 1 && shape_ok && c[0] <= max_sym && (c[0] == 0 ? P == 1 : P >= 2) &&
+                 4 * (hdr + P + W) + 2 * nw <= e - a;
             for (int m = 1; ok && m < N; m++) ok = c[m] <= c[m - 1];
         }
         if (!ok) {

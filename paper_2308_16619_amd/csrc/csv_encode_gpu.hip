@@ -672,7 +672,7 @@ extern "C" int csv_encode_volume_gpu(const uint32_t *labels, uint32_t nx, uint32
     csv_encode_opts_default(&o);
     if (opts) o = *opts;
     if (o.brick_log2 != (uint32_t)kN || o.scale_bits < 8 || o.scale_bits > 12 || o.lane_k < 1 || o.lane_max < 1 ||
-        o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)) || o.tables > 2)
+        o.lane_max > 64 || (o.lane_max & (o.lane_max - 1)) || o.tables > 2 || o.coding != 0)
         return CSV_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev || device >= kMaxDevices)

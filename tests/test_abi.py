@@ -81,7 +81,7 @@ def test_strerror():
     assert csv.lib().csv_strerror(-3) == b"corrupt data"
 
 
-@pytest.mark.parametrize("case", ["cfg1", "random", "padded", "bits8", "k1", "b16", "one_table", "one_table_b64"])
+@pytest.mark.parametrize("case", ["cfg1", "random", "padded", "bits8", "k1", "b16", "one_table", "one_table_b64", "raw32", "raw16", "raw64"])
 def test_encoder_bytes_identical_to_oracle(orc, case):
     import paper_2308_16619_amd as csv
     kw = {}
@@ -103,6 +103,14 @@ def test_encoder_bytes_identical_to_oracle(orc, case):
     elif case == "one_table":
         vol = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)
         kw = dict(tables=1)
+    elif case.startswith("raw"):
+        vol = synth.cells(n=64, grid=6, seed=8)
+        N = {"raw32": 5, "raw16": 4, "raw64": 6}[case]
+        mine = csv.encode_volume(vol, brick_log2=N, coding=1)
+        assert csv.blob_info(mine)["coding"] == 1
+        assert csv.blob_check(mine)[0] == 0
+        assert mine == orc.encode_volume(vol, brick_log2=N, scale_bits=10, lane_k=64, tables=0)
+        return
     else:
         vol = synth.voronoi_bg(n=128, sites=300, seed=7)
         kw = dict(tables=1, brick_log2=6)
