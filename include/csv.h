@@ -160,7 +160,14 @@ void csv_pool_destroy(csv_pool *pool);
  * its own copy, so the blob may be freed afterwards.  Its bricks get the
  * global ids first_brick_id .. first_brick_id + n_bricks - 1 (volumes are
  * numbered in the order they are added; each keeps its own table pair).
- * Only 32^3 bricks (brick_log2 5) are accepted; every record is checked
+ * Every volume of a pool has the same brick size (edge 2^brick_log2,
+ * brick_log2 1..6; another size is CSV_EINVAL).  Pools of 32^3 rANS bricks
+ * decode with the tuned kernels; a volume of another brick size or with raw
+ * nibbles (csv_encode_opts.coding 1) makes every decode of the pool take the
+ * generic decoder (one workgroup per brick, levels in global memory; Table
+ * 1's variants), which has no launch shape, no graphs, no
+ * csv_decode_bricks_noalloc, no detail separation, no serving loop and no
+ * frame cache (those return CSV_EINVAL).  Every record is checked
  * first (csv_blob_check).  Synchronous, with no stream argument: the pool's
  * per-brick arrays and decode tables are re-uploaded, so the call waits for
  * every decode on the device that may read the old ones.  Errors:
@@ -212,7 +219,7 @@ typedef struct {
     uint32_t n_volumes, n_bricks;
     uint64_t device_bytes; /* HBM held by the pool */
     int device;
-    int32_t pad;
+    uint32_t brick_log2;   /* brick edge 2^brick_log2 of the pool's volumes (0: no volume yet) */
     uint64_t host_bytes;   /* pinned host memory holding level-0 detail (CSV_DETAIL_HOST volumes) */
 } csv_pool_info;
 int csv_pool_info_get(const csv_pool *pool, csv_pool_info *info);
@@ -226,6 +233,11 @@ int csv_pool_info_get(const csv_pool *pool, csv_pool_info *info);
 int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total);
 /* The same packing in bytes (offsets[i] and *total are 4x the element figures). */
 int csv_output_bytes(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total);
+/* csv_output_elems for bricks of edge 2^brick_log2 (1..6): request i takes
+ * ((2^brick_log2) >> lods_host[i])^3 elements; CSV_ERANGE for a level past
+ * brick_log2. */
+int csv_output_elems_log2(uint32_t brick_log2, const uint8_t *lods_host, uint32_t n, uint64_t *offsets,
+                          uint64_t *total);
 
 /*
  * THE HOT PATH: decode n bricks on the GPU, asynchronously on `stream`.

@@ -87,7 +87,7 @@ class Stats(ctypes.Structure):
 
 class PoolInfo(ctypes.Structure):
     _fields_ = [("n_volumes", ctypes.c_uint32), ("n_bricks", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
-                ("device", ctypes.c_int), ("pad", ctypes.c_int32), ("host_bytes", ctypes.c_uint64)]
+                ("device", ctypes.c_int), ("brick_log2", ctypes.c_uint32), ("host_bytes", ctypes.c_uint64)]
 
 
 def lib():
@@ -122,6 +122,7 @@ def lib():
         L.csv_pool_info_get.argtypes = [vp, ctypes.POINTER(PoolInfo)]
         L.csv_output_elems.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
         L.csv_output_bytes.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
+        L.csv_output_elems_log2.argtypes = [u32, vp, u32, vp, ctypes.POINTER(u64)]
         L.csv_decode_bricks_status.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, vp]
         for f in ("csv_decode_bricks", "csv_decode_bricks_plain"):
             getattr(L, f).argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
@@ -236,12 +237,14 @@ def blob_check(blob: bytes) -> tuple:
     return rc, (bad.value if rc == CSV_ECORRUPT and bad.value != 0xFFFFFFFF else None)
 
 
-def output_offsets(lods) -> tuple:
-    """Element offsets of requests packed back to back, and the total."""
+def output_offsets(lods, brick_log2: int = 5) -> tuple:
+    """Element offsets of requests packed back to back, and the total
+    (bricks of edge 2^brick_log2)."""
     lods = np.ascontiguousarray(lods, dtype=np.uint8)
     off = np.zeros(len(lods), dtype=np.uint64)
     tot = ctypes.c_uint64()
-    _chk(lib().csv_output_elems(_np_ptr(lods), len(lods), _np_ptr(off), ctypes.byref(tot)), "csv_output_elems")
+    _chk(lib().csv_output_elems_log2(brick_log2, _np_ptr(lods), len(lods), _np_ptr(off), ctypes.byref(tot)),
+         "csv_output_elems_log2")
     return off, int(tot.value)
 
 

@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("csv_decode.hip", "csv_encode_gpu.hip", "csv_cache.hip", "csv_encode.cpp", "csv_server.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("csv_decode.hip", "csv_generic.hip", "csv_encode_gpu.hip", "csv_cache.hip", "csv_encode.cpp",
+                                                   "csv_server.cpp")]
 LIB = os.path.join(HERE, "libcsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -206,7 +206,8 @@ int csv_frame_cache_create(csv_pool *pool, uint64_t cache_bytes, uint32_t max_re
     csv_pool_info info;
     int rc = csv_pool_info_get(pool, &info);
     if (rc) return rc;
-    if (info.n_bricks == 0 || (uint64_t)info.n_bricks * kLods >= (1ull << 32)) return CSV_EINVAL;
+    if (info.n_bricks == 0 || info.brick_log2 != 5 || (uint64_t)info.n_bricks * kLods >= (1ull << 32))
+        return CSV_EINVAL;  // blocks of 32^3 bricks
     csv_frame_cache *c = new (std::nothrow) csv_frame_cache;
     if (!c) return CSV_ENOMEM;
     c->pool = pool;

@@ -45,6 +45,7 @@
 
 #include "../../include/csv.h"
 #include "csv_format.hpp"
+#include "csv_generic.hpp"
 
 namespace {
 
@@ -1639,9 +1640,8 @@ __global__ void zero_words(uint32_t *p, uint32_t n) {
 __global__ __launch_bounds__(256) void visible_kernel(const uint64_t *rec_ptr, const uint32_t *rec_size,
                                                       uint32_t n_bricks, const uint32_t *ids, uint32_t n,
                                                       const uint32_t *bits, uint32_t n_bits, uint8_t *out,
-                                                      int *err) {
+                                                      int *err, uint32_t hdr) {
     const uint32_t L = lane(), wave = uniform(threadIdx.x >> 6);
-    const uint32_t hdr = csv::record_header_words(kLog2);
     for (uint32_t r = blockIdx.x * 4 + wave; r < n; r += gridDim.x * 4) {
         const uint32_t id = ld_s(ids + r);
         if (id >= n_bricks) {
@@ -1692,6 +1692,8 @@ struct LaunchBufs {
     bool dirty = false;            // counters left non-zero by a failed launch
     uint32_t slot_dw = 0;
     uint32_t cap_n = 0;
+    uint8_t *gen = nullptr;        // scratch of the decoder for other brick sizes and raw nibbles
+    uint64_t gen_bytes = 0;
     uint32_t slot_bytes() const { return 4 * slot_dw + kSlotExtra; }
     void release() {
         if (owned) {
@@ -1701,7 +1703,10 @@ struct LaunchBufs {
             (void)hipFree(slow_list);
             (void)hipFree(small);
             (void)hipFree(arenas);
+            (void)hipFree(gen);
         }
+        gen = nullptr;
+        gen_bytes = 0;
         slots = nullptr;
         order = nullptr;
         leaf_list = nullptr;
@@ -1746,7 +1751,9 @@ struct LaunchBufs {
     static uint64_t sized(uint32_t cap, uint32_t dw) {
         return (uint64_t)cap * (4ull * dw + kSlotExtra + 4 + 2 * sizeof(LeafDesc)) + 4 * 72;
     }
-    uint64_t bytes() const { return (slots ? sized(cap_n, slot_dw) : 0) + (uint64_t)arena_groups * kArenaBytes; }
+    uint64_t bytes() const {
+        return (slots ? sized(cap_n, slot_dw) : 0) + (uint64_t)arena_groups * kArenaBytes + gen_bytes;
+    }
 };
 constexpr size_t kMaxStreamBufs = 16;
 
@@ -1783,6 +1790,11 @@ struct csv_pool {
     uint32_t *d_bits = nullptr;
     int *d_err = nullptr;
     std::vector<LaunchBufs> bufs;             // per stream, at most kMaxStreamBufs
+    uint32_t brick_log2 = 0;                  // brick edge 2^brick_log2 of every volume (0: none yet)
+    bool generic = false;                     // a volume of another brick size or with raw nibbles:
+                                              // every decode takes the generic decoder
+    std::vector<uint8_t> vol_raw;             // per volume: symbols stored as raw nibbles
+    uint8_t *d_vol_raw = nullptr;
     uint64_t use_clock = 0;
     uint32_t max_c0 = 0;                      // most symbols of any brick in the pool
     uint32_t max_fast_bytes = 0;              // largest LDS arena a brick of the pool needs (nibbles not staged)
@@ -1925,6 +1937,49 @@ int scratch_address(int dev, uint8_t **out) {
     return CSV_OK;
 }
 
+// the buffer set of stream s, taken over from the least recently used
+// stream when all kMaxStreamBufs sets are in use (pool->mu held)
+int find_bufs(csv_pool *pool, hipStream_t s, LaunchBufs **out) {
+    LaunchBufs *b = nullptr;
+    for (auto &e : pool->bufs)
+        if (e.stream == s) b = &e;
+    if (!b) {
+        if (pool->bufs.size() < kMaxStreamBufs) {
+            pool->bufs.emplace_back();
+            b = &pool->bufs.back();
+        } else {
+            if (capturing(s)) return CSV_EBUSY;
+            if (hipDeviceSynchronize() != hipSuccess) return CSV_EHIP;
+            b = &pool->bufs[0];
+            for (auto &e : pool->bufs)
+                if (e.last_use < b->last_use) b = &e;
+        }
+        b->stream = s;
+    }
+    b->last_use = ++pool->use_clock;
+    *out = b;
+    return CSV_OK;
+}
+
+// ... with `bytes` of scratch for the generic decoder (pool->mu held)
+int generic_bufs(csv_pool *pool, hipStream_t s, uint64_t bytes, LaunchBufs **out) {
+    LaunchBufs *b = nullptr;
+    int rc = find_bufs(pool, s, &b);
+    if (rc) return rc;
+    if (b->gen_bytes < bytes) {
+        if (capturing(s)) return CSV_EBUSY;
+        if (b->gen && hipStreamSynchronize(s) != hipSuccess) return CSV_EHIP;
+        if (over_budget(pool, bytes - b->gen_bytes)) return CSV_ENOMEM;
+        (void)hipFree(b->gen);
+        b->gen = nullptr;
+        b->gen_bytes = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&b->gen), bytes) != hipSuccess) return CSV_ENOMEM;
+        b->gen_bytes = bytes;
+    }
+    *out = b;
+    return CSV_OK;
+}
+
 int stream_bufs(csv_pool *pool, hipStream_t s, uint32_t n, LaunchBufs **out) {
     LaunchBufs *b = nullptr;
     for (auto &e : pool->bufs)
@@ -2009,6 +2064,53 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     std::call_once(once_b, [] { attr_b = set_lds_attr(leaf_kernel<kWavesLeaf, false>); });
     if (attr_b != hipSuccess) return CSV_EHIP;
     std::lock_guard<std::mutex> lk(pool->mu);
+    if (pool->generic) {
+        // other brick sizes and raw nibbles: the generic decoder, one
+        // workgroup per brick (no launch shape, no fixed buffers)
+        if (fixed || words_out) return CSV_EINVAL;
+        const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
+        const uint32_t groups = plain ? 1u : std::min(n, 2 * cu);
+        csv::GenericArgs ga{};
+        ga.sym_cap = pool->max_c0 + 16;
+        ga.scratch_per_group = csv::generic_scratch_bytes(pool->brick_log2, ga.sym_cap);
+        LaunchBufs *G = nullptr;
+        const int rc = generic_bufs(pool, s, ga.scratch_per_group * groups, &G);
+        if (rc) return rc;
+        ga.rec_ptr = pool->d_rec_ptr;
+        ga.rec_size = pool->d_rec_size;
+        ga.rec_vol = pool->d_rec_vol;
+        ga.luts = pool->d_luts;
+        ga.lut_off = pool->d_lut_off;
+        ga.vol_bits = pool->d_bits;
+        ga.vol_raw = pool->d_vol_raw;
+        ga.n_bricks = (uint32_t)pool->rec_ptr.size();
+        ga.log2 = pool->brick_log2;
+        ga.ids = ids;
+        ga.lods = lods;
+        ga.lod_scalar = lod_scalar;
+        ga.out_off = out_off;
+        ga.out = out;
+        ga.n = n;
+        ga.err = pool->d_err;
+        ga.req_err = req_err;
+        ga.rq_base = rq_base;
+        ga.scratch = G->gen;
+        if (!plain) return csv::generic_launch(ga, groups, s) == hipSuccess ? CSV_OK : CSV_EHIP;
+        // one launch per brick
+        const uint64_t g1 = (1u << pool->brick_log2) >> (lods ? 0u : lod_scalar);
+        for (uint32_t i = 0; i < n; i++) {
+            csv::GenericArgs gi = ga;
+            gi.ids = ids + i;
+            gi.lods = lods ? lods + i : nullptr;
+            gi.out_off = out_off ? out_off + i : nullptr;
+            gi.out = out_off ? out : out + (uint64_t)i * g1 * g1 * g1;
+            gi.n = 1;
+            gi.req_err = req_err ? req_err + i : nullptr;
+            gi.rq_base = rq_base + i;
+            if (csv::generic_launch(gi, 1, s) != hipSuccess) return CSV_EHIP;
+        }
+        return CSV_OK;
+    }
     LaunchBufs *B = fixed;
     if (!B) {
         const int rc = stream_bufs(pool, s, n, &B);
@@ -2167,6 +2269,7 @@ int launch(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lo
            uint32_t chunks = 1) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     chunks = std::min(chunks, n / kMinChunk);
+    if (pool && pool->generic) chunks = 1;  // the generic decoder runs as one launch
     if (chunks <= 1 || !pool || plain || fixed || words_out || !ids || !out || (lods && !out_off) ||
         (!lods && lod_scalar > (uint32_t)kLog2) || capturing(s))
         return launch_one(pool, ids, lods, lod_scalar, out_off, n, out, stream, plain, waves_a, groups_b, queue,
@@ -2287,6 +2390,7 @@ void csv_pool_destroy(csv_pool *p) {
     (void)hipFree(p->d_luts);
     (void)hipFree(p->d_lut_off);
     (void)hipFree(p->d_bits);
+    (void)hipFree(p->d_vol_raw);
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_pfx_dw);
     (void)hipFree(p->d_sfx);
@@ -2309,7 +2413,11 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     csv_volume_info info;
     int rc = csv_blob_info(blob, blob_bytes, &info);
     if (rc) return rc;
-    if (info.brick_log2 != (uint32_t)kLog2 || info.scale_bits > (uint32_t)kLutMaxBits) return CSV_EINVAL;
+    if (info.scale_bits > (uint32_t)kLutMaxBits || info.coding > 1) return CSV_EINVAL;
+    // one brick size per pool; other sizes and raw nibbles take the generic decoder
+    if (p->brick_log2 && info.brick_log2 != p->brick_log2) return CSV_EINVAL;
+    const bool gen = info.brick_log2 != (uint32_t)kLog2 || info.coding != 0;
+    if (gen && p->any_split) return CSV_EINVAL;  // detail separation needs the 32^3 rANS path
     // every record is checked on the host before anything reaches the device
     if ((rc = csv_blob_check(blob, blob_bytes, nullptr))) return rc;
     if ((uint64_t)p->rec_ptr.size() + info.n_bricks >= (1ull << 32) || p->bits.size() >= 65535) return CSV_ERANGE;
@@ -2321,10 +2429,12 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     bool big = p->any_big_palette;
     for (uint32_t i = 0; i < info.n_bricks; i++) {
         const uint32_t *w = reinterpret_cast<const uint32_t *>(blob + rs + index[i]);
-        const uint32_t P = w[0], c0 = w[3], c1 = w[4];
+        const uint32_t P = w[0], c0 = w[3];
         if (c0 == 0) continue;
-        big |= P > kPalFast;
         max_c0 = std::max(max_c0, c0);
+        if (info.brick_log2 != (uint32_t)kLog2) continue;
+        const uint32_t c1 = w[4];
+        big |= P > kPalFast;
         const uint32_t e1 = std::min((c0 - c1) / 8, 4096u);
         // a brick whose staged nibbles do not fit reads them from its slot
         max_fast = std::max(max_fast, make_layout_l(true, P, 0, e1, 1).total);
@@ -2343,6 +2453,9 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
     p->max_c0 = max_c0;
     p->max_fast_bytes = max_fast;
     p->any_big_palette = big;
+    p->brick_log2 = info.brick_log2;
+    p->generic = p->generic || gen;
+    p->vol_raw.push_back((uint8_t)info.coding);
     p->generation++;
     const uint32_t first = (uint32_t)p->rec_ptr.size();
     const uint16_t vol = (uint16_t)p->bits.size();
@@ -2360,7 +2473,8 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
             for (uint32_t q = 0; q < info.freq[tb][s]; q++) p->luts.push_back(csv::lut_entry(s, q, info.freq[tb][s]));
     if ((rc = upload(&p->d_rec_ptr, p->rec_ptr)) || (rc = upload(&p->d_rec_size, p->rec_size)) ||
         (rc = upload(&p->d_rec_vol, p->rec_vol)) || (rc = upload(&p->d_luts, p->luts)) ||
-        (rc = upload(&p->d_lut_off, p->lut_off)) || (rc = upload(&p->d_bits, p->bits)) || (rc = sync_split(p)))
+        (rc = upload(&p->d_lut_off, p->lut_off)) || (rc = upload(&p->d_bits, p->bits)) ||
+        (rc = upload(&p->d_vol_raw, p->vol_raw)) || (rc = sync_split(p)))
         return rc;
     if (first_brick_id) *first_brick_id = first;
     return CSV_OK;
@@ -2369,6 +2483,12 @@ int csv_pool_add_volume(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uin
 int csv_pool_add_volume_ex(csv_pool *p, const uint8_t *blob, size_t blob_bytes, uint32_t flags,
                            uint32_t *first_brick_id) {
     if (!p || !blob || (flags & ~(uint32_t)CSV_DETAIL_HOST)) return CSV_EINVAL;
+    if (flags & CSV_DETAIL_HOST) {  // detail separation: 32^3 rANS pools only
+        csv_volume_info vi;
+        const int r = csv_blob_info(blob, blob_bytes, &vi);
+        if (r) return r;
+        if (p->generic || vi.brick_log2 != (uint32_t)kLog2 || vi.coding != 0) return CSV_EINVAL;
+    }
     uint32_t first = 0;
     int rc = csv_pool_add_volume(p, blob, blob_bytes, &first);
     if (rc) return rc;
@@ -2575,23 +2695,28 @@ int csv_pool_info_get(const csv_pool *p, csv_pool_info *info) {
     info->n_volumes = (uint32_t)p->bits.size();
     info->n_bricks = (uint32_t)p->rec_ptr.size();
     info->device = p->device;
-    info->pad = 0;
+    info->brick_log2 = p->brick_log2;
     info->device_bytes = pool_device_bytes(p);
     info->host_bytes = p->host_bytes;
     return CSV_OK;
 }
 
-int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total) {
-    if ((n && !lods_host) || !total) return CSV_EINVAL;
+int csv_output_elems_log2(uint32_t brick_log2, const uint8_t *lods_host, uint32_t n, uint64_t *offsets,
+                          uint64_t *total) {
+    if ((n && !lods_host) || !total || brick_log2 < 1 || brick_log2 > (uint32_t)csv::kMaxLog2) return CSV_EINVAL;
     uint64_t o = 0;
     for (uint32_t i = 0; i < n; i++) {
-        if (lods_host[i] > kLog2) return CSV_ERANGE;
+        if (lods_host[i] > brick_log2) return CSV_ERANGE;
         if (offsets) offsets[i] = o;
-        const uint64_t g = 32u >> lods_host[i];
+        const uint64_t g = (1u << brick_log2) >> lods_host[i];
         o += g * g * g;
     }
     *total = o;
     return CSV_OK;
+}
+
+int csv_output_elems(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total) {
+    return csv_output_elems_log2((uint32_t)kLog2, lods_host, n, offsets, total);
 }
 
 int csv_output_bytes(const uint8_t *lods_host, uint32_t n, uint64_t *offsets, uint64_t *total) {
@@ -2643,7 +2768,7 @@ int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const u
     csv_shape sh;
     {
         std::lock_guard<std::mutex> lk(p->mu);
-        if (p->rec_ptr.empty() || !p->d_err) return CSV_EINVAL;
+        if (p->rec_ptr.empty() || !p->d_err || p->generic) return CSV_EINVAL;
         v.slot_dw = slot_dw(p);
         sh = shape_for(p, lods, lod_scalar, n);
     }
@@ -2691,7 +2816,8 @@ int csv_bricks_visible(const csv_pool *pool, const uint32_t *ids, uint32_t n, co
     const uint32_t cu = (uint32_t)std::max(1, p->n_cu);
     const uint32_t grid = std::max(1u, std::min((n + 3) / 4, cu * 8));
     hipLaunchKernelGGL(visible_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, p->d_rec_ptr, p->d_rec_size,
-                       (uint32_t)p->rec_ptr.size(), ids, n, visible_bits, n_label_bits, visible, p->d_err);
+                       (uint32_t)p->rec_ptr.size(), ids, n, visible_bits, n_label_bits, visible, p->d_err,
+                       csv::record_header_words((int)p->brick_log2));
     return hipGetLastError() == hipSuccess ? CSV_OK : CSV_EHIP;
 }
 
@@ -2880,7 +3006,7 @@ static void graph_free(csv_graph *G) {
 
 int csv_graph_create(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
                      const uint64_t *out_off, uint32_t n, uint32_t *out, void *stream, csv_graph **graph) {
-    if (!pool || !graph || !n) return CSV_EINVAL;
+    if (!pool || !graph || !n || pool->generic) return CSV_EINVAL;
     DeviceGuard g(pool->device);
     csv_graph *G = new (std::nothrow) csv_graph;
     if (!G) return CSV_ENOMEM;

@@ -612,7 +612,7 @@ int csv_server_create(csv_pool *pool, const csv_server_opts *o, csv_server **out
     csv_pool_info info;
     int rc = csv_pool_info_get(pool, &info);
     if (rc) return rc;
-    if (info.n_bricks == 0) return CSV_EINVAL;
+    if (info.n_bricks == 0 || info.brick_log2 != 5) return CSV_EINVAL;  // the cache holds 32^3 blocks
     csv_server *s = new (std::nothrow) csv_server;
     if (!s) return CSV_ENOMEM;
     s->pool = pool;

@@ -1,13 +1,10 @@
 """CPU test of the format sweep tool (sizes only): every variant encodes;
-the no-rANS size equals a raw-nibble layout computed from the oracle's
-symbol streams and palettes; more interleaved rANS states cost bytes (each
-state is 4 bytes of record)."""
+the no-rANS container is the oracle's raw-nibble container; more
+interleaved rANS states cost bytes (each state is 4 bytes of record)."""
 import json
 import os
 import subprocess
 import sys
-
-import numpy as np
 
 import synth
 
@@ -27,13 +24,7 @@ def test_format_sweep_ratios(orc):
     by_lanes = {r["lane_max"]: r["compressed_bytes"] for r in rows[9:] if r["scale_bits"] == 10}
     by_lanes[64] = table1[(32, "rANS, 2 tables")]
     assert by_lanes[1] <= by_lanes[4] <= by_lanes[16] <= by_lanes[64]
-    # raw nibbles for 32^3 bricks from the oracle: u32 P, u32 cum[5], palette, nibbles two per byte
+    # the no-rANS containers are the oracle's raw-nibble ones
     vol = synth.cells(n=64, grid=max(2, round(37 * 64 / 512)), seed=2)
-    total = (128 + 8 * 9 + 15) & ~15
-    for bz in range(2):
-        for by in range(2):
-            for bx in range(2):
-                br = np.ascontiguousarray(vol[32 * bz:32 * bz + 32, 32 * by:32 * by + 32, 32 * bx:32 * bx + 32])
-                sym, _, pal = orc.brick_symbols(br)
-                total += 4 * (1 + 5 + len(pal)) + (((len(sym) + 1) // 2 + 3) & ~3)
-    assert table1[(32, "no rANS (raw nibbles)")] == total
+    for log2 in (4, 5, 6):
+        assert table1[(1 << log2, "no rANS (raw nibbles)")] == len(orc.encode_volume(vol, brick_log2=log2, tables=0))
