@@ -513,7 +513,7 @@ static int build_record(const brick_stream *s, int N, const rans_tables *t, uint
     for (int m = 0; m < N; m++) w[3 + m] = s->cum[m];
     memcpy(w + hdr, s->pal.pal, 4 * s->pal.np);
     memcpy(w + hdr + s->pal.np, states, 4 * W);
-    memcpy(b + 4 * (hdr + s->pal.np + W), words, 2 * nw);
+    if (nw) memcpy(b + 4 * (hdr + s->pal.np + W), words, 2 * nw); /* a uniform brick has no words */
     free(words);
     r->bytes = b;
     r->size = size;
