@@ -187,8 +187,12 @@ def serving_leg(csv, synth, seconds):
                  "p99_us": round(st["p99_us"], 1), "p99_miss_us": round(st["p99_miss_us"], 1),
                  "max_us": round(st["max_us"], 1),
                  "hit_rate": round(st["hits"] / max(st["requests"], 1), 4),
+                 "p50_miss_us": round(st["p50_miss_us"], 1),
                  "joined": int(st["joined"]), "evictions": int(st["evictions"]), "rebuilds": int(st["rebuilds"]),
-                 "batches": int(st["batches"]), "decoded_gb": round(st["decoded_bytes"] / 1e9, 3),
+                 "batches": int(st["batches"]), "mean_batch": round(st["misses"] / max(st["batches"], 1), 1),
+                 "stalls_batch_inflight_slot": [int(st["stall_batch"]), int(st["stall_inflight"]),
+                                                int(st["stall_slot"])],
+                 "decoded_gb": round(st["decoded_bytes"] / 1e9, 3),
                  "worker_busy_frac": round(st["worker_busy_ns"] * 1e-9 / seconds, 3),
                  "worker_launch_frac": round(st["worker_launch_ns"] * 1e-9 / seconds, 3),
                  "lod_hist": [round(float(x), 4) for x in hist]}

@@ -2068,8 +2068,10 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
         // other brick sizes and raw nibbles: the generic decoder, one
         // workgroup per brick (no launch shape, no fixed buffers)
         if (fixed || words_out) return CSV_EINVAL;
+        // 8 workgroups per CU (few registers and 112 bytes of LDS each), 4 for
+        // 64^3 bricks (1.9 MB of scratch per workgroup)
         const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
-        const uint32_t groups = plain ? 1u : std::min(n, 2 * cu);
+        const uint32_t groups = plain ? 1u : std::min(n, (pool->brick_log2 >= 6 ? 4u : 8u) * cu);
         csv::GenericArgs ga{};
         ga.sym_cap = pool->max_c0 + 16;
         ga.scratch_per_group = csv::generic_scratch_bytes(pool->brick_log2, ga.sym_cap);
