@@ -134,7 +134,7 @@ struct LaunchA {
 
 struct LaunchB {
     uint32_t arena_bytes;    // LDS arena per workgroup
-    uint32_t *queue;         // work counter over the leaf list (nullptr: static round robin)
+    uint32_t *queue;         // work counter over the leaf list
     const LeafDesc *leaf_list;
     const uint32_t *leaf_count;
     LeafDesc *slow_list;     // leaf requests that do not fit the LDS arena
@@ -521,20 +521,28 @@ __device__ __forceinline__ uint32_t pal_at(const uint32_t *pal, uint32_t i, uint
 // aligned (kAl16, a compile-time choice so that the compiler keeps the wide
 // store), else four dword stores (outputs of mixed levels of detail need
 // not be aligned)
+//
+// Output stores go through global-address-space pointers, so that they are
+// global (not flat) stores even where the output address was loaded from
+// memory: a flat store also counts on lgkmcnt, and every LDS wait after it
+// would wait for the store as well.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
 __device__ __forceinline__ void store_nt(uint32_t *dst, const uint4 &o) {
     u32x4 v = {o.x, o.y, o.z, o.w};
-    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
+    __builtin_nontemporal_store(v, (g_u32x4 *)dst);
 }
 template <bool kAl16>
 __device__ __forceinline__ void store4(uint32_t *dst, const uint4 &o) {
     if constexpr (kAl16) {
         store_nt(dst, o);
     } else {
-        dst[0] = o.x;
-        dst[1] = o.y;
-        dst[2] = o.z;
-        dst[3] = o.w;
+        g_u32 *g = (g_u32 *)dst;
+        g[0] = o.x;
+        g[1] = o.y;
+        g[2] = o.z;
+        g[3] = o.w;
     }
 }
 
@@ -545,7 +553,7 @@ __device__ __forceinline__ void fill_labels(uint32_t *dst, uint32_t count, uint3
         const uint4 q = make_uint4(v, v, v, v);
         for (uint32_t e = 4 * tid; e < count; e += 4 * kThreads) store_nt(dst + e, q);
     } else {
-        for (uint32_t e = tid; e < count; e += kThreads) dst[e] = v;
+        for (uint32_t e = tid; e < count; e += kThreads) ((g_u32 *)dst)[e] = v;
     }
 }
 
@@ -1133,6 +1141,9 @@ struct SmallB {
     int err;
     uint32_t nref;  // same-level references in the leaf level (list length)
     uint32_t wt[kWavesLeaf][2];  // per-wave totals of P_a, P_delta
+    uint32_t desc[2][16];        // leaf descriptors (dwords 0..11) and work items (dword 12) of the
+                                 // current and the next brick
+    uint32_t item2;              // the work item after those
 };
 
 // Arena of a leaf brick: palette (P entries) and nib4 16-byte groups of
@@ -1204,12 +1215,19 @@ __device__ __forceinline__ uint32_t chase(const IdxT *D, uint32_t i, uint32_t v)
 // same-level references; they are resolved in one pass before the output,
 // which then needs no chasing (a brick with more references than fit
 // chases them in the output loop).  False on a malformed stream.
-template <class IdxT, bool kG, int NW>
+//
+// after_pass2() runs once pass 2 is complete and checked, on every thread,
+// before the references and the output (the leaf kernel issues the next
+// brick's loads there, ahead of this brick's output stores).
+struct NoHook {
+    __device__ void operator()() const {}
+};
+template <class IdxT, bool kG, int NW, class Hook = NoHook>
 __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t ipl, const uint32_t *nib,
                                             uint32_t nib0, const IdxT *l1m, const uint64_t *bm1w,
                                             const uint32_t *pal, uint8_t *ar, const LayoutL &lay, SmallB *sm,
                                             uint32_t *dst, uint16_t *refs, uint32_t ref_cap,
-                                            const uint4 *l1pre = nullptr) {
+                                            const uint4 *l1pre = nullptr, Hook after_pass2 = Hook{}) {
     constexpr bool kList = sizeof(IdxT) == 1 && !kG;
     using V = Vec8<IdxT>;
     using VT = typename V::T;
@@ -1300,6 +1318,8 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     // the expanded L_1 nodes (Morton indices) in Morton (= stream) order,
     // from the bitmask: 8 bits per thread
     for (uint32_t t = tid; t < 512; t += (64 * NW)) {
+        // recomputed per brick rather than held in registers across bricks
+        __asm__ volatile("" : "+v"(t));
         const uint32_t wd = t >> 3, q = t & 7u;
         const uint64_t word = bm1w[wd];
         uint32_t bits = (uint32_t)(word >> (8 * q)) & 0xFFu;
@@ -1386,6 +1406,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     __syncthreads();
     if (sm->err) return false;
     phase_mark(h.rq, 15);
+    after_pass2();
     // the listed references, each followed to its value (concurrent chases
     // see a reference or its final value, both of which lead to the value)
     bool resolved = false;
@@ -1407,7 +1428,7 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     constexpr uint32_t kMark = sizeof(IdxT) == 1 ? 253u : 65533u;
     auto slices = [&](auto al16, auto refs_left) {
         for (uint32_t zz = w; zz < 32; zz += NW) {
-#pragma unroll
+#pragma unroll 2
             for (int c = 0; c < 4; c++) {
                 const uint32_t v0 = 4 * (L & 7u) + 32 * ((L >> 3) + 8 * (uint32_t)c) + 1024 * zz;
                 uint32_t idx[4];
@@ -1464,84 +1485,190 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     return true;
 }
 
-// kSlow false: bricks whose arrays fit the LDS arena, the others deferred
-// to the slow list; kSlow true: the slow list, on an arena in global memory
-template <int NW, bool kSlow>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ? 4 : 6))) void leaf_kernel(DecodeArgs a,
-                                                                                                      LaunchB l) {
+// A leaf descriptor in one VGPR: lane j (< 12) holds dword j of the
+// descriptor of work item `item`, lane 12 the item itself (a vector load:
+// it counts on vmcnt, not on lgkmcnt, so the LDS waits of the brick in
+// progress never wait for it)
+__device__ __forceinline__ uint32_t desc_lane(const LeafDesc *list, uint32_t item, uint32_t n_items) {
+    uint32_t L = lane();
+    // the lane's address is recomputed per call, not kept in registers
+    // across the replay
+    __asm__ volatile("" : "+v"(L));
+    if (L == 12) return item;
+    return (item < n_items && L < 12) ? glob(reinterpret_cast<const uint32_t *>(list + item))[L] : 0u;
+}
+struct LeafFields {
+    uint32_t rq, id, P, c0, c1, E1, ipl, item;
+    uint64_t rec, dst;
+};
+__device__ __forceinline__ LeafFields leaf_fields(uint32_t v) {
+    LeafFields f;
+    f.rq = __builtin_amdgcn_readlane(v, 0);
+    f.id = __builtin_amdgcn_readlane(v, 1);
+    f.P = __builtin_amdgcn_readlane(v, 2);
+    f.c0 = __builtin_amdgcn_readlane(v, 3);
+    f.c1 = __builtin_amdgcn_readlane(v, 4);
+    f.E1 = __builtin_amdgcn_readlane(v, 5);
+    f.ipl = __builtin_amdgcn_readlane(v, 6);
+    f.item = __builtin_amdgcn_readlane(v, 12);
+    // readlane returns an int: widen through uint32_t (no sign extension)
+    f.rec = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(v, 8) | (uint64_t)(uint32_t)__builtin_amdgcn_readlane(v, 9) << 32;
+    f.dst = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(v, 10) | (uint64_t)(uint32_t)__builtin_amdgcn_readlane(v, 11) << 32;
+    return f;
+}
+// the descriptor in LDS slot k, one dword per lane
+__device__ __forceinline__ LeafFields leaf_fields_lds(const SmallB *sm, uint32_t k) {
+    const uint32_t L = lane();
+    return leaf_fields(sm->desc[k][L < 13 ? L : 0]);
+}
+// How a leaf brick is staged: fast (palette, nibbles from the delta segment
+// of L_0 on, from a 16-byte boundary, and the arrays in the LDS arena), lean
+// (the same without the nibbles, which are then read from the slot), or
+// neither (the slow list)
+struct LeafKind {
+    uint32_t nb0, nib4;
+    bool fast, lean;
+    LayoutL lay;
+};
+__device__ __forceinline__ LeafKind leaf_kind(const LeafFields &f, uint32_t arena_bytes) {
+    LeafKind k;
+    const uint32_t E1c = f.E1 < 4096 ? f.E1 : 4096u;
+    k.nb0 = (f.c1 >> 5) << 2;
+    k.nib4 = (((f.c0 + 7) >> 3) + 2 - k.nb0 + 3) / 4;
+    const LayoutL fast = make_layout_l(true, f.P, k.nib4, E1c, 1);
+    const LayoutL lean = make_layout_l(true, f.P, 0, E1c, 1);
+    k.fast = f.P <= kPalFast && fast.total <= arena_bytes;
+    k.lean = !k.fast && f.P <= kPalFast && lean.total <= arena_bytes;
+    k.lay = k.fast ? fast : lean;
+    return k;
+}
+// A leaf brick's staging data in registers: q is group tid of L_1 (Morton
+// order) for tid < 256 and group tid - 256 of its expansion bits for
+// 256 <= tid < 288; nb is nibble group tid (fast bricks); pal is palette
+// entry tid
+struct LeafPre {
+    uint4 q, nb;
+    uint32_t pal;
+};
+__device__ __forceinline__ void leaf_prefetch(LeafPre &p, const LeafFields &f, bool valid, const LaunchB &l,
+                                              uint32_t hdr, uint32_t tid) {
+    p.q = make_uint4(0u, 0u, 0u, 0u);
+    p.nb = p.q;
+    p.pal = 0;
+    if (!valid) return;
+    const LeafKind k = leaf_kind(f, l.arena_bytes);
+    if (!k.fast && !k.lean) return;
+    const uint8_t *slot = glob(l.slots) + (size_t)f.rq * l.slot_bytes;
+    const uint8_t *slv = slot + 4 * l.slot_dw;
+    if (tid < 256) p.q = reinterpret_cast<const uint4 *>(slv)[tid];
+    else if (tid < 288) p.q = reinterpret_cast<const uint4 *>(slv + kSlotLv)[tid - 256];
+    if (tid < f.P) p.pal = rec_at(f.rec)[hdr + tid];
+    if (k.fast && tid < k.nib4) p.nb = reinterpret_cast<const uint4 *>(slot + 4 * k.nb0)[tid];
+}
+
+// Bricks that fit the LDS arena.  Each brick is staged from registers
+// loaded while the workgroup replayed the previous brick, after its pass 2
+// and before its output: loads issued after a brick's output stores would
+// wait behind them (on gfx9 one counter tracks both, and the memory path
+// serves them in order).  The work items come from a counter, and run ahead
+// of the replay so that nothing waits for them: while brick k is replayed the
+// workgroup loads the staging data of brick k + 1 and the descriptor of
+// brick k + 2, and takes the item of brick k + 3.  Descriptors and items
+// pass through LDS (two descriptor slots and one item), so that no register
+// holds them during a replay.
+template <int NW>
+__device__ __forceinline__ void leaf_fast_bricks(const DecodeArgs &a, const LaunchB &l, SmallB *sm, uint8_t *arena,
+                                                 uint32_t n_items, const LeafDesc *list) {
     constexpr uint32_t NT = 64 * NW;
-    static_assert(kSlow || NT >= 256, "thread t < 256 preloads level-1 group t");
-    extern __shared__ __align__(16) uint8_t smem[];
-    SmallB *sm = reinterpret_cast<SmallB *>(smem);
-    uint8_t *arena = smem + align16(sizeof(SmallB));
-    uint8_t *gslot = l.scratch ? glob(l.scratch) + (size_t)blockIdx.x * l.scratch_bytes : nullptr;
-    const uint32_t tid = threadIdx.x;
+    static_assert(NT >= 288, "threads below 288 hold level 1 and its expansion bits");
+    const uint32_t tid = threadIdx.x, w = tid >> 6;
     const uint32_t hdr = csv::record_header_words(kLog2);
-    const uint32_t n_items = *glob(kSlow ? l.slow_count : l.leaf_count);
-    const LeafDesc *list = kSlow ? l.slow_list : l.leaf_list;
-    uint32_t *queue = kSlow ? l.slow_queue : l.queue;
-    for (uint32_t k = 0;; k++) {
-        if (tid == 0) sm->req = queue ? atomicAdd(queue, 1u) : blockIdx.x + k * gridDim.x;
+    uint32_t *queue = glob(l.queue);
+    // the next work item (thread 0).  An increment, not an add: the compiler
+    // rewrites a uniform-address add so that it reads the result at once,
+    // and that wait would also wait for the loads issued just before it.
+    auto take = [&]() -> uint32_t { return atomicInc(queue, 0xFFFFFFFFu); };
+    if (tid == 0) {
+        const uint32_t i0 = take(), i1 = take(), i2 = take();
+        sm->desc[0][12] = i0;
+        sm->desc[1][12] = i1;
+        sm->item2 = i2;
+    }
+    __syncthreads();
+    // brick 0's descriptor and staging data, and brick 1's descriptor
+    LeafPre pre;
+    uint32_t ndv = 0, r = 0;
+    {
+        const uint32_t i0 = sm->desc[0][12], v0 = desc_lane(list, i0, n_items);
+        leaf_prefetch(pre, leaf_fields(v0), i0 < n_items, l, hdr, tid);
+        if (w == 0) ndv = desc_lane(list, sm->desc[1][12], n_items);
         __syncthreads();
-        const uint32_t item = uniform(sm->req);
-        if (item >= n_items) break;
-        // a request at t = 0 the front kernel has checked and decoded down to level 1
-        const LeafDesc *ds = list + item;
-        const uint32_t rq = ld_s(&ds->rq);
+        if (tid < 13) sm->desc[0][tid] = v0;
+    }
+    __syncthreads();
+    for (uint32_t k = 0;; k++) {
+        const uint32_t cur = k & 1u;
+        const LeafFields f = leaf_fields_lds(sm, cur);
+        if (f.item >= n_items) break;
+        const uint32_t rq = f.rq;
+        phase_mark(rq, 6);
+#ifdef CSV_PHASE_TIMING
+        if (g_phase && tid == 0) g_phase[16 * (size_t)rq + 7] = (uint64_t)blockIdx.x | (uint64_t)k << 32;
+#endif
         Hdr h;
         h.rq = rq;
-        h.id = ld_s(&ds->id);
-        h.P = ld_s(&ds->P);
-        h.c0 = ld_s(&ds->c0);
-        h.c1 = ld_s(&ds->c1);
-        h.rec = rec_at(ld_s(&ds->rec));
-        uint32_t *dst = reinterpret_cast<uint32_t *>(ld_s(&ds->dst));
-        const uint32_t count = 32768u;
-        const uint32_t E1 = ld_s(&ds->E1), ipl = ld_s(&ds->ipl);
-        phase_mark(rq, 6);
-        const uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
-        const uint32_t *gnib = reinterpret_cast<const uint32_t *>(slot);
-        const uint8_t *slv = slot + 4 * l.slot_dw;
-        const uint8_t *sbm = slv + kSlotLv;
-        const uint32_t E1c = E1 < 4096 ? E1 : 4096u;
+        h.id = f.id;
+        h.P = f.P;
+        h.c0 = f.c0;
+        h.c1 = f.c1;
+        h.rec = rec_at(f.rec);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(f.dst);
+        const uint32_t *gnib = reinterpret_cast<const uint32_t *>(glob(l.slots) + (size_t)rq * l.slot_bytes);
+        const uint8_t *slv = reinterpret_cast<const uint8_t *>(gnib) + 4 * l.slot_dw;
+        const LeafKind kd = leaf_kind(f, l.arena_bytes);
         if (tid == 0) {
             sm->err = 0;
             sm->nref = 0;
+            if (k > 0) sm->item2 = r;  // the item of brick k + 2, taken while brick k - 1 was replayed
         }
-        bool ok = true, done = true;
-        if constexpr (!kSlow) {
-            // nibbles from the delta segment of L_0 on, from a 16-byte boundary
-            const uint32_t nb0 = (h.c1 >> 5) << 2, nib4 = (((h.c0 + 7) >> 3) + 2 - nb0 + 3) / 4;
-            const LayoutL fast = make_layout_l(true, h.P, nib4, E1c, 1);
-            // without its nibbles staged (they are read from the slot)
-            const LayoutL lean = make_layout_l(true, h.P, 0, E1c, 1);
-            if (h.P <= kPalFast && fast.total > l.arena_bytes && lean.total <= l.arena_bytes) {
-                for (uint32_t e = tid; e < h.P; e += NT) reinterpret_cast<uint32_t *>(arena + lean.pal)[e] = h.rec[hdr + e];
-                if (tid < 32) reinterpret_cast<uint4 *>(arena + lean.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
-                const uint4 l1q = tid < 256 ? reinterpret_cast<const uint4 *>(slv)[tid] : make_uint4(0u, 0u, 0u, 0u);
-                __syncthreads();
-                ok = leaf_replay<uint8_t, false, NW>(h, E1, ipl, gnib, 0, slv,
-                                                     reinterpret_cast<const uint64_t *>(arena + lean.bm1),
-                                                     reinterpret_cast<const uint32_t *>(arena + lean.pal), arena, lean,
-                                                     sm, dst, reinterpret_cast<uint16_t *>(arena + lean.total),
-                                                     min((l.arena_bytes - lean.total) / 2, l.ref_cap), &l1q);
-            } else if (h.P <= kPalFast && fast.total <= l.arena_bytes) {
-                for (uint32_t e = tid; e < h.P; e += NT) reinterpret_cast<uint32_t *>(arena + fast.pal)[e] = h.rec[hdr + e];
-                for (uint32_t e = tid; e < nib4; e += NT)
-                    reinterpret_cast<uint4 *>(arena + fast.nib)[e] = reinterpret_cast<const uint4 *>(gnib + nb0)[e];
-                if (tid < 32) reinterpret_cast<uint4 *>(arena + fast.bm1)[tid] = reinterpret_cast<const uint4 *>(sbm)[tid];
-                // level 1 (Morton order) with the other loads: one round trip
-                const uint4 l1q = tid < 256 ? reinterpret_cast<const uint4 *>(slv)[tid] : make_uint4(0u, 0u, 0u, 0u);
-                __syncthreads();
-                ok = leaf_replay<uint8_t, false, NW>(h, E1, ipl, reinterpret_cast<const uint32_t *>(arena + fast.nib),
-                                                     8 * nb0, slv, reinterpret_cast<const uint64_t *>(arena + fast.bm1),
-                                                     reinterpret_cast<const uint32_t *>(arena + fast.pal), arena, fast,
-                                                     sm, dst, reinterpret_cast<uint16_t *>(arena + fast.total),
-                                                     min((l.arena_bytes - fast.total) / 2, l.ref_cap), &l1q);
-            } else if (l.slow_list) {  // the slow kernel takes it
+        if (tid < 13) sm->desc[cur ^ 1u][tid] = ndv;
+        bool ok = true, done = true, pre_done = false;
+        // loads for the next bricks (every thread; after a barrier that
+        // follows the LDS writes above)
+        auto next = [&]() {
+            const LeafFields nf = leaf_fields_lds(sm, cur ^ 1u);
+            leaf_prefetch(pre, nf, nf.item < n_items, l, hdr, tid);
+            if (w == 0) ndv = desc_lane(list, sm->item2, n_items);
+            if (tid == 0) r = take();
+            pre_done = true;
+        };
+        if (kd.fast || kd.lean) {
+            if (tid < h.P) reinterpret_cast<uint32_t *>(arena + kd.lay.pal)[tid] = pre.pal;
+            if (tid >= 256 && tid < 288) reinterpret_cast<uint4 *>(arena + kd.lay.bm1)[tid - 256] = pre.q;
+            if (kd.fast) {
+                if (tid < kd.nib4) reinterpret_cast<uint4 *>(arena + kd.lay.nib)[tid] = pre.nb;
+                for (uint32_t e = tid + NT; e < kd.nib4; e += NT)
+                    reinterpret_cast<uint4 *>(arena + kd.lay.nib)[e] = reinterpret_cast<const uint4 *>(gnib + kd.nb0)[e];
+            }
+            const uint4 l1q = pre.q;
+            __syncthreads();
+            const uint32_t ref_cap = min((l.arena_bytes - kd.lay.total) / 2, l.ref_cap);
+            uint16_t *refs = reinterpret_cast<uint16_t *>(arena + kd.lay.total);
+            const uint64_t *bm1 = reinterpret_cast<const uint64_t *>(arena + kd.lay.bm1);
+            const uint32_t *pal = reinterpret_cast<const uint32_t *>(arena + kd.lay.pal);
+            if (kd.fast)
+                ok = leaf_replay<uint8_t, false, NW>(h, f.E1, f.ipl, reinterpret_cast<const uint32_t *>(arena + kd.lay.nib),
+                                                     8 * kd.nb0, slv, bm1, pal, arena, kd.lay, sm, dst, refs, ref_cap,
+                                                     &l1q, next);
+            else
+                ok = leaf_replay<uint8_t, false, NW>(h, f.E1, f.ipl, gnib, 0, slv, bm1, pal, arena, kd.lay, sm, dst,
+                                                     refs, ref_cap, &l1q, next);
+        } else {
+            __syncthreads();
+            if (l.slow_list) {  // the slow kernel takes it
                 done = false;
                 if (tid == 0) {
-                    const uint4 *src = reinterpret_cast<const uint4 *>(glob(ds));
+                    const uint4 *src = reinterpret_cast<const uint4 *>(glob(list + f.item));
                     uint4 *to = reinterpret_cast<uint4 *>(l.slow_list + atomicAdd(l.slow_count, 1u));
                     to[0] = src[0];
                     to[1] = src[1];
@@ -1550,10 +1677,68 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
             } else {  // the pool's bounds say every brick fits: a corrupt record
                 ok = false;
             }
-        } else {
+        }
+        if (!pre_done) next();  // no replay, or one that stopped early
+        __syncthreads();
+        if (done && !ok) {
+            if (tid == 0) fail(a, rq, CSV_ECORRUPT, h.id);
+            fill_labels<NT>(dst, 32768u, 0u, tid);
+        }
+        __syncthreads();
+    }
+    // the last item taken has returned before this workgroup reports that it
+    // is done (the last workgroup to finish clears the counter)
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+// kSlow false: bricks whose arrays fit the LDS arena, the others deferred
+// to the slow list; kSlow true: the slow list, on an arena in global memory
+template <int NW, bool kSlow>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ? 4 : 6))) void leaf_kernel(DecodeArgs a,
+                                                                                                      LaunchB l) {
+    constexpr uint32_t NT = 64 * NW;
+    extern __shared__ __align__(16) uint8_t smem[];
+    SmallB *sm = reinterpret_cast<SmallB *>(smem);
+    uint8_t *arena = smem + align16(sizeof(SmallB));
+    uint8_t *gslot = l.scratch ? glob(l.scratch) + (size_t)blockIdx.x * l.scratch_bytes : nullptr;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t hdr = csv::record_header_words(kLog2);
+    const uint32_t n_items = *glob(kSlow ? l.slow_count : l.leaf_count);
+    const LeafDesc *list = kSlow ? l.slow_list : l.leaf_list;
+    if constexpr (!kSlow) {
+        leaf_fast_bricks<NW>(a, l, sm, arena, n_items, list);
+    } else {
+        uint32_t *queue = l.slow_queue;
+        for (uint32_t k = 0;; k++) {
+            if (tid == 0) sm->req = queue ? atomicAdd(queue, 1u) : blockIdx.x + k * gridDim.x;
+            __syncthreads();
+            const uint32_t item = uniform(sm->req);
+            if (item >= n_items) break;
+            // a request at t = 0 the front kernel has checked and decoded down
+            // to level 1, whose arrays do not fit the LDS arena
+            const LeafDesc *ds = list + item;
+            const uint32_t rq = ld_s(&ds->rq);
+            Hdr h;
+            h.rq = rq;
+            h.id = ld_s(&ds->id);
+            h.P = ld_s(&ds->P);
+            h.c0 = ld_s(&ds->c0);
+            h.c1 = ld_s(&ds->c1);
+            h.rec = rec_at(ld_s(&ds->rec));
+            uint32_t *dst = reinterpret_cast<uint32_t *>(ld_s(&ds->dst));
+            const uint32_t E1 = ld_s(&ds->E1), ipl = ld_s(&ds->ipl);
+            phase_mark(rq, 6);
+            const uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
+            const uint32_t *gnib = reinterpret_cast<const uint32_t *>(slot);
+            const uint8_t *slv = slot + 4 * l.slot_dw;
+            const uint64_t *gbm = reinterpret_cast<const uint64_t *>(slv + kSlotLv);
+            if (tid == 0) {
+                sm->err = 0;
+                sm->nref = 0;
+            }
             phase_mark(rq, 7);
             __syncthreads();
-            const uint64_t *gbm = reinterpret_cast<const uint64_t *>(sbm);
+            bool ok;
             if (!gslot)
                 ok = false;
             else if (h.P <= kPalFast)
@@ -1563,13 +1748,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
                 ok = leaf_replay<uint16_t, true, NW>(h, E1, ipl, gnib, 0, reinterpret_cast<const uint16_t *>(slv), gbm,
                                                      h.rec + hdr, gslot, make_layout_l(false, 0, 0, 4096, 2), sm, dst,
                                                      nullptr, 0);
+            __syncthreads();
+            if (!ok) {
+                if (tid == 0) fail(a, rq, gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
+                fill_labels<NT>(dst, 32768u, 0u, tid);
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (done && !ok) {
-            if (tid == 0) fail(a, rq, !kSlow || gslot ? CSV_ECORRUPT : CSV_EINVAL, h.id);
-            fill_labels<NT>(dst, count, 0u, tid);
-        }
-        __syncthreads();
     }
     // the last workgroup to finish clears the counters this kernel was the
     // last to use, for the next launch on these buffers: every other
@@ -2175,7 +2360,7 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     la.words_out = words_out;
     LaunchB lb;
     lb.arena_bytes = arena_b(groups_b);
-    lb.queue = (queue || plain) ? ctr + 1 : nullptr;
+    lb.queue = ctr + 1;  // the leaf kernel always takes its bricks from a counter
     lb.leaf_list = B->leaf_list;
     lb.leaf_count = ctr + 2;
     lb.slow_count = ctr + 3;
