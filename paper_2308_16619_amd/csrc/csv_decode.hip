@@ -1066,15 +1066,24 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     const uint32_t L = lane(), wave = uniform(threadIdx.x >> 6);
     uint8_t *wl = smem + align16(4 * l.lut_lds_words) + wave * kWaveLds;
     const uint32_t wid = blockIdx.x * WPG + wave;
+    // With a work counter, each request is taken one brick ahead (lane 0)
+    // and its value read at the end of the brick before: a read at the top
+    // of a brick would wait behind the previous brick's stores (on gfx9 one
+    // counter tracks loads and stores, served in order), and then the
+    // brick's own loads would wait again.  An increment, not an add: the
+    // compiler rewrites a uniform-address add to read its result at once.
+    uint32_t taken = 0, cur = 0;
+    if (l.queue) {
+        if (L == 0) taken = atomicInc(l.queue, 0xFFFFFFFFu);
+        cur = uniform(taken);
+        if (L == 0) taken = atomicInc(l.queue, 0xFFFFFFFFu);
+    }
     for (uint32_t k = 0;; k++) {
-        uint32_t req;
-        if (l.queue) {
-            uint32_t v = 0;
-            if (L == 0) v = atomicAdd(l.queue, 1u);
-            req = uniform(v) + l.base;
-        } else {
-            req = l.base + wid + k * gridDim.x * WPG;
+        if (k > 0 && l.queue) {
+            cur = uniform(taken);
+            if (L == 0) taken = atomicInc(l.queue, 0xFFFFFFFFu);
         }
+        const uint32_t req = l.base + (l.queue ? cur : wid + k * gridDim.x * WPG);
         if (req >= a.n) break;
         const uint32_t rq = l.order ? ld_s(l.order + req) : req;
         phase_mark(rq, 0);
@@ -1779,10 +1788,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
     }
 }
 
-// Longest-first request order: requests are binned by the log2 of their
-// work (symbols to decode plus output voxels / 8), largest bin first, and
-// laid out bin by bin.
-constexpr int kBins = 32;
+// Longest-first request order: requests are binned by their work (symbols
+// to decode plus output voxels / 8) on a log scale with 8 bins per octave
+// (the bits after the leading one), largest first, and laid out bin by bin;
+// the order within a bin is arbitrary.  Two launches of many workgroups:
+// order_count adds up the bin sizes, order_place gives each request its
+// position (exclusive scan of the sizes plus a per-bin cursor).
+constexpr int kBins = 128;
+constexpr uint32_t kOrderWords = 2 * kBins + 8;   // bin sizes, bin cursors, done counter
+constexpr uint32_t kSmallWords = kOrderWords + 8; // then the launch counters
 __device__ __forceinline__ uint32_t work_bin(const DecodeArgs &a, uint32_t r) {
     const uint32_t id = a.ids[r];
     const uint32_t t = a.lods ? (uint32_t)a.lods[r] : a.lod_scalar;
@@ -1791,29 +1805,56 @@ __device__ __forceinline__ uint32_t work_bin(const DecodeArgs &a, uint32_t r) {
     const uint32_t n = t < (uint32_t)kLog2 ? rec[3 + t] : 0u;
     const uint32_t g = 32u >> t;
     const uint32_t work = n + (g * g * g) / 8 + 1;
-    return (uint32_t)__builtin_clz(work);  // 32 - bit length: small for big work
+    const uint32_t lz = 31u - (uint32_t)__builtin_clz(work);  // floor(log2(work))
+    const uint32_t frac = lz >= 3 ? (work >> (lz - 3)) & 7u : (work << (3 - lz)) & 7u;
+    const uint32_t key = 8 * lz + frac;                       // about 8 log2(work)
+    return key >= (uint32_t)kBins - 1 ? 0u : (uint32_t)kBins - 1 - key;
 }
-// one workgroup: bin counts and offsets in LDS, then each request takes
-// the next slot of its bin (the order within a bin is arbitrary)
-__global__ __launch_bounds__(1024) void order_lpt(DecodeArgs a, uint32_t *order) {
-    __shared__ uint32_t cnt[kBins], off[kBins];
+__global__ __launch_bounds__(256) void order_count(DecodeArgs a, uint32_t *cnt) {
+    __shared__ uint32_t h[kBins];
     const uint32_t tid = threadIdx.x;
-    if (tid < kBins) cnt[tid] = 0;
+    for (uint32_t b = tid; b < (uint32_t)kBins; b += 256) h[b] = 0;
     __syncthreads();
-    for (uint32_t r = tid; r < a.n; r += blockDim.x) atomicAdd(&cnt[work_bin(a, r)], 1u);
+    for (uint32_t r = blockIdx.x * 256 + tid; r < a.n; r += gridDim.x * 256) atomicAdd(&h[work_bin(a, r)], 1u);
     __syncthreads();
-    if (tid == 0) {
-        uint32_t o = 0;
-        for (int b = 0; b < kBins; b++) {
-            off[b] = o;
-            o += cnt[b];
-        }
+    for (uint32_t b = tid; b < (uint32_t)kBins; b += 256)
+        if (h[b]) atomicAdd(cnt + b, h[b]);
+}
+// same grid as order_count; the last workgroup to finish clears the sizes,
+// cursors and its done counter for the next launch
+__global__ __launch_bounds__(256) void order_place(DecodeArgs a, uint32_t *small, uint32_t *order) {
+    static_assert(kBins == 128, "two waves scan the bin sizes");
+    __shared__ uint32_t off[kBins], h[kBins], base[kBins], tot0, last;
+    uint32_t *cnt = glob(small), *cur = cnt + kBins, *done = cnt + 2 * kBins;
+    const uint32_t tid = threadIdx.x;
+    // exclusive scan of the bin sizes (waves 0 and 1, 64 bins each)
+    uint32_t c = 0, inc = 0;
+    if (tid < (uint32_t)kBins) {
+        c = cnt[tid];
+        inc = wave_incl_scan(c);
+        if (tid == 63) tot0 = inc;
+        h[tid] = 0;
     }
     __syncthreads();
-    for (uint32_t r = tid; r < a.n; r += blockDim.x) order[atomicAdd(&off[work_bin(a, r)], 1u)] = r;
+    if (tid < (uint32_t)kBins) off[tid] = inc - c + (tid >= 64 ? tot0 : 0u);
+    // this workgroup's bin sizes, then its range of each bin
+    for (uint32_t r = blockIdx.x * 256 + tid; r < a.n; r += gridDim.x * 256) atomicAdd(&h[work_bin(a, r)], 1u);
+    __syncthreads();
+    if (tid < (uint32_t)kBins) {
+        base[tid] = h[tid] ? atomicAdd(cur + tid, h[tid]) : 0u;
+        h[tid] = 0;
+    }
+    __syncthreads();
+    for (uint32_t r = blockIdx.x * 256 + tid; r < a.n; r += gridDim.x * 256) {
+        const uint32_t b = work_bin(a, r);
+        order[off[b] + base[b] + atomicAdd(&h[b], 1u)] = r;
+    }
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (last)
+        for (uint32_t i = tid; i < 2 * (uint32_t)kBins + 1; i += 256) cnt[i] = 0;
 }
-
-
 __global__ void zero_words(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -1870,7 +1911,7 @@ struct LaunchBufs {
     uint32_t *order = nullptr;     // longest-first order
     LeafDesc *leaf_list = nullptr; // requests for the leaf kernel
     LeafDesc *slow_list = nullptr; // ... of them for its global-arena variant
-    uint32_t *small = nullptr;     // [0, 64): order bins; [64, 72): the launch counters
+    uint32_t *small = nullptr;     // kOrderWords of order bins, then 8 launch counters
     uint8_t *arenas = nullptr;     // global arenas of the global-arena leaf kernel, one per workgroup
     uint32_t arena_groups = 0;     // workgroups they serve
     bool owned = true;             // false: a view of memory the library does not allocate
@@ -1922,7 +1963,7 @@ struct LaunchBufs {
             hipMalloc(reinterpret_cast<void **>(&order), 4ull * cap) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&leaf_list), sizeof(LeafDesc) * cap) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&slow_list), sizeof(LeafDesc) * cap) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&small), 4 * 72) != hipSuccess) {
+            hipMalloc(reinterpret_cast<void **>(&small), 4 * kSmallWords) != hipSuccess) {
             release();
             return CSV_ENOMEM;
         }
@@ -1947,7 +1988,9 @@ constexpr size_t kMaxStreamBufs = 16;
 // out of one fixed device array instead of allocated memory
 constexpr size_t kNoAllocBytes = 64ull << 20;
 constexpr uint32_t kNoAllocArenas = 32;
-constexpr size_t kNoAllocHead = 512 + (size_t)kNoAllocArenas * kArenaBytes;  // counters, then arenas
+constexpr size_t kNoAllocSmall = 2048;  // order bins and counters
+constexpr size_t kNoAllocHead = kNoAllocSmall + (size_t)kNoAllocArenas * kArenaBytes;  // then the arenas
+static_assert(4 * kSmallWords <= kNoAllocSmall, "order bins and counters");
 static_assert(kNoAllocHead % 256 == 0, "arena layout");
 
 }  // namespace
@@ -2342,9 +2385,9 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     // when a launch starts: zeroed at allocation, then by the last
     // workgroup of the leaf kernels (0, 1, 2, 5) and of the global-arena
     // kernel (3, 4, 6), which only runs when the leaf kernel may defer to it.
-    uint32_t *ctr = B->small + 2 * kBins;
+    uint32_t *ctr = B->small + kOrderWords;
     if (B->dirty) {  // new buffers, or a launch failed part way: start from zero (a kernel, in stream order)
-        hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, B->small, 72u);
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, B->small, kSmallWords);
         B->dirty = false;
     }
     LaunchA la;
@@ -2401,7 +2444,9 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
         }
     } else {
         if (lpt) {
-            hipLaunchKernelGGL(order_lpt, dim3(1), dim3(1024), 0, s, a, B->order);
+            const uint32_t grid_o = std::min(256u, (n + 255) / 256);
+            hipLaunchKernelGGL(order_count, dim3(grid_o), dim3(256), 0, s, a, B->small);
+            hipLaunchKernelGGL(order_place, dim3(grid_o), dim3(256), 0, s, a, B->small, B->order);
             la.order = B->order;
         }
         go_a(a, la, grid_a);
@@ -2967,7 +3012,7 @@ int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const u
     if (fit == 0) return CSV_ERANGE;  // one request's slot exceeds the scratch
     const uint32_t chunk = (uint32_t)std::min<uint64_t>(fit, n);
     v.small = reinterpret_cast<uint32_t *>(base);
-    v.arenas = base + 512;
+    v.arenas = base + kNoAllocSmall;
     v.arena_groups = kNoAllocArenas;
     v.order = reinterpret_cast<uint32_t *>(base + kNoAllocHead);
     v.leaf_list = reinterpret_cast<LeafDesc *>(base + kNoAllocHead + ((4ull * chunk + 15) & ~15ull));
@@ -2977,7 +3022,7 @@ int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const u
     v.cap_n = chunk;
     // the previous call's counters and order bins may be left non-zero (a
     // failed launch): clear them with a kernel, in stream order
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, v.stream, v.small, 72u);
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, v.stream, v.small, kSmallWords);
     if (hipGetLastError() != hipSuccess) return CSV_EHIP;
     const uint64_t g = 32u >> lod_scalar;
     for (uint32_t at = 0; at < n; at += chunk) {

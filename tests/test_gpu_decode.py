@@ -280,7 +280,8 @@ def test_launch_shapes_agree(csvlib, orc, cfg2, shape):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), want)
 
 
-@pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (16, 3, 0, 0, 2), (8, 2, 1, 1, 4), (16, 4, 0, 0, 8)])
+@pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (16, 3, 0, 0, 2), (8, 2, 1, 1, 4), (16, 4, 0, 0, 8),
+                                   (8, 3, 0, 1, 4), (16, 3, 0, 1, 1)])
 def test_pipelined_chunks_agree(csvlib, orc, cfg1, cfg2, shape):
     # the requests split into chunks that alternate between the caller's
     # stream and the pool's second stream: mixed LODs over two volumes with

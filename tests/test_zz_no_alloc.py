@@ -52,7 +52,8 @@ def _both(csv, pool, ids, lods=None, lod=0):
     return got.cpu().numpy().view(np.uint32), want.cpu().numpy().view(np.uint32)
 
 
-def test_noalloc_matches_decode_twice(csvlib, orc):
+@pytest.mark.parametrize("shape", [None, (8, 3, 0, 1, 1)])
+def test_noalloc_matches_decode_twice(csvlib, orc, shape):
     # one pool: the edge bricks (palettes beyond 252 and beyond the LDS
     # arena, so the global-arena kernel runs on the scratch's arenas; the
     # 32,768-label brick makes each request's slot about 47 KB, so 3000
@@ -64,6 +65,8 @@ def test_noalloc_matches_decode_twice(csvlib, orc):
     pool = csvlib.Pool()
     assert pool.add_volume(b_edge) == 0
     assert pool.add_volume(b_vor) == 8
+    if shape is not None:  # longest-first order: its bins live in the scratch too
+        pool.set_shape(shape)
     rng = np.random.default_rng(77)
     n1 = 3000
     ids = rng.integers(0, 16, n1)
