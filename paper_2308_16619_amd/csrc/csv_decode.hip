@@ -1579,12 +1579,12 @@ __device__ __forceinline__ void leaf_prefetch(LeafPre &p, const LeafFields &f, b
 // loaded while the workgroup replayed the previous brick, after its pass 2
 // and before its output: loads issued after a brick's output stores would
 // wait behind them (on gfx9 one counter tracks both, and the memory path
-// serves them in order).  The work items come from a counter, and run ahead
-// of the replay so that nothing waits for them: while brick k is replayed the
-// workgroup loads the staging data of brick k + 1 and the descriptor of
-// brick k + 2, and takes the item of brick k + 3.  Descriptors and items
-// pass through LDS (two descriptor slots and one item), so that no register
-// holds them during a replay.
+// serves them in order).  The work items come from a counter (after a first
+// fixed round), and run ahead of the replay so that nothing waits for them:
+// while brick k is replayed the workgroup loads the staging data of brick
+// k + 1 and the descriptor of brick k + 2, and takes the item of brick
+// k + 3.  Descriptors and items pass through LDS (two descriptor slots and
+// one item), so that no register holds them during a replay.
 template <int NW>
 __device__ __forceinline__ void leaf_fast_bricks(const DecodeArgs &a, const LaunchB &l, SmallB *sm, uint8_t *arena,
                                                  uint32_t n_items, const LeafDesc *list) {
@@ -1593,15 +1593,17 @@ __device__ __forceinline__ void leaf_fast_bricks(const DecodeArgs &a, const Laun
     const uint32_t tid = threadIdx.x, w = tid >> 6;
     const uint32_t hdr = csv::record_header_words(kLog2);
     uint32_t *queue = glob(l.queue);
-    // the next work item (thread 0).  An increment, not an add: the compiler
-    // rewrites a uniform-address add so that it reads the result at once,
-    // and that wait would also wait for the loads issued just before it.
-    auto take = [&]() -> uint32_t { return atomicInc(queue, 0xFFFFFFFFu); };
+    // Items 0 .. 3 gridDim.x - 1 go out in a fixed order (workgroup b starts
+    // with b, b + G and b + 2G), the rest from the counter, one per replayed
+    // brick (thread 0).  An increment, not an add: the compiler rewrites a
+    // uniform-address add so that it reads the result at once, and that
+    // wait would also wait for the loads issued just before it.
+    const uint32_t G = gridDim.x;
+    auto take = [&]() -> uint32_t { return 3 * G + atomicInc(queue, 0xFFFFFFFFu); };
     if (tid == 0) {
-        const uint32_t i0 = take(), i1 = take(), i2 = take();
-        sm->desc[0][12] = i0;
-        sm->desc[1][12] = i1;
-        sm->item2 = i2;
+        sm->desc[0][12] = blockIdx.x;
+        sm->desc[1][12] = blockIdx.x + G;
+        sm->item2 = blockIdx.x + 2 * G;
     }
     __syncthreads();
     // brick 0's descriptor and staging data, and brick 1's descriptor
