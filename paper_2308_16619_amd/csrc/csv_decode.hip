@@ -1422,7 +1422,26 @@ __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t 
     if constexpr (kList) {
         const uint32_t nref = sm->nref;
         if (nref <= ref_cap) {
-            for (uint32_t e = tid; e < nref; e += 64 * NW) {
+            // two chains per thread and round, their loads in flight together
+            constexpr uint32_t kMarkL = sizeof(IdxT) == 1 ? 253u : 65533u;
+            uint32_t e = tid;
+            for (; e + 64 * NW < nref; e += 2 * 64 * NW) {
+                const uint32_t a0 = refs[e], b0 = refs[e + 64 * NW];
+                uint32_t ia = a0, ib = b0, va = D[a0], vb = D[b0];
+                while (va >= kMarkL || vb >= kMarkL) {
+                    if (va >= kMarkL) {
+                        ia -= 1u << (5 * (va - kMarkL));
+                        va = D[ia];
+                    }
+                    if (vb >= kMarkL) {
+                        ib -= 1u << (5 * (vb - kMarkL));
+                        vb = D[ib];
+                    }
+                }
+                D[a0] = (IdxT)va;
+                D[b0] = (IdxT)vb;
+            }
+            if (e < nref) {
                 const uint32_t v = refs[e];
                 D[v] = (IdxT)chase<IdxT>(D, v, D[v]);
             }
@@ -1792,10 +1811,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kSlow ?
 
 // Longest-first request order: requests are binned by their work (symbols
 // to decode plus output voxels / 8) on a log scale with 8 bins per octave
-// (the bits after the leading one), largest first, and laid out bin by bin;
-// the order within a bin is arbitrary.  Two launches of many workgroups:
-// order_count adds up the bin sizes, order_place gives each request its
-// position (exclusive scan of the sizes plus a per-bin cursor).
+// (the bits after the leading one), largest first; the order within a bin
+// is arbitrary.  Two launches of many workgroups: order_count adds up the
+// bin sizes, order_place gives each request its rank (exclusive scan of
+// the sizes plus a per-bin cursor).  The ranks are laid out for the front
+// kernel's fixed assignment, in which round k of its W waves takes
+// positions kW .. kW + W - 1: odd rounds run in reverse (snake order), so
+// that the wave with the largest brick of one round gets the smallest of
+// the next (a partial last round keeps its ranks).
 constexpr int kBins = 128;
 constexpr uint32_t kOrderWords = 2 * kBins + 8;   // bin sizes, bin cursors, done counter
 constexpr uint32_t kSmallWords = kOrderWords + 8; // then the launch counters
@@ -1824,7 +1847,7 @@ __global__ __launch_bounds__(256) void order_count(DecodeArgs a, uint32_t *cnt) 
 }
 // same grid as order_count; the last workgroup to finish clears the sizes,
 // cursors and its done counter for the next launch
-__global__ __launch_bounds__(256) void order_place(DecodeArgs a, uint32_t *small, uint32_t *order) {
+__global__ __launch_bounds__(256) void order_place(DecodeArgs a, uint32_t *small, uint32_t *order, uint32_t W) {
     static_assert(kBins == 128, "two waves scan the bin sizes");
     __shared__ uint32_t off[kBins], h[kBins], base[kBins], tot0, last;
     uint32_t *cnt = glob(small), *cur = cnt + kBins, *done = cnt + 2 * kBins;
@@ -1849,7 +1872,10 @@ __global__ __launch_bounds__(256) void order_place(DecodeArgs a, uint32_t *small
     __syncthreads();
     for (uint32_t r = blockIdx.x * 256 + tid; r < a.n; r += gridDim.x * 256) {
         const uint32_t b = work_bin(a, r);
-        order[off[b] + base[b] + atomicAdd(&h[b], 1u)] = r;
+        uint32_t pos = off[b] + base[b] + atomicAdd(&h[b], 1u);
+        const uint32_t rnd = pos / W, w = pos - rnd * W;
+        if ((rnd & 1u) && (uint64_t)rnd * W + W <= a.n) pos = rnd * W + (W - 1 - w);
+        order[pos] = r;
     }
     __syncthreads();
     if (tid == 0) last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
@@ -2445,10 +2471,12 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
             if (slow) hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(1), dim3(64 * kWavesLeafG), lds_g, s, b, lb);
         }
     } else {
-        if (lpt) {
+        // with at most one request per front wave the order changes nothing
+        if (lpt && n > grid_a * (uint32_t)waves_a) {
             const uint32_t grid_o = std::min(256u, (n + 255) / 256);
             hipLaunchKernelGGL(order_count, dim3(grid_o), dim3(256), 0, s, a, B->small);
-            hipLaunchKernelGGL(order_place, dim3(grid_o), dim3(256), 0, s, a, B->small, B->order);
+            hipLaunchKernelGGL(order_place, dim3(grid_o), dim3(256), 0, s, a, B->small, B->order,
+                               grid_a * (uint32_t)waves_a);
             la.order = B->order;
         }
         go_a(a, la, grid_a);
