@@ -249,12 +249,11 @@ int csv_output_elems_log2(uint32_t brick_log2, const uint8_t *lods_host, uint32_
  *                i is written at i * (32 >> lod_scalar)^3 (requires lods NULL)
  *   out          device, uint32 destination of the decoded blocks
  * Decodes every brick bit-exactly: the result is level L_lod of the brick's
- * resolution pyramid.  Two persistent launches that take requests from
- * device work counters (or by static round robin, per the launch shape): an
- * entropy decoder that also replays levels 4..max(lod, 1) (a wavefront per
- * brick, many per compute unit; Sec. 3.3, Sec. 3.2) and leaves level 1 and
- * the leaf-level symbols of each full-LOD brick in a pool buffer, then the
- * leaf-level replay and output (an 8-wavefront workgroup per brick; Alg. 1),
+ * resolution pyramid.  Two persistent launches: an entropy decoder that
+ * also replays levels 4..max(lod, 1) (a wavefront per brick, many per
+ * compute unit; Sec. 3.3, Sec. 3.2) and leaves level 1 and the leaf-level
+ * symbols of each full-LOD brick in a pool buffer, then the leaf-level
+ * replay and output (an 8-wavefront workgroup per brick; Alg. 1),
  * plus a third launch for pools holding bricks whose leaf arrays may not
  * fit that workgroup's LDS.
  * Large batches are split into chunks that alternate between `stream` and
@@ -321,10 +320,13 @@ typedef struct {
                                160 KiB / groups_per_cu of LDS (rounded down to 4 KiB; bricks
                                whose arrays do not fit take a slower path through a global-memory
                                arena) */
-    int use_queue;          /* 1: waves / workgroups take requests from device work counters;
-                               0: static round robin */
-    int lpt_order;          /* 1: requests are first ordered longest-first (binned by log2 of their
-                               symbols + output voxels / 8; one small kernel before the decode) */
+    int use_queue;          /* front kernel: 1: waves take requests from a device work counter;
+                               0: static round robin (the leaf kernel always takes its bricks from
+                               a counter after a first fixed round) */
+    int lpt_order;          /* 1: requests are first ordered longest-first (binned by their symbols
+                               + output voxels / 8, 8 bins per octave; two small kernels before the
+                               decode) and laid out in snake rounds for the front kernel's round
+                               robin; skipped when each front wavefront gets at most one request */
     uint32_t chunks;        /* 1..64: the requests are split into this many consecutive chunks that
                                alternate between the caller's stream and a second stream the pool
                                keeps for it, so that the entropy decode of one chunk overlaps the
