@@ -1,9 +1,12 @@
 // GPU brick decoder for gfx950 and the device pool that feeds it.
 //
 // A decode of n requests (brick, level of detail t; Sec. 3.4, Alg. 1) is
-// two persistent launches that take requests from device work counters:
+// two persistent launches (large batches: per chunk of requests, the chunks
+// alternating between two streams):
 //
-// A. front kernel: one wavefront per brick, 16 per CU, 8 KB of LDS each.
+// A. front kernel: one wavefront per brick, 16 per CU, 8 KB of LDS each;
+//    requests by round robin (optionally in longest-first order) or from a
+//    work counter.
 //    - Entropy decode (Sec. 3.3).  The W interleaved states run in
 //      lockstep, one per lane; a renormalising lane takes its 16-bit word at
 //      the stream cursor plus the number of lower lanes that renormalise too
@@ -22,10 +25,12 @@
 //    - t >= 1: the level-t block goes through the palette to the output.
 //      t = 0: L_1, its expansion bits and the list of expanded L_1 nodes go
 //      to the slot and the request joins the leaf list.
-// B. leaf kernel: one 4-wave workgroup per brick of the leaf list, several
-//    per CU: L_1, the leaf nibbles and the palette staged in LDS; leaf values
-//    kept only for the expanded L_1 nodes (found by a popcount rank over the
-//    expansion bitmask); chains resolved in three independent rounds; the
+// B. leaf kernel: one 8-wave workgroup per brick of the leaf list, 3 per CU
+//    by default, bricks from a work counter: L_1, the leaf nibbles and the
+//    palette staged in LDS (loaded into registers while the previous brick
+//    was replayed); the leaf level as a dense 32^3 byte array, every voxel
+//    first its L_1 node's index, the children of expanded nodes written over
+//    it; same-level references listed, then each followed to its value; the
 //    32^3 block written through the palette as dense rows of 16-byte stores.
 //    Bricks whose arrays do not fit the LDS arena use the same code on an
 //    arena in global memory.
