@@ -45,7 +45,7 @@ enum {
                           written upsampled 2x */
 };
 
-#define CSV_ABI_VERSION 2u
+#define CSV_ABI_VERSION 3u
 uint32_t csv_abi_version(void);
 
 /* Human-readable name of a CSV_E* code (static string). */
@@ -282,6 +282,22 @@ int csv_decode_bricks(const csv_pool *pool, const uint32_t *brick_ids, const uin
 int csv_decode_bricks_status(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
                              uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n, uint32_t *out,
                              void *stream, int32_t *status);
+
+/* csv_decode_bricks for a request list whose length is known only on the
+ * device (Sec. 4.1: a frame's bricks to decode, found by a kernel):
+ *   n_max   requests the arrays hold (host; bounds the launch and the
+ *           intermediate buffers)
+ *   n_dev   device uint32: the kernels decode requests 0 .. min(n_max,
+ *           *n_dev) - 1, reading the count when they start; the output of
+ *           the other requests is not written
+ * Nothing waits for the device, so the call can be captured in a graph
+ * once the stream's buffers are sized for n_max (a first call outside the
+ * capture).  One launch pair on `stream` (no chunks, no longest-first
+ * order).  Pools of other brick sizes or raw nibbles: CSV_EINVAL.  Other
+ * arguments and errors as csv_decode_bricks. */
+int csv_decode_bricks_devcount(const csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
+                               uint32_t lod_scalar, const uint64_t *out_offsets, uint32_t n_max,
+                               const uint32_t *n_dev, uint32_t *out, void *stream);
 
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): csv_decode_bricks
@@ -555,16 +571,25 @@ int csv_frame_cache_create(csv_pool *pool, uint64_t cache_bytes, uint32_t max_re
  * decoded into the cache on `stream` and slots[i] (device uint64[n]) will
  * hold the element offset of request i's block in csv_frame_cache_data (the
  * (32 >> lod)^3 labels in x-fastest order), or UINT64_MAX for LOD 5,
- * invisible or unknown requests.  The call waits for the stream once (the
- * number of bricks to decode goes to the host between the cache update and
- * the decode).  Frames of one cache run one at a time.  *stats (may be NULL)
- * describes the frame.  Errors: CSV_EINVAL (null pointers, n above
- * max_requests), CSV_ENOMEM (the frame's distinct bricks alone exceed the
- * cache: nothing is cached, every slot UINT64_MAX), CSV_EHIP.
+ * invisible or unknown requests.  Frames of one cache run one at a time.
+ * With stats (not NULL) the call waits for the stream once (the frame state
+ * goes to the host between the cache update and the decode) and *stats
+ * describes the frame.  With stats NULL nothing waits for the device: the
+ * decode takes the number of bricks from device memory
+ * (csv_decode_bricks_devcount), so the frame can be captured in a graph;
+ * csv_frame_cache_last_stats gives its statistics later.  Errors:
+ * CSV_EINVAL (null pointers, n above max_requests), CSV_ENOMEM (with stats:
+ * the frame's distinct bricks alone exceed the cache: nothing is cached,
+ * every slot UINT64_MAX; without stats the same frame returns CSV_OK and
+ * csv_frame_cache_last_stats reports CSV_ENOMEM), CSV_EHIP.
  */
 int csv_frame_cache_frame(csv_frame_cache *cache, const uint32_t *brick_ids, const uint8_t *lods, uint32_t n,
                           const uint32_t *visible_bits, uint32_t n_label_bits, uint64_t *slots, void *stream,
                           csv_frame_stats *stats);
+/* Statistics of the cache's last frame (waits for all work on the device).
+ * Returns CSV_ENOMEM if that frame did not fit (see csv_frame_cache_frame),
+ * else CSV_OK; CSV_EINVAL for null pointers, CSV_EHIP. */
+int csv_frame_cache_last_stats(csv_frame_cache *cache, csv_frame_stats *stats);
 /* Device address of the cache memory (uint32 labels). */
 uint32_t *csv_frame_cache_data(csv_frame_cache *cache);
 /* Copy n labels from element elem_offset of the cache to host memory (synchronous,

@@ -124,6 +124,7 @@ def lib():
         L.csv_output_bytes.argtypes = [vp, u32, vp, ctypes.POINTER(u64)]
         L.csv_output_elems_log2.argtypes = [u32, vp, u32, vp, ctypes.POINTER(u64)]
         L.csv_decode_bricks_status.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, vp]
+        L.csv_decode_bricks_devcount.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, vp]
         for f in ("csv_decode_bricks", "csv_decode_bricks_plain"):
             getattr(L, f).argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
         L.csv_decode_bricks_noalloc.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp]
@@ -157,8 +158,9 @@ def lib():
         L.csv_frame_cache_data.restype = vp
         L.csv_frame_cache_data.argtypes = [vp]
         L.csv_frame_cache_read.argtypes = [vp, u64, u64, vp]
+        L.csv_frame_cache_last_stats.argtypes = [vp, ctypes.POINTER(FrameStats)]
         L.csv_frame_cache_destroy.argtypes = [vp]
-        if L.csv_abi_version() != 2:
+        if L.csv_abi_version() != 3:
             raise RuntimeError("libcsv.so ABI mismatch")
         _lib = L
     return _lib
@@ -329,6 +331,14 @@ class Pool:
             _chk(lib().csv_decode_bricks_plain(*args), "csv_decode_bricks_plain")
         else:
             _chk(lib().csv_decode_bricks(*args), "csv_decode_bricks")
+
+    def decode_devcount(self, ids, out, n_dev, lods=None, lod=0, out_offsets=None, stream=None):
+        """decode() of requests 0 .. min(ids.numel(), n_dev[0]) - 1, the count
+        read on the device from `n_dev` (int32/uint32 cuda tensor) by the
+        kernels (csv_decode_bricks_devcount); nothing waits for the device."""
+        a = self._args(ids, out, lods, lod, out_offsets, stream)
+        _chk(lib().csv_decode_bricks_devcount(*a[:6], ctypes.c_void_p(n_dev.data_ptr()), *a[6:]),
+             "csv_decode_bricks_devcount")
 
     def decode_noalloc(self, ids, out, lods=None, lod=0, out_offsets=None, stream=None):
         """decode() through csv_decode_bricks_noalloc: no device allocation;
@@ -518,10 +528,12 @@ class FrameCache:
         _chk(lib().csv_frame_cache_create(pool._p, int(cache_bytes), int(max_requests), ctypes.byref(self._c)),
              "csv_frame_cache_create")
 
-    def frame(self, ids, lods, visible_bits=None, n_label_bits: int = 0, slots=None, stream=None):
+    def frame(self, ids, lods, visible_bits=None, n_label_bits: int = 0, slots=None, stream=None,
+              stats: bool = True):
         """ids (int32/uint32 CUDA tensor), lods (uint8 CUDA tensor); returns
         (slots int64 CUDA tensor: element offsets in data(), -1 if not stored,
-        stats dict)."""
+        stats dict).  stats=False: nothing waits for the device and the dict
+        is None (last_stats() reads it later)."""
         import torch
         n = ids.numel()
         if slots is None:
@@ -530,8 +542,16 @@ class FrameCache:
         vb = ctypes.c_void_p(visible_bits.data_ptr()) if visible_bits is not None else None
         _chk(lib().csv_frame_cache_frame(self._c, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(lods.data_ptr()),
                                          n, vb, int(n_label_bits), ctypes.c_void_p(slots.data_ptr()),
-                                         _stream_handle(stream), ctypes.byref(st)), "csv_frame_cache_frame")
-        return slots, {f: getattr(st, f) for f, _ in FrameStats._fields_}
+                                         _stream_handle(stream), ctypes.byref(st) if stats else None),
+             "csv_frame_cache_frame")
+        return slots, ({f: getattr(st, f) for f, _ in FrameStats._fields_} if stats else None)
+
+    def last_stats(self):
+        """Statistics of the last frame (waits for the device); raises
+        CsvError(CSV_ENOMEM) if that frame did not fit."""
+        st = FrameStats()
+        _chk(lib().csv_frame_cache_last_stats(self._c, ctypes.byref(st)), "csv_frame_cache_last_stats")
+        return {f: getattr(st, f) for f, _ in FrameStats._fields_}
 
     def data_ptr(self) -> int:
         """Device address of the cache memory (uint32 labels)."""

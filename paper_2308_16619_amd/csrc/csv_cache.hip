@@ -11,9 +11,11 @@
 //
 // One frame = mark (dedupe, hits, misses per block size), evict (a scan of
 // all (brick, LOD) keys), assign (one workgroup: stacks, top, rebuild),
-// then the decode of the assigned bricks into their blocks by
-// csv_decode_bricks, and the requests' slots.  The host reads one small
-// record (how many bricks to decode) between assign and decode.
+// then the decode of the assigned bricks into their blocks, and the
+// requests' slots.  With statistics requested, the host reads the frame
+// state (how many bricks to decode, counts) between assign and decode;
+// without, the decode reads the number of bricks from device memory
+// (csv_decode_bricks_devcount) and nothing waits for the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -195,7 +197,7 @@ struct csv_frame_cache {
     CacheDev d{};
     uint8_t *vis = nullptr;    // per request: visibility mask
     FrameState *h_st = nullptr;  // pinned copy of the frame state
-    uint32_t frame = 0;
+    uint32_t last_n = 0;         // requests of the last frame
 };
 
 extern "C" {
@@ -247,6 +249,22 @@ int csv_frame_cache_create(csv_pool *pool, uint64_t cache_bytes, uint32_t max_re
     return CSV_OK;
 }
 
+static void fill_stats(const csv_frame_cache *c, const FrameState &st, csv_frame_stats *stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->frame = st.frame;
+    stats->requests = c->last_n;
+    for (uint32_t t = 0; t < kLods; t++) {
+        stats->distinct += st.n_uniq[t];
+        stats->new_entries += st.n_miss[t];
+    }
+    stats->decoded = st.error ? 0 : st.n_dec;
+    stats->hits = st.error ? 0 : stats->distinct - st.n_dec;
+    stats->evicted = st.evicted;
+    stats->rebuilt = st.rebuilt;
+    stats->used_bytes = st.top * 32;
+    stats->capacity_bytes = c->cap_elems * 32;
+}
+
 int csv_frame_cache_frame(csv_frame_cache *c, const uint32_t *ids, const uint8_t *lods, uint32_t n,
                           const uint32_t *visible_bits, uint32_t n_label_bits, uint64_t *slots, void *stream,
                           csv_frame_stats *stats) {
@@ -266,34 +284,41 @@ int csv_frame_cache_frame(csv_frame_cache *c, const uint32_t *ids, const uint8_t
     const uint64_t nk = (uint64_t)c->n_bricks * kLods;
     hipLaunchKernelGGL(evict_kernel, dim3((uint32_t)std::min<uint64_t>((nk + 255) / 256, 4096)), dim3(256), 0, s, d);
     hipLaunchKernelGGL(assign_kernel, dim3(1), dim3(1024), 0, s, d);
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(c->h_st, d.st, sizeof(FrameState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipGetLastError() != hipSuccess) return CSV_EHIP;
+    c->last_n = n;
+    if (!stats) {
+        // no round trip to the host: the decode reads the number of bricks
+        // from the frame state (0 when the frame does not fit)
+        int rc = CSV_OK;
+        if (n) rc = csv_decode_bricks_devcount(c->pool, d.dec_ids, d.dec_lods, 0, d.dec_off, n, &d.st->n_dec,
+                                               c->data, s);
+        if (n) hipLaunchKernelGGL(slots_kernel, dim3(gr), dim3(256), 0, s, d, ids, lods, vis, n, slots);
+        if (hipGetLastError() != hipSuccess && !rc) rc = CSV_EHIP;
+        return rc;
+    }
+    if (hipMemcpyAsync(c->h_st, d.st, sizeof(FrameState), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return CSV_EHIP;
     const FrameState st = *c->h_st;
-    c->frame = st.frame;
     int rc = CSV_OK;
     if (!st.error && st.n_dec)
         rc = csv_decode_bricks(c->pool, d.dec_ids, d.dec_lods, 0, d.dec_off, st.n_dec, c->data, s);
     if (n) hipLaunchKernelGGL(slots_kernel, dim3(gr), dim3(256), 0, s, d, ids, lods, vis, n, slots);
     if (hipGetLastError() != hipSuccess && !rc) rc = CSV_EHIP;
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->frame = st.frame;
-        stats->requests = n;
-        for (uint32_t t = 0; t < kLods; t++) {
-            stats->distinct += st.n_uniq[t];
-            stats->new_entries += st.n_miss[t];
-        }
-        stats->decoded = st.error ? 0 : st.n_dec;
-        stats->hits = st.error ? 0 : stats->distinct - st.n_dec;
-        stats->evicted = st.evicted;
-        stats->rebuilt = st.rebuilt;
-        stats->used_bytes = st.top * 32;
-        stats->capacity_bytes = c->cap_elems * 32;
-    }
+    fill_stats(c, st, stats);
     if (!rc && st.error) rc = CSV_ENOMEM;
     return rc;
+}
+
+int csv_frame_cache_last_stats(csv_frame_cache *c, csv_frame_stats *stats) {
+    if (!c || !stats) return CSV_EINVAL;
+    DeviceGuard g(c->device);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(c->h_st, c->d.st, sizeof(FrameState), hipMemcpyDeviceToHost) != hipSuccess)
+        return CSV_EHIP;
+    const FrameState st = *c->h_st;
+    fill_stats(c, st, stats);
+    return st.error ? CSV_ENOMEM : CSV_OK;
 }
 
 uint32_t *csv_frame_cache_data(csv_frame_cache *c) { return c ? c->data : nullptr; }

@@ -99,6 +99,7 @@ struct DecodeArgs {
     const uint64_t *out_off;
     uint32_t *out;
     uint32_t n;
+    const uint32_t *n_dev;  // device request count (the launch decodes min(n, *n_dev)), or nullptr
     int *err;  // [0] first error code, [1] brick id (or request index)
     // pools with level-0 detail in host memory (else nullptr): per brick the
     // word dwords held in the device record (0xFFFFFFFF: all of them) and the
@@ -1071,6 +1072,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     const uint32_t L = lane(), wave = uniform(threadIdx.x >> 6);
     uint8_t *wl = smem + align16(4 * l.lut_lds_words) + wave * kWaveLds;
     const uint32_t wid = blockIdx.x * WPG + wave;
+    const uint32_t n_req = a.n_dev ? min(a.n, ld_s(a.n_dev)) : a.n;
     // With a work counter, each request is taken one brick ahead (lane 0)
     // and its value read at the end of the brick before: a read at the top
     // of a brick would wait behind the previous brick's stores (on gfx9 one
@@ -1089,7 +1091,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
             if (L == 0) taken = atomicInc(l.queue, 0xFFFFFFFFu);
         }
         const uint32_t req = l.base + (l.queue ? cur : wid + k * gridDim.x * WPG);
-        if (req >= a.n) break;
+        if (req >= n_req) break;
         const uint32_t rq = l.order ? ld_s(l.order + req) : req;
         phase_mark(rq, 0);
         Hdr h;
@@ -2310,7 +2312,8 @@ uint32_t ref_list_cap() {
 
 int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar, const uint64_t *out_off,
                uint32_t n, uint32_t *out, void *stream, bool plain, int waves_a, uint32_t groups_b, bool queue,
-               bool lpt, LaunchBufs *fixed, uint32_t *words_out, int *req_err, uint32_t rq_base = 0) {
+               bool lpt, LaunchBufs *fixed, uint32_t *words_out, int *req_err, uint32_t rq_base = 0,
+               const uint32_t *n_dev = nullptr) {
     if (!pool || (n && (!ids || !out))) return CSV_EINVAL;
     if (!lods && lod_scalar > (uint32_t)kLog2) return CSV_ERANGE;
     if (lods && !out_off) return CSV_EINVAL;
@@ -2328,7 +2331,7 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     if (pool->generic) {
         // other brick sizes and raw nibbles: the generic decoder, one
         // workgroup per brick (no launch shape, no fixed buffers)
-        if (fixed || words_out) return CSV_EINVAL;
+        if (fixed || words_out || n_dev) return CSV_EINVAL;
         // 8 workgroups per CU (few registers and 112 bytes of LDS each), 4 for
         // 64^3 bricks (1.9 MB of scratch per workgroup)
         const uint32_t cu = (uint32_t)std::max(1, pool->n_cu);
@@ -2395,6 +2398,7 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     a.out_off = out_off;
     a.out = out;
     a.n = n;
+    a.n_dev = n_dev;
     a.err = pool->d_err;
     a.pfx_dw = pool->any_split ? pool->d_pfx_dw : nullptr;
     a.sfx = pool->any_split ? pool->d_sfx : nullptr;
@@ -2476,8 +2480,9 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
             if (slow) hipLaunchKernelGGL((leaf_kernel<kWavesLeafG, true>), dim3(1), dim3(64 * kWavesLeafG), lds_g, s, b, lb);
         }
     } else {
-        // with at most one request per front wave the order changes nothing
-        if (lpt && n > grid_a * (uint32_t)waves_a) {
+        // with at most one request per front wave the order changes nothing;
+        // with a device-side count the order kernels would not know it
+        if (lpt && !n_dev && n > grid_a * (uint32_t)waves_a) {
             const uint32_t grid_o = std::min(256u, (n + 255) / 256);
             hipLaunchKernelGGL(order_count, dim3(grid_o), dim3(256), 0, s, a, B->small);
             hipLaunchKernelGGL(order_place, dim3(grid_o), dim3(256), 0, s, a, B->small, B->order,
@@ -3017,6 +3022,16 @@ int csv_decode_bricks(const csv_pool *pool, const uint32_t *ids, const uint8_t *
     return launch(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n, out, stream, false,
                   sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, sh.lpt_order != 0, nullptr,
                   nullptr, nullptr, sh.chunks);
+}
+
+int csv_decode_bricks_devcount(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,
+                               const uint64_t *out_off, uint32_t n_max, const uint32_t *n_dev, uint32_t *out,
+                               void *stream) {
+    if (!pool || !n_dev) return CSV_EINVAL;
+    const csv_shape sh = current_shape(pool, lods, lod_scalar, n_max);
+    return launch_one(const_cast<csv_pool *>(pool), ids, lods, lod_scalar, out_off, n_max, out, stream, false,
+                      sh.waves_per_group, (uint32_t)sh.groups_per_cu, sh.use_queue != 0, false, nullptr, nullptr,
+                      nullptr, 0, n_dev);
 }
 
 int csv_decode_bricks_noalloc(const csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_t lod_scalar,

@@ -418,3 +418,46 @@ def test_graph_replays(csvlib, orc, cfg2, shape):
         pool.decode(d_ids[:7].contiguous(), torch.empty(7 * 32768, dtype=torch.int32, device="cuda"), lod=0)
         torch.cuda.synchronize()
     g.close()
+
+
+@pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (8, 3, 1, 1, 4)])
+def test_device_count_decodes_a_prefix(csvlib, orc, cfg1, cfg2, shape):
+    # csv_decode_bricks_devcount: the kernels decode min(n_max, *n_dev)
+    # requests and leave the other outputs untouched (a lpt or chunked shape
+    # runs as one launch pair without the order)
+    torch = torch_cuda()
+    pool = csvlib.Pool()
+    pool.add_volume(cfg1[1])
+    pool.add_volume(cfg2[1])
+    pool.set_shape(shape)
+    n_max = 2500
+    ids, lods = mixed_requests(31, n_max, 8 + 4096)
+    off, tot = csvlib.output_offsets(lods)
+    ref = [orc.decode_brick(cfg1[1], int(i), int(t)).ravel() if i < 8 else
+           orc.decode_brick(cfg2[1], int(i) - 8, int(t)).ravel() for i, t in zip(ids, lods)]
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    d_lods = torch.from_numpy(lods.copy()).cuda()
+    d_off = torch.from_numpy(off.view(np.int64)).cuda()
+    for k in (0, 1, 1777, n_max, 10 ** 6):
+        log("device count %d of %d, shape %s" % (k, n_max, shape))
+        out = torch.full((tot,), -1, dtype=torch.int32, device="cuda")
+        cnt = torch.tensor([k], dtype=torch.int32, device="cuda")
+        pool.decode_devcount(d_ids, out, cnt, lods=d_lods, out_offsets=d_off)
+        torch.cuda.synchronize()
+        assert pool.last_error() == (0, 0)
+        got = out.cpu().numpy().view(np.uint32)
+        m = min(k, n_max)
+        end = int(off[m]) if m < n_max else tot
+        np.testing.assert_array_equal(got[:end], np.concatenate(ref[:m]) if m else got[:0])
+        assert (got[end:] == 0xFFFFFFFF).all()
+    # packed outputs at one LOD
+    g = 32 >> 1
+    out = torch.full((300 * g ** 3,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.tensor([123], dtype=torch.int32, device="cuda")
+    pool.decode_devcount(d_ids[:300].contiguous(), out, cnt, lod=1)
+    torch.cuda.synchronize()
+    want = np.concatenate([orc.decode_brick(cfg1[1], int(i), 1).ravel() if i < 8 else
+                           orc.decode_brick(cfg2[1], int(i) - 8, 1).ravel() for i in ids[:123]])
+    got = out.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got[:123 * g ** 3], want)
+    assert (got[123 * g ** 3:] == 0xFFFFFFFF).all()

@@ -96,7 +96,9 @@ def frames(n_bricks, n_frames, seed):
     return out
 
 
-def run_frames(csv, orc, blobs, labels, cap_bytes, n_frames=8, seed=3, density=None, expect_error=False):
+def run_frames(csv, orc, blobs, labels, cap_bytes, n_frames=8, seed=3, density=None, expect_error=False, sync=True):
+    """sync False: frames without statistics (no wait for the device), the
+    statistics read afterwards with last_stats()."""
     torch = torch_cuda()
     pool = csv.Pool()
     for b in blobs:
@@ -122,13 +124,23 @@ def run_frames(csv, orc, blobs, labels, cap_bytes, n_frames=8, seed=3, density=N
         want = model.frame(keys)
         log("frame %d: %d requests, %d distinct keys, cache %d bytes" % (f + 1, len(ids), len(keys), cap_bytes))
         if want["error"]:
-            with pytest.raises(csv.CsvError) as e:
-                cache.frame(d_ids, d_lods, bits, n_lab if bits is not None else 0)
+            if sync:
+                with pytest.raises(csv.CsvError) as e:
+                    cache.frame(d_ids, d_lods, bits, n_lab if bits is not None else 0)
+            else:
+                slots, st = cache.frame(d_ids, d_lods, bits, n_lab if bits is not None else 0, stats=False)
+                assert st is None
+                with pytest.raises(csv.CsvError) as e:
+                    cache.last_stats()
+                assert (slots.cpu().numpy() == -1).all()
             assert e.value.code == csv.CSV_ENOMEM
             assert expect_error
             pool.last_error()
             continue
-        slots, st = cache.frame(d_ids, d_lods, bits, n_lab if bits is not None else 0)
+        slots, st = cache.frame(d_ids, d_lods, bits, n_lab if bits is not None else 0, stats=sync)
+        if not sync:
+            assert st is None
+            st = cache.last_stats()
         torch.cuda.synchronize()
         pool.last_error()  # unknown ids are reported by the visibility test; the cache skips them
         assert st["frame"] == f + 1 and st["requests"] == len(ids)
@@ -184,6 +196,73 @@ def test_frames_mixed_rebuilds_and_overflows(setup, orc):
     # frames start from an empty cache
     st = run_frames(csv, orc, blobs, labels, 6400 << 10, n_frames=10, seed=7, expect_error=True)
     assert any(s["rebuilt"] for s in st) and len(st) < 10
+
+
+@pytest.mark.parametrize("cap,n_frames,seed,density,err", [(256 << 20, 8, 5, 0.002, False), (6912 << 10, 10, 7, None, False),
+                                                       (6400 << 10, 10, 7, None, True)])
+def test_frames_without_stats(setup, orc, cap, n_frames, seed, density, err):
+    # the same frames with the decode's count read on the device: same
+    # blocks, same counts (read afterwards), rebuilds and overflows included
+    csv, blobs, labels = setup
+    st = run_frames(csv, orc, blobs, labels, cap, n_frames=n_frames, seed=seed, density=density, expect_error=err,
+                    sync=False)
+    assert st
+
+
+def test_frame_graph_replays(setup, orc):
+    # a frame without statistics captured in a graph and replayed for new
+    # request lists, each replay checked against the same frame run eagerly
+    # on a second cache (with eager work and synchronisation in between)
+    csv, blobs, labels = setup
+    torch = torch_cuda()
+    pool = csv.Pool()
+    for b in blobs:
+        pool.add_volume(b)
+    nb = len(labels)
+    seq = frames(nb, 5, seed=11)
+    s = torch.cuda.Stream()
+    eager = csv.FrameCache(pool, 64 << 20, 512)
+    graph = csv.FrameCache(pool, 64 << 20, 512)
+    ids_g = torch.from_numpy(seq[0][0].view(np.int32)).cuda()
+    lods_g = torch.from_numpy(seq[0][1]).cuda()
+    slots_g = torch.empty(len(seq[0][0]), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        # the first frame outside the capture sizes the stream's buffers
+        log("graph: frame 1 eager on both caches")
+        graph.frame(ids_g, lods_g, slots=slots_g, stream=s, stats=False)
+        eager.frame(ids_g, lods_g, stream=s, stats=False)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        graph.frame(ids_g, lods_g, slots=slots_g, stream=s, stats=False)
+    for f in range(1, 5):
+        ids, lods = seq[f]
+        ids_g.copy_(torch.from_numpy(ids.view(np.int32)))
+        lods_g.copy_(torch.from_numpy(lods))
+        torch.cuda.synchronize()
+        log("graph: replay for frame %d" % (f + 1))
+        g.replay()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            slots_e, _ = eager.frame(ids_g.clone(), lods_g.clone(), stream=s, stats=False)
+        s.synchronize()
+        # block positions depend on the order in which the mark kernel's
+        # atomics list the misses, so the two caches agree on what is stored
+        # and on the counts, and each block holds its brick
+        sg, se = slots_g.cpu().numpy(), slots_e.cpu().numpy()
+        np.testing.assert_array_equal(sg >= 0, se >= 0)
+        st_g, st_e = graph.last_stats(), eager.last_stats()
+        assert st_g == st_e and st_g["frame"] == f + 1
+        for i, t, sl, sl_e in zip(ids.tolist(), lods.tolist(), sg.tolist(), se.tolist()):
+            if sl >= 0:
+                n = (32 >> t) ** 3
+                ref = decode_ref(orc, blobs, int(i), int(t))
+                np.testing.assert_array_equal(graph.read(sl, n), ref)
+                np.testing.assert_array_equal(eager.read(sl_e, n), ref)
+    del g
+    graph.close()
+    eager.close()
 
 
 def test_frame_larger_than_cache(setup, orc):
