@@ -2355,12 +2355,12 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
         ga.lods = lods;
         ga.lod_scalar = lod_scalar;
         ga.out_off = out_off;
-        ga.out = out;
+        ga.out = reinterpret_cast<uint64_t>(out);
         ga.n = n;
         ga.err = pool->d_err;
         ga.req_err = req_err;
         ga.rq_base = rq_base;
-        ga.scratch = G->gen;
+        ga.scratch = reinterpret_cast<uint64_t>(G->gen);
         if (!plain) return csv::generic_launch(ga, groups, s) == hipSuccess ? CSV_OK : CSV_EHIP;
         // one launch per brick
         const uint64_t g1 = (1u << pool->brick_log2) >> (lods ? 0u : lod_scalar);
@@ -2369,7 +2369,7 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
             gi.ids = ids + i;
             gi.lods = lods ? lods + i : nullptr;
             gi.out_off = out_off ? out_off + i : nullptr;
-            gi.out = out_off ? out : out + (uint64_t)i * g1 * g1 * g1;
+            gi.out = reinterpret_cast<uint64_t>(out_off ? out : out + (uint64_t)i * g1 * g1 * g1);
             gi.n = 1;
             gi.req_err = req_err ? req_err + i : nullptr;
             gi.rq_base = rq_base + i;

@@ -91,9 +91,19 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, ui
     return before + x - v;
 }
 
+// A device address as a pointer into the global address space, so that the
+// accesses compile to global (not flat) instructions: a flat access also
+// counts on lgkmcnt, and the LDS waits of the block scans would wait for it.
+// The addresses travel as integers (kernel arguments, the request record in
+// LDS), so that nothing turns them back into generic pointers.
+template <class T>
+__device__ __forceinline__ T *gmem(uint64_t v) {
+    return (T *)(__attribute__((address_space(1))) T *)v;
+}
+
 struct GReq {
-    const uint32_t *rec;
-    uint32_t *dst;
+    uint64_t rec;  // record address
+    uint64_t dst;  // output address
     uint32_t P, W, nw, t, vol, id, raw, count;
     uint32_t cum[kMaxLog2];
     int err;           // first error found for this request
@@ -113,7 +123,7 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
     __shared__ uint32_t sh[kGT / 64];
     __shared__ int bad;
     const uint32_t tid = threadIdx.x;
-    uint8_t *base = a.scratch + (size_t)blockIdx.x * a.scratch_per_group;
+    uint8_t *base = gmem<uint8_t>(a.scratch + (uint64_t)blockIdx.x * a.scratch_per_group);
     uint8_t *sym = base;
     uint32_t *lev = reinterpret_cast<uint32_t *>(base + align256(a.sym_cap));
     uint8_t *flg = reinterpret_cast<uint8_t *>(lev) + align256(4 * all_nodes(N));
@@ -132,7 +142,7 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
             R.err = 0;
             R.fill = 0;
             R.count = 0;
-            R.dst = nullptr;
+            R.dst = 0;
             R.id = a.ids[rq];
             R.t = a.lods ? (uint32_t)a.lods[rq] : a.lod_scalar;
             if (R.t > N) {
@@ -140,13 +150,13 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
             } else {
                 const uint32_t G = (1u << N) >> R.t;
                 R.count = G * G * G;
-                R.dst = a.out + (a.out_off ? a.out_off[rq] : (uint64_t)rq * R.count);
+                R.dst = a.out + 4 * (a.out_off ? a.out_off[rq] : (uint64_t)rq * R.count);
                 if (R.id >= a.n_bricks) {
                     R.err = CSV_ERANGE;
                 } else {
-                    const uint32_t *rec = reinterpret_cast<const uint32_t *>(a.rec_ptr[R.id]);
+                    const uint32_t *rec = gmem<const uint32_t>(a.rec_ptr[R.id]);
                     const uint64_t size = a.rec_size[R.id];
-                    R.rec = rec;
+                    R.rec = a.rec_ptr[R.id];
                     R.vol = a.rec_vol[R.id];
                     R.raw = a.vol_raw[R.vol];
                     R.P = rec[0];
@@ -174,7 +184,7 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
         }
         __syncthreads();
         const uint32_t t = R.t, P = R.P, W = R.W;
-        const uint32_t *rec = R.rec;
+        const uint32_t *rec = gmem<const uint32_t>(R.rec);
         const uint32_t *pal = rec + hdr;
         if (R.err == 0 && R.fill == 0) {
             // 2. entropy decode of the first n symbols
@@ -343,7 +353,7 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
         if (R.err == 0 && !agree()) {
             const uint32_t G = (1u << N) >> t, lg = N - t;
             const uint32_t *lt = lev + level_off(N, t);
-            uint32_t *dst = R.dst;
+            uint32_t *dst = gmem<uint32_t>(R.dst);
             for (uint32_t v = tid; v < R.count; v += kGT) {
                 uint32_t label = R.fill_v;
                 if (!R.fill) {
@@ -359,7 +369,7 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
             if (tid == 0)
                 g_report(a, rq, R.err ? R.err : CSV_ECORRUPT,
                          (R.err == CSV_ERANGE) ? a.rq_base + rq : R.id);
-            for (uint32_t v = tid; v < R.count; v += kGT) R.dst[v] = 0u;
+            for (uint32_t v = tid; v < R.count; v += kGT) gmem<uint32_t>(R.dst)[v] = 0u;
         }
         __syncthreads();
     }

@@ -24,12 +24,12 @@ struct GenericArgs {
     const uint8_t *lods;
     uint32_t lod_scalar;
     const uint64_t *out_off;
-    uint32_t *out;
+    uint64_t out;              // device address of the uint32 output
     uint32_t n;
     int *err;                  // [0] first error code, [1] brick id or request index
     int *req_err;              // per-request status, or nullptr
     uint32_t rq_base;          // index of request 0 in the caller's batch
-    uint8_t *scratch;          // scratch_per_group bytes per workgroup
+    uint64_t scratch;          // device address: scratch_per_group bytes per workgroup
     uint64_t scratch_per_group;
     uint32_t sym_cap;          // symbols a workgroup's scratch holds
 };
