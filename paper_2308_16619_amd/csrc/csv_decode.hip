@@ -2347,6 +2347,8 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
         ga.rec_vol = pool->d_rec_vol;
         ga.luts = pool->d_luts;
         ga.lut_off = pool->d_lut_off;
+        // the tables in LDS when 8 workgroups per CU still fit
+        ga.lut_lds_words = 4 * pool->luts.size() <= 16 * 1024 ? (uint32_t)pool->luts.size() : 0u;
         ga.vol_bits = pool->d_bits;
         ga.vol_raw = pool->d_vol_raw;
         ga.n_bricks = (uint32_t)pool->rec_ptr.size();

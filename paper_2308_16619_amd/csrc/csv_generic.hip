@@ -122,7 +122,10 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
     __shared__ GReq R;
     __shared__ uint32_t sh[kGT / 64];
     __shared__ int bad;
+    extern __shared__ uint32_t glut[];  // the decode tables when a.lut_lds_words > 0
     const uint32_t tid = threadIdx.x;
+    for (uint32_t e = tid; e < a.lut_lds_words; e += kGT) glut[e] = a.luts[e];
+    __syncthreads();
     uint8_t *base = gmem<uint8_t>(a.scratch + (uint64_t)blockIdx.x * a.scratch_per_group);
     uint8_t *sym = base;
     uint32_t *lev = reinterpret_cast<uint32_t *>(base + align256(a.sym_cap));
@@ -195,42 +198,51 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
                 // a complete decode finds the last word's unused nibbles zero
                 if (tid == 0 && t == 0 && (R.cum[0] & 3) && (words[R.nw - 1] >> (4 * (R.cum[0] & 3))) != 0) bad = 1;
             } else if (tid < 64) {
-                const uint32_t L = tid, vol = R.vol;
-                const uint32_t sbits = a.vol_bits[vol], lutn = 1u << sbits, mask = lutn - 1u;
-                const uint32_t *lut = a.luts + a.lut_off[vol];
-                const uint32_t leaf = N >= 2 ? R.cum[1] : 0u;
-                uint32_t x = L < W ? rec[hdr + P + L] : 0u;
-                uint32_t cursor = 0;
-                bool fail = false;
-                const uint32_t steps = W ? (n + W - 1) / W : 0u;
-                for (uint32_t s = 0; s < steps; s++) {
-                    const uint32_t i = s * W + L;
-                    const bool act = L < W && i < n;
-                    bool need = false;
-                    uint32_t v = 0;
-                    if (act) {
-                        const uint32_t e = lut[(i >= leaf ? lutn : 0u) + (x & mask)];
-                        v = e & 15u;
-                        x = (e >> 20) * (x >> sbits) + ((e >> 8) & 0xFFFu);
-                        need = x < kRansLower;
+                // the rANS steps, with the decode tables in LDS or in global
+                // memory (two instantiations, so that each reads one address
+                // space)
+                auto rans = [&](auto luts) {
+                    const uint32_t L = tid, vol = R.vol;
+                    const uint32_t sbits = a.vol_bits[vol], lutn = 1u << sbits, mask = lutn - 1u;
+                    const auto lut = luts + a.lut_off[vol];
+                    const uint32_t leaf = N >= 2 ? R.cum[1] : 0u;
+                    uint32_t x = L < W ? rec[hdr + P + L] : 0u;
+                    uint32_t cursor = 0;
+                    bool fail = false;
+                    const uint32_t steps = W ? (n + W - 1) / W : 0u;
+                    for (uint32_t s = 0; s < steps; s++) {
+                        const uint32_t i = s * W + L;
+                        const bool act = L < W && i < n;
+                        bool need = false;
+                        uint32_t v = 0;
+                        if (act) {
+                            const uint32_t e = lut[(i >= leaf ? lutn : 0u) + (x & mask)];
+                            v = e & 15u;
+                            x = (e >> 20) * (x >> sbits) + ((e >> 8) & 0xFFFu);
+                            need = x < kRansLower;
+                        }
+                        const uint64_t bal = __ballot(need);
+                        const uint32_t cnt = (uint32_t)__popcll(bal);
+                        if (cursor + cnt > R.nw) {  // words past the end of the stream
+                            fail = true;
+                            break;
+                        }
+                        if (need) {
+                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                            x = (x << 16) | words[cursor + rank];
+                        }
+                        cursor += cnt;
+                        if (act) sym[i] = (uint8_t)v;
                     }
-                    const uint64_t bal = __ballot(need);
-                    const uint32_t cnt = (uint32_t)__popcll(bal);
-                    if (cursor + cnt > R.nw) {  // words past the end of the stream
-                        fail = true;
-                        break;
-                    }
-                    if (need) {
-                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                        x = (x << 16) | words[cursor + rank];
-                    }
-                    cursor += cnt;
-                    if (act) sym[i] = (uint8_t)v;
-                }
-                // a complete decode ends in the encoder's initial states with every word read
-                if (!fail && t == 0) fail = __ballot(L < W && x != kRansLower) != 0 || cursor != R.nw;
-                if (fail && L == 0) bad = 1;
+                    // a complete decode ends in the encoder's initial states with every word read
+                    if (!fail && t == 0) fail = __ballot(L < W && x != kRansLower) != 0 || cursor != R.nw;
+                    if (fail && L == 0) bad = 1;
+                };
+                if (a.lut_lds_words)
+                    rans((const __attribute__((address_space(3))) uint32_t *)glut);
+                else
+                    rans((const __attribute__((address_space(1))) uint32_t *)a.luts);
             }
             // 3. replay, levels N-1 .. t
             if (tid == 0) {
@@ -377,7 +389,7 @@ __global__ __launch_bounds__(kGT) void generic_kernel(GenericArgs a) {
 
 template <uint32_t N>
 hipError_t go(const GenericArgs &a, uint32_t groups, hipStream_t s) {
-    hipLaunchKernelGGL(generic_kernel<N>, dim3(groups), dim3(kGT), 0, s, a);
+    hipLaunchKernelGGL(generic_kernel<N>, dim3(groups), dim3(kGT), 4 * a.lut_lds_words, s, a);
     return hipGetLastError();
 }
 

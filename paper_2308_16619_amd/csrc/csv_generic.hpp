@@ -16,6 +16,7 @@ struct GenericArgs {
     const uint16_t *rec_vol;   // per brick: volume
     const uint32_t *luts;      // decode tables of all volumes (see lut_entry)
     const uint32_t *lut_off;   // per volume: first entry of its two tables
+    uint32_t lut_lds_words;    // words of luts copied to LDS per workgroup (0: read from global memory)
     const uint32_t *vol_bits;  // per volume: table precision
     const uint8_t *vol_raw;    // per volume: 1 if its symbols are stored as raw nibbles
     uint32_t n_bricks;
