@@ -45,7 +45,7 @@ enum {
                           written upsampled 2x */
 };
 
-#define CSV_ABI_VERSION 3u
+#define CSV_ABI_VERSION 4u
 uint32_t csv_abi_version(void);
 
 /* Human-readable name of a CSV_E* code (static string). */
@@ -581,11 +581,57 @@ int csv_frame_cache_create(csv_pool *pool, uint64_t cache_bytes, uint32_t max_re
  * CSV_EINVAL (null pointers, n above max_requests), CSV_ENOMEM (with stats:
  * the frame's distinct bricks alone exceed the cache: nothing is cached,
  * every slot UINT64_MAX; without stats the same frame returns CSV_OK and
- * csv_frame_cache_last_stats reports CSV_ENOMEM), CSV_EHIP.
+ * csv_frame_cache_last_stats reports CSV_ENOMEM), CSV_EHIP.  A cache over a
+ * pool that keeps level-0 detail in host memory takes its frames through
+ * csv_frame_cache_frame_detail (this call returns CSV_EINVAL).
  */
 int csv_frame_cache_frame(csv_frame_cache *cache, const uint32_t *brick_ids, const uint8_t *lods, uint32_t n,
                           const uint32_t *visible_bits, uint32_t n_label_bits, uint64_t *slots, void *stream,
                           csv_frame_stats *stats);
+
+/*
+ * Detail streaming in frames (Sec. 4.2) for caches over pools that keep
+ * level-0 detail in host memory (CSV_DETAIL_HOST).  A full-LOD request for
+ * a brick whose detail is not on the device, and whose full LOD is not
+ * cached, is served at LOD 1, the finest level in HBM: its slot holds the
+ * 16^3 block, served_lods[i] says 1, and the brick is listed as wanting its
+ * detail.  The next frame of the cache first uploads that detail, then the
+ * detail of predict_ids (device, uint32[n_predict], n_predict <= the
+ * cache's max_requests; e.g. the bricks close to the camera, most urgent
+ * first) that are not cached at full LOD after this frame, so that a
+ * predicted brick is decoded at full LOD in the first frame that requests
+ * it.  Uploads go through the pool's staging buffer; detail already there
+ * stays while the new detail fits behind it, else all of it is dropped
+ * first and the lists are staged from the start until the buffer is full.
+ * While the cache exists the pool's staged detail is the cache's: no other
+ * caller stages or releases detail on that pool, and its frames run on one
+ * stream (the staging of a frame follows the previous frame's work in
+ * stream order).  The lists reach the host after the frame's work; the
+ * next frame waits for them.  Not for stream capture.  Detail the cache
+ * staged stays staged after csv_frame_cache_destroy (csv_pool_release_detail
+ * drops it).
+ *   served_lods  device, uint8[n], or NULL: the LOD of the block slots[i]
+ *                points at (0xFF when slots[i] is UINT64_MAX)
+ *   stats, detail_stats  as csv_frame_cache_frame's stats; detail_stats
+ *                (may be NULL; needs stats) describes the frame's detail
+ * Other arguments and errors as csv_frame_cache_frame; on a cache over a
+ * pool without detail in host memory the call is csv_frame_cache_frame
+ * with served_lods.
+ */
+typedef struct {
+    uint32_t fallbacks;       /* bricks requested at full LOD and served at LOD 1 in this frame */
+    uint32_t wanted;          /* the previous frame's fallbacks */
+    uint32_t predicted;       /* bricks of the previous frame's predictions not cached at full LOD */
+    uint32_t staged;          /* of wanted + predicted (each brick once): detail on the device for this frame */
+    uint32_t released;        /* 1: the staged detail was dropped to make room */
+    uint32_t pad;
+    uint64_t uploaded_bytes;  /* detail uploaded for this frame (staging granules) */
+    uint64_t resident_bytes;  /* detail staged by the cache after the upload */
+} csv_frame_detail_stats;
+int csv_frame_cache_frame_detail(csv_frame_cache *cache, const uint32_t *brick_ids, const uint8_t *lods, uint32_t n,
+                                 const uint32_t *visible_bits, uint32_t n_label_bits, const uint32_t *predict_ids,
+                                 uint32_t n_predict, uint64_t *slots, uint8_t *served_lods, void *stream,
+                                 csv_frame_stats *stats, csv_frame_detail_stats *detail_stats);
 /* Statistics of the cache's last frame (waits for all work on the device).
  * Returns CSV_ENOMEM if that frame did not fit (see csv_frame_cache_frame),
  * else CSV_OK; CSV_EINVAL for null pointers, CSV_EHIP. */

@@ -70,6 +70,12 @@ class FrameStats(ctypes.Structure):
                 ("capacity_bytes", ctypes.c_uint64)]
 
 
+class FrameDetailStats(ctypes.Structure):
+    _fields_ = [("fallbacks", ctypes.c_uint32), ("wanted", ctypes.c_uint32), ("predicted", ctypes.c_uint32),
+                ("staged", ctypes.c_uint32), ("released", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("uploaded_bytes", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("cache_bytes", ctypes.c_uint64), ("inflight_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32)]
@@ -157,10 +163,13 @@ def lib():
         L.csv_frame_cache_frame.argtypes = [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(FrameStats)]
         L.csv_frame_cache_data.restype = vp
         L.csv_frame_cache_data.argtypes = [vp]
+        L.csv_frame_cache_frame_detail.argtypes = [vp, vp, vp, u32, vp, u32, vp, u32, vp, vp, vp,
+                                                   ctypes.POINTER(FrameStats), ctypes.POINTER(FrameDetailStats)]
+        L.csv_pool_detail_bytes.argtypes = [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u64)]
         L.csv_frame_cache_read.argtypes = [vp, u64, u64, vp]
         L.csv_frame_cache_last_stats.argtypes = [vp, ctypes.POINTER(FrameStats)]
         L.csv_frame_cache_destroy.argtypes = [vp]
-        if L.csv_abi_version() != 3:
+        if L.csv_abi_version() != 4:
             raise RuntimeError("libcsv.so ABI mismatch")
         _lib = L
     return _lib
@@ -297,6 +306,12 @@ class Pool:
 
     def release_detail(self, stream=None) -> None:
         _chk(lib().csv_pool_release_detail(self._p, _stream_handle(stream)), "csv_pool_release_detail")
+
+    def detail_bytes(self, brick_id: int) -> int:
+        """Staging bytes of a brick's level-0 detail (0: its record is whole in HBM)."""
+        b = ctypes.c_uint32()
+        _chk(lib().csv_pool_detail_bytes(self._p, int(brick_id), ctypes.byref(b), None), "csv_pool_detail_bytes")
+        return b.value
 
     def set_detail_staging(self, nbytes: int) -> None:
         _chk(lib().csv_pool_set_detail_staging(self._p, int(nbytes)), "csv_pool_set_detail_staging")
@@ -545,6 +560,33 @@ class FrameCache:
                                          _stream_handle(stream), ctypes.byref(st) if stats else None),
              "csv_frame_cache_frame")
         return slots, ({f: getattr(st, f) for f, _ in FrameStats._fields_} if stats else None)
+
+    def frame_detail(self, ids, lods, predict=None, visible_bits=None, n_label_bits: int = 0, slots=None,
+                     served=None, stream=None, stats: bool = True):
+        """A frame on a pool with level-0 detail in host memory: full-LOD
+        requests without detail on the device are served at LOD 1 and their
+        detail uploaded for the next frame, with the detail of `predict`
+        (int32/uint32 CUDA tensor of brick ids, most urgent first).  Returns
+        (slots, served LODs uint8 CUDA tensor, stats dict, detail stats
+        dict); both dicts are None with stats=False."""
+        import torch
+        n = ids.numel()
+        if slots is None:
+            slots = torch.empty(n, dtype=torch.int64, device=ids.device)
+        if served is None:
+            served = torch.empty(n, dtype=torch.uint8, device=ids.device)
+        st, ds = FrameStats(), FrameDetailStats()
+        vb = ctypes.c_void_p(visible_bits.data_ptr()) if visible_bits is not None else None
+        npred = predict.numel() if predict is not None else 0
+        pp = ctypes.c_void_p(predict.data_ptr()) if npred else None
+        _chk(lib().csv_frame_cache_frame_detail(
+            self._c, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(lods.data_ptr()), n, vb, int(n_label_bits),
+            pp, npred, ctypes.c_void_p(slots.data_ptr()), ctypes.c_void_p(served.data_ptr()), _stream_handle(stream),
+            ctypes.byref(st) if stats else None, ctypes.byref(ds) if stats else None), "csv_frame_cache_frame_detail")
+        if not stats:
+            return slots, served, None, None
+        return (slots, served, {f: getattr(st, f) for f, _ in FrameStats._fields_},
+                {f: getattr(ds, f) for f, _ in FrameDetailStats._fields_ if f != "pad"})
 
     def last_stats(self):
         """Statistics of the last frame (waits for the device); raises

@@ -16,11 +16,23 @@
 // state (how many bricks to decode, counts) between assign and decode;
 // without, the decode reads the number of bricks from device memory
 // (csv_decode_bricks_devcount) and nothing waits for the device.
+//
+// Detail streaming (Sec. 4.2), for pools that keep level-0 detail in host
+// memory: a full-LOD request for a brick whose detail is not on the device
+// and whose full LOD is not cached is served at LOD 1 (the finest level in
+// HBM) and the brick goes on the frame's list of wanted detail.  Both
+// options of the paper hide the resulting lag: the next frame uploads the
+// wanted detail first, then the detail of the bricks the caller predicted
+// (bricks close to the camera) that are not cached at full LOD, through
+// the pool's staging buffer, so that predicted bricks are decoded at full
+// LOD in the frame that first requests them.  The lists reach the host
+// after the frame's work, in stream order; the next frame reads them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "csv.h"
 
@@ -39,6 +51,7 @@ struct FrameState {
     uint32_t stack_top[kLods];
     uint64_t top;             // base elements handed out
     uint32_t n_dec, evicted, rebuilt, error;
+    uint32_t n_want;          // bricks served at LOD 1 for want of level-0 detail
 };
 
 struct CacheDev {
@@ -53,12 +66,25 @@ struct CacheDev {
     uint8_t *dec_lods;
     uint64_t *dec_off;
     FrameState *st;
+    // detail streaming (nullptr for pools without detail in host memory)
+    const uint8_t *det;   // per brick: bit 0 level-0 detail in host memory, bit 1 staged by this cache
+    uint32_t *want;       // n_req bricks whose full-LOD request was served at LOD 1
+    uint32_t *pred;       // n_req predicted bricks that need their detail uploaded (~0u: not)
 };
+
+constexpr uint8_t kSplit = 1, kStaged = 2;
+
+// a full-LOD request of a brick whose detail is in host memory and not
+// staged, when its full LOD is not cached
+__device__ __forceinline__ bool wants_detail(const CacheDev &c, uint32_t id) {
+    const uint8_t m = c.det[id];
+    return (m & kSplit) && !(m & kStaged) && c.index[id * kLods] == kNone64;
+}
 
 __global__ void begin_kernel(CacheDev c) {
     if (threadIdx.x == 0) {
         c.st->frame++;
-        c.st->n_dec = c.st->evicted = c.st->rebuilt = c.st->error = 0;
+        c.st->n_dec = c.st->evicted = c.st->rebuilt = c.st->error = c.st->n_want = 0;
     }
     if (threadIdx.x < kLods) {
         c.st->n_miss[threadIdx.x] = 0;
@@ -67,13 +93,22 @@ __global__ void begin_kernel(CacheDev c) {
 }
 
 // request r: a visible, cacheable key is stamped with the frame; its first
-// request this frame lists it (and, if not cached, as a miss)
+// request this frame lists it (and, if not cached, as a miss).  A full-LOD
+// request that wants detail takes the LOD-1 key; its brick is listed once
+// (the full-LOD key's stamp, which eviction ignores as that key is not
+// cached, marks it listed).
 __global__ void mark_kernel(CacheDev c, const uint32_t *ids, const uint8_t *lods, const uint8_t *vis, uint32_t n) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const uint32_t id = ids[r], t = lods[r];
+    const uint32_t id = ids[r];
+    uint32_t t = lods[r];
     if (id >= c.n_bricks || t >= kLods || (vis && !vis[r])) return;
-    const uint32_t key = id * kLods + t, frame = c.st->frame;
+    const uint32_t frame = c.st->frame;
+    if (t == 0 && c.det && wants_detail(c, id)) {
+        if (atomicExch(&c.stamp[id * kLods], frame) != frame) c.want[atomicAdd(&c.st->n_want, 1u)] = id;
+        t = 1;
+    }
+    const uint32_t key = id * kLods + t;
     if (atomicExch(&c.stamp[key], frame) == frame) return;
     c.uniq[t * c.n_req + atomicAdd(&c.st->n_uniq[t], 1u)] = key;
     if (c.index[key] == kNone64) c.miss[t * c.n_req + atomicAdd(&c.st->n_miss[t], 1u)] = key;
@@ -151,18 +186,35 @@ __global__ __launch_bounds__(1024) void assign_kernel(CacheDev c) {
     }
 }
 
-// per request: element offset of its block in the cache, or ~0
+// per request: element offset of its block in the cache, or ~0; with
+// `served`, the LOD of that block (0xFF for none): a full-LOD request of a
+// brick with detail in host memory whose full LOD is not cached was served
+// at LOD 1
 __global__ void slots_kernel(CacheDev c, const uint32_t *ids, const uint8_t *lods, const uint8_t *vis, uint32_t n,
-                             uint64_t *slots) {
+                             uint64_t *slots, uint8_t *served) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const uint32_t id = ids[r], t = lods[r];
+    const uint32_t id = ids[r];
+    uint32_t t = lods[r];
     uint64_t s = kNone64;
     if (id < c.n_bricks && t < kLods && (!vis || vis[r])) {
+        if (t == 0 && c.det && (c.det[id] & kSplit) && c.index[id * kLods] == kNone64) t = 1;
         const uint64_t e = c.index[id * kLods + t];
         if (e != kNone64) s = e * 8;
     }
     slots[r] = s;
+    if (served) served[r] = s == kNone64 ? (uint8_t)0xFF : (uint8_t)t;
+}
+
+// predicted bricks: pred[r] = the id if its detail is in host memory and
+// its full LOD is not cached (after this frame's assignment), else ~0u;
+// the caller's order is kept
+__global__ void predict_kernel(CacheDev c, const uint32_t *ids, uint32_t n) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t id = ids[r];
+    const bool need = id < c.n_bricks && (c.det[id] & kSplit) && c.index[id * kLods] == kNone64;
+    c.pred[r] = need ? id : ~0u;
 }
 
 __global__ void fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
@@ -198,6 +250,17 @@ struct csv_frame_cache {
     uint8_t *vis = nullptr;    // per request: visibility mask
     FrameState *h_st = nullptr;  // pinned copy of the frame state
     uint32_t last_n = 0;         // requests of the last frame
+    // detail streaming (pools with level-0 detail in host memory)
+    bool detail = false;
+    uint8_t *d_det = nullptr;         // CacheDev::det
+    uint8_t *h_det = nullptr;         // its pinned host image
+    std::vector<uint32_t> det_gran;   // per brick: staging bytes of its detail (0: none in host memory)
+    std::vector<uint32_t> staged;     // bricks this cache staged since the last release
+    uint64_t stage_used = 0;          // staging bytes of those bricks
+    uint8_t *h_lists = nullptr;       // pinned: frame state, wanted bricks, predictions of the last frame
+    uint32_t list_n = 0, list_np = 0; // the last frame's requests and predictions
+    bool lists_pending = false;
+    hipEvent_t lists_ev = nullptr;    // the copy of the lists (and everything before it on the stream)
 };
 
 extern "C" {
@@ -236,6 +299,27 @@ int csv_frame_cache_create(csv_pool *pool, uint64_t cache_bytes, uint32_t max_re
               hipMalloc(reinterpret_cast<void **>(&c->vis), nr) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&c->h_st), sizeof(FrameState), hipHostMallocDefault) ==
                   hipSuccess;
+    if (ok && info.host_bytes) {
+        // a pool with level-0 detail in host memory: which bricks, and how
+        // much staging each takes
+        c->detail = true;
+        c->det_gran.assign(info.n_bricks, 0u);
+        ok = hipHostMalloc(reinterpret_cast<void **>(&c->h_det), info.n_bricks, hipHostMallocDefault) == hipSuccess;
+        for (uint32_t id = 0; ok && id < info.n_bricks; id++) {
+            uint32_t b = 0;
+            if (csv_pool_detail_bytes(pool, id, &b, nullptr) != CSV_OK) ok = false;
+            c->det_gran[id] = b;
+            c->h_det[id] = b ? kSplit : 0;
+        }
+        ok = ok && hipMalloc(reinterpret_cast<void **>(&c->d_det), info.n_bricks) == hipSuccess &&
+             hipMalloc(reinterpret_cast<void **>(&d.want), 4 * nr) == hipSuccess &&
+             hipMalloc(reinterpret_cast<void **>(&d.pred), 4 * nr) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void **>(&c->h_lists), sizeof(FrameState) + 8 * nr,
+                           hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&c->lists_ev, hipEventDisableTiming) == hipSuccess &&
+             hipMemcpy(c->d_det, c->h_det, info.n_bricks, hipMemcpyHostToDevice) == hipSuccess;
+        d.det = c->d_det;
+    }
     if (ok) {
         hipLaunchKernelGGL(fill_u64, dim3(256), dim3(256), 0, nullptr, d.index, nk, kNone64);
         hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, nullptr, d.stamp, nk, 0u);
@@ -265,13 +349,101 @@ static void fill_stats(const csv_frame_cache *c, const FrameState &st, csv_frame
     stats->capacity_bytes = c->cap_elems * 32;
 }
 
-int csv_frame_cache_frame(csv_frame_cache *c, const uint32_t *ids, const uint8_t *lods, uint32_t n,
-                          const uint32_t *visible_bits, uint32_t n_label_bits, uint64_t *slots, void *stream,
-                          csv_frame_stats *stats) {
-    if (!c || n > c->max_req || (n && (!ids || !lods || !slots))) return CSV_EINVAL;
+// Detail for this frame (frames of caches over pools with level-0 detail in
+// host memory): the last frame's wanted bricks (by id), then its predicted
+// bricks that still need detail (in the caller's order), staged behind the
+// detail already on the device when they fit, else after dropping it.
+static int stage_frame_detail(csv_frame_cache *c, hipStream_t s, csv_frame_detail_stats *ds) {
+    constexpr uint8_t kListed = 4;
+    // the last frame's copies (lists, and the detail flags from the pinned
+    // image) are done
+    if (hipEventSynchronize(c->lists_ev) != hipSuccess) return CSV_EHIP;
+    std::vector<uint32_t> list;  // each brick once: wanted (by id), then predicted
+    uint32_t n_want = 0, n_pred = 0;
+    if (c->lists_pending) {
+        c->lists_pending = false;
+        FrameState st;
+        std::memcpy(&st, c->h_lists, sizeof(st));
+        const uint32_t *want = reinterpret_cast<const uint32_t *>(c->h_lists + sizeof(FrameState));
+        const uint32_t *pred = want + c->max_req;
+        n_want = std::min(st.n_want, c->list_n);
+        std::vector<uint32_t> w(want, want + n_want);
+        std::sort(w.begin(), w.end());
+        for (uint32_t r = 0; r < c->list_np; r++) n_pred += pred[r] < c->n_bricks ? 1u : 0u;
+        auto add = [&](uint32_t id) {
+            if (id >= c->n_bricks || (c->h_det[id] & kListed)) return;
+            c->h_det[id] |= kListed;
+            list.push_back(id);
+        };
+        for (uint32_t id : w) add(id);
+        for (uint32_t r = 0; r < c->list_np; r++) add(pred[r]);
+        for (uint32_t id : list) c->h_det[id] &= (uint8_t)~kListed;
+    }
+    uint64_t cap = 0;
+    int rc = csv_pool_detail_bytes(c->pool, 0, nullptr, &cap);
+    if (rc) return rc;
+    // listed bricks whose detail is not staged
+    std::vector<uint32_t> fresh;
+    auto fresh_of = [&]() {
+        uint64_t need = 0;
+        fresh.clear();
+        for (uint32_t id : list)
+            if (!(c->h_det[id] & kStaged)) {
+                fresh.push_back(id);
+                need += c->det_gran[id];
+            }
+        return need;
+    };
+    const uint64_t need = fresh_of();
+    bool changed = false, released = false;
+    if (!c->staged.empty() && c->stage_used + need > cap) {
+        rc = csv_pool_release_detail(c->pool, s);
+        if (rc) return rc;
+        for (uint32_t id : c->staged) c->h_det[id] &= (uint8_t)~kStaged;
+        c->staged.clear();
+        c->stage_used = 0;
+        released = changed = true;
+        fresh_of();
+    }
+    uint32_t done = 0;
+    uint64_t up = 0;
+    if (!fresh.empty()) {
+        rc = csv_pool_stage_detail(c->pool, fresh.data(), (uint32_t)fresh.size(), s, &done);
+        if (rc) return rc;
+        for (uint32_t k = 0; k < done; k++) {
+            const uint32_t id = fresh[k];
+            if (!c->det_gran[id]) continue;
+            c->h_det[id] |= kStaged;
+            c->staged.push_back(id);
+            c->stage_used += c->det_gran[id];
+            up += c->det_gran[id];
+        }
+        changed = changed || done > 0;
+    }
+    if (changed && (hipMemcpyAsync(c->d_det, c->h_det, c->n_bricks, hipMemcpyHostToDevice, s) != hipSuccess ||
+                    hipEventRecord(c->lists_ev, s) != hipSuccess))
+        return CSV_EHIP;
+    if (ds) {
+        ds->wanted = n_want;
+        ds->predicted = n_pred;
+        for (uint32_t id : list) ds->staged += (c->h_det[id] & kStaged) ? 1u : 0u;
+        ds->released = released ? 1u : 0u;
+        ds->uploaded_bytes = up;
+        ds->resident_bytes = c->stage_used;
+    }
+    return CSV_OK;
+}
+
+static int frame_impl(csv_frame_cache *c, const uint32_t *ids, const uint8_t *lods, uint32_t n,
+                      const uint32_t *visible_bits, uint32_t n_label_bits, const uint32_t *pred, uint32_t n_pred,
+                      uint64_t *slots, uint8_t *served, hipStream_t s, csv_frame_stats *stats,
+                      csv_frame_detail_stats *dstats) {
     DeviceGuard g(c->device);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const CacheDev &d = c->d;
+    if (c->detail) {
+        const int rc = stage_frame_detail(c, s, dstats);
+        if (rc) return rc;
+    }
     const bool test = visible_bits != nullptr || n_label_bits != 0;
     if (test && n) {
         const int rc = csv_bricks_visible(c->pool, ids, n, visible_bits, n_label_bits, c->vis, s);
@@ -286,28 +458,65 @@ int csv_frame_cache_frame(csv_frame_cache *c, const uint32_t *ids, const uint8_t
     hipLaunchKernelGGL(assign_kernel, dim3(1), dim3(1024), 0, s, d);
     if (hipGetLastError() != hipSuccess) return CSV_EHIP;
     c->last_n = n;
+    int rc = CSV_OK;
+    FrameState st{};
     if (!stats) {
         // no round trip to the host: the decode reads the number of bricks
         // from the frame state (0 when the frame does not fit)
-        int rc = CSV_OK;
         if (n) rc = csv_decode_bricks_devcount(c->pool, d.dec_ids, d.dec_lods, 0, d.dec_off, n, &d.st->n_dec,
                                                c->data, s);
-        if (n) hipLaunchKernelGGL(slots_kernel, dim3(gr), dim3(256), 0, s, d, ids, lods, vis, n, slots);
-        if (hipGetLastError() != hipSuccess && !rc) rc = CSV_EHIP;
-        return rc;
+    } else {
+        if (hipMemcpyAsync(c->h_st, d.st, sizeof(FrameState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return CSV_EHIP;
+        st = *c->h_st;
+        if (!st.error && st.n_dec)
+            rc = csv_decode_bricks(c->pool, d.dec_ids, d.dec_lods, 0, d.dec_off, st.n_dec, c->data, s);
     }
-    if (hipMemcpyAsync(c->h_st, d.st, sizeof(FrameState), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return CSV_EHIP;
-    const FrameState st = *c->h_st;
-    int rc = CSV_OK;
-    if (!st.error && st.n_dec)
-        rc = csv_decode_bricks(c->pool, d.dec_ids, d.dec_lods, 0, d.dec_off, st.n_dec, c->data, s);
-    if (n) hipLaunchKernelGGL(slots_kernel, dim3(gr), dim3(256), 0, s, d, ids, lods, vis, n, slots);
+    if (n) hipLaunchKernelGGL(slots_kernel, dim3(gr), dim3(256), 0, s, d, ids, lods, vis, n, slots, served);
+    if (c->detail) {
+        // the lists for the next frame: this frame's state (its count of
+        // wanted bricks), the wanted bricks, the predictions still in need
+        const uint32_t np = pred ? n_pred : 0;
+        if (np) hipLaunchKernelGGL(predict_kernel, dim3((np + 255) / 256), dim3(256), 0, s, d, pred, np);
+        uint8_t *hw = c->h_lists + sizeof(FrameState);
+        if (hipMemcpyAsync(c->h_lists, d.st, sizeof(FrameState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            (n && hipMemcpyAsync(hw, d.want, 4ull * n, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+            (np && hipMemcpyAsync(hw + 4ull * c->max_req, d.pred, 4ull * np, hipMemcpyDeviceToHost, s) !=
+                       hipSuccess) ||
+            hipEventRecord(c->lists_ev, s) != hipSuccess)
+            return CSV_EHIP;
+        c->list_n = n;
+        c->list_np = np;
+        c->lists_pending = true;
+        if (dstats) dstats->fallbacks = st.n_want;
+    }
     if (hipGetLastError() != hipSuccess && !rc) rc = CSV_EHIP;
-    fill_stats(c, st, stats);
-    if (!rc && st.error) rc = CSV_ENOMEM;
+    if (stats) {
+        fill_stats(c, st, stats);
+        if (!rc && st.error) rc = CSV_ENOMEM;
+    }
     return rc;
+}
+
+int csv_frame_cache_frame(csv_frame_cache *c, const uint32_t *ids, const uint8_t *lods, uint32_t n,
+                          const uint32_t *visible_bits, uint32_t n_label_bits, uint64_t *slots, void *stream,
+                          csv_frame_stats *stats) {
+    if (!c || c->detail || n > c->max_req || (n && (!ids || !lods || !slots))) return CSV_EINVAL;
+    return frame_impl(c, ids, lods, n, visible_bits, n_label_bits, nullptr, 0, slots, nullptr,
+                      reinterpret_cast<hipStream_t>(stream), stats, nullptr);
+}
+
+int csv_frame_cache_frame_detail(csv_frame_cache *c, const uint32_t *ids, const uint8_t *lods, uint32_t n,
+                                 const uint32_t *visible_bits, uint32_t n_label_bits, const uint32_t *predict_ids,
+                                 uint32_t n_predict, uint64_t *slots, uint8_t *served_lods, void *stream,
+                                 csv_frame_stats *stats, csv_frame_detail_stats *detail_stats) {
+    if (!c || n > c->max_req || n_predict > c->max_req || (n && (!ids || !lods || !slots)) ||
+        (n_predict && !predict_ids) || (detail_stats && !stats))
+        return CSV_EINVAL;
+    if (detail_stats) std::memset(detail_stats, 0, sizeof(*detail_stats));
+    return frame_impl(c, ids, lods, n, visible_bits, n_label_bits, predict_ids, n_predict, slots, served_lods,
+                      reinterpret_cast<hipStream_t>(stream), stats, detail_stats);
 }
 
 int csv_frame_cache_last_stats(csv_frame_cache *c, csv_frame_stats *stats) {
@@ -348,6 +557,12 @@ void csv_frame_cache_destroy(csv_frame_cache *c) {
     (void)hipFree(c->d.st);
     (void)hipFree(c->vis);
     if (c->h_st) (void)hipHostFree(c->h_st);
+    if (c->h_det) (void)hipHostFree(c->h_det);
+    (void)hipFree(c->d_det);
+    (void)hipFree(c->d.want);
+    (void)hipFree(c->d.pred);
+    if (c->h_lists) (void)hipHostFree(c->h_lists);
+    if (c->lists_ev) (void)hipEventDestroy(c->lists_ev);
     delete c;
 }
 

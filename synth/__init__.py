@@ -154,3 +154,28 @@ def camera_pose(ctrl: np.ndarray, u):
         lib.synth_camera_pose(cp, float(x), p3.ctypes.data_as(ctypes.c_void_p), t3.ctypes.data_as(ctypes.c_void_p))
         pos[i], tan[i] = p3, t3
     return pos, tan
+
+
+def brick_centres(nbx: int, nby: int, nbz: int, brick: int = 32) -> np.ndarray:
+    """Centres (x, y, z) in voxels of a volume's nbx * nby * nbz bricks, in
+    brick id order (x fastest)."""
+    z, y, x = np.meshgrid(np.arange(nbz), np.arange(nby), np.arange(nbx), indexing="ij")
+    return (np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.float64) + 0.5) * brick
+
+
+def frame_requests(nbx: int, nby: int, nbz: int, pos, d0: float, brick: int = 32, max_lod: int = 5):
+    """One frame's requests from a camera at pos (voxels) that sees every
+    brick: each brick once, at level of detail 0 when its centre lies within
+    d0 voxels, else floor(log2(d / d0)) + 1, at most max_lod (one voxel per
+    pixel at distance d0, as camera_trace).  Returns (ids u32, lods u8)."""
+    d = np.linalg.norm(brick_centres(nbx, nby, nbz, brick) - np.asarray(pos, np.float64), axis=1)
+    lod = np.where(d < d0, 0, np.floor(np.log2(np.maximum(d, d0) / d0)) + 1)
+    return np.arange(len(d), dtype=np.uint32), np.minimum(lod, max_lod).astype(np.uint8)
+
+
+def near_bricks(nbx: int, nby: int, nbz: int, pos, radius: float, brick: int = 32) -> np.ndarray:
+    """Ids (u32) of the bricks whose centres lie within radius voxels of pos,
+    nearest first (ties by id)."""
+    d = np.linalg.norm(brick_centres(nbx, nby, nbz, brick) - np.asarray(pos, np.float64), axis=1)
+    ids = np.nonzero(d < radius)[0]
+    return ids[np.lexsort((ids, d[ids]))].astype(np.uint32)

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     L = csv.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert L.csv_abi_version() == 3
+    assert L.csv_abi_version() == 4
 
 
 def test_visibility_test_rejects_a_missing_pool():
