@@ -309,6 +309,8 @@ def detail_leg(csv, torch, blob, ids_np, ids, out, shape, whole_pool, reps=10):
     # full LOD with nothing staged: level 1 upsampled, CSV_EDETAIL recorded
     fb_ms = timed(dpool, out2, 0)
     assert dpool.last_error()[0] == csv.CSV_EDETAIL
+    del out2
+    cam = camera_frames(csv, torch, dpool, csv.blob_info(blob))
     med = lambda v: sorted(v)[len(v) // 2]
     staged_bytes = host if done == B else None
     return {"record_bytes": rec, "hbm_record_bytes": rec - host, "host_detail_bytes": host,
@@ -318,7 +320,54 @@ def detail_leg(csv, torch, blob, ids_np, ids, out, shape, whole_pool, reps=10):
                       "stage_ms": round(med(st), 4), "decode_ms": round(med(dec), 4),
                       "wall_ms": round(med(wall), 4),
                       "stage_gbs": round(staged_bytes / (med(st) * 1e-3) / 1e9, 2) if staged_bytes else None},
-            "unstaged_full_lod_ms": round(fb_ms, 4)}
+            "unstaged_full_lod_ms": round(fb_ms, 4), "camera_frames": cam}
+
+
+def camera_frames(csv, torch, dpool, info, n_frames=60, step=8.0, d0=96.0, ahead=4):
+    """Detail streaming in frames (Sec. 4.2) on the pool with level-0 detail
+    in host memory: a camera moves `step` voxels per frame along x through
+    the middle of the volume; each frame requests every brick at the level
+    of detail its distance gives (full LOD within d0 voxels) through the
+    frame cache.  Without prediction a brick entering the full-LOD zone is
+    served at LOD 1 for one frame; with prediction the detail of the bricks
+    within d0 + ahead * step voxels is uploaded one frame ahead.  Per-frame
+    wall time from the call to the end of its decode."""
+    import synth
+    g = info["nbx"], info["nby"], info["nbz"]
+    runs = {}
+    for mode, radius in (("on_demand", None), ("predictive", d0 + ahead * step)):
+        fc = csv.FrameCache(dpool, 256 << 20, g[0] * g[1] * g[2])
+        ms, fbs, up, res = [], [], [], []
+        for k in range(n_frames):
+            pos = (-40.0 + step * k, info["ny"] / 2 - 6, info["nz"] / 2 + 6)
+            ids, lods = synth.frame_requests(*g, pos, d0)
+            d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+            d_lods = torch.from_numpy(lods).cuda()
+            pred = None
+            if radius:
+                pred = torch.from_numpy(synth.near_bricks(*g, pos, radius).view(np.int32)).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st, ds = fc.frame_detail(d_ids, d_lods, predict=pred)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            fbs.append(ds["fallbacks"])
+            up.append(ds["uploaded_bytes"])
+            res.append(ds["resident_bytes"])
+        fc.close()
+        dpool.release_detail()
+        assert dpool.last_error()[0] == 0
+        ms_s = sorted(ms[1:])  # the first frame fills an empty cache
+        runs[mode] = {"frames": n_frames, "p50_ms": round(ms_s[len(ms_s) // 2], 3),
+                      "p99_ms": round(ms_s[int(0.99 * (len(ms_s) - 1))], 3),
+                      "first_frame_fallbacks": fbs[0],
+                      "fallbacks_after_first": int(sum(fbs[1:])),
+                      "frames_with_fallbacks": int(sum(1 for f in fbs[1:] if f)),
+                      "uploaded_kib_per_frame": round(sum(up[1:]) / max(n_frames - 1, 1) / 1024, 1),
+                      "max_resident_kib": round(max(res) / 1024, 1)}
+        log("camera frames %s %s" % (mode, runs[mode]))
+    return {"step_voxels": step, "full_lod_voxels": d0, "predict_radius_voxels": d0 + ahead * step,
+            "staging_bytes": 8 << 20, **runs}
 
 
 def encoder_leg(csv, torch, vol, blob, host_s, host_threads, reps=3):
