@@ -40,7 +40,9 @@ def setup(orc):
     csv.lib()
     vol = synth.cells(n=512, grid=37, seed=2)[:256, :256, :256].copy()
     blob = orc.encode_volume(vol, scale_bits=10, lane_k=64)
-    return csv, blob, {}
+    labels = [np.unique(vol[32 * bz:32 * bz + 32, 32 * by:32 * by + 32, 32 * bx:32 * bx + 32])
+              for bz in range(G) for by in range(G) for bx in range(G)]
+    return csv, blob, {}, labels
 
 
 def detail_pool(csv, blob, staging=None):
@@ -68,7 +70,13 @@ class Model:
         self.cached0 = set()   # bricks whose full LOD is cached after the last frame
         self.want, self.pred = [], []
 
-    def frame(self, ids, lods, predict):
+    def frame(self, ids, lods, predict, vis=None, cap_bytes=None):
+        """vis: per request visible (None: all); cap_bytes: cache size (a
+        frame whose distinct blocks exceed it stores nothing).  Returns the
+        served LODs (0xFF: not stored), the detail counts and whether the
+        frame did not fit."""
+        if vis is None:
+            vis = np.ones(len(ids), bool)
         lst = list(dict.fromkeys(sorted(self.want) + list(self.pred)))
         fresh = [b for b in lst if b not in self.staged]
         need = sum(int(self.gran[b]) for b in fresh)
@@ -85,52 +93,88 @@ class Model:
             up += int(self.gran[b])
         ds = dict(wanted=len(self.want), predicted=len(self.pred), staged=sum(b in self.staged for b in lst),
                   released=released, uploaded_bytes=up, resident_bytes=self.used)
-        served = lods.copy()
+        served = np.where(vis & (lods < 5), lods, 0xFF).astype(np.uint8)
         fb = set()
-        for r, (b, t) in enumerate(zip(ids.tolist(), lods.tolist())):
+        for r, (b, t) in enumerate(zip(ids.tolist(), served.tolist())):
             if t == 0 and self.gran[b] and b not in self.cached0 and b not in self.staged:
                 served[r] = 1
                 fb.add(b)
         ds["fallbacks"] = len(fb)
-        self.cached0 = {b for b, t, s in zip(ids.tolist(), lods.tolist(), served.tolist()) if t == 0 and s == 0}
+        keys = {(b, t) for b, t in zip(ids.tolist(), served.tolist()) if t != 0xFF}
+        error = cap_bytes is not None and sum(32 << (3 * (4 - t)) for _, t in keys) > cap_bytes
+        if error:
+            served[:] = 0xFF
+        self.cached0 = {b for b, t in keys if t == 0 and not error}
         self.want = sorted(fb)
         self.pred = [int(b) for b in predict if self.gran[b] and int(b) not in self.cached0]
-        return served, ds
+        return served, ds, error
 
 
-def run(csv, orc, blob, refs, n_frames, radius=None, staging=None, stats=True, check_all=True):
+def run(csv, orc, blob, refs, n_frames, radius=None, staging=None, stats=True, check_all=True, cache_bytes=256 << 20,
+        density=None, labels=None):
     """Frames along the path; radius: predict the bricks within that many
-    voxels.  Returns per frame (served LODs, detail stats)."""
-    torch = torch_cuda()
+    voxels; density: a share of the labels visible (a new draw every other
+    frame; labels: each brick's labels).  Returns per frame (served LODs,
+    detail stats or None for a frame that did not fit)."""
     pool, gran = detail_pool(csv, blob, staging)
     cap = staging if staging is not None else 8 << 20
-    cache = csv.FrameCache(pool, 256 << 20, G ** 3)
+    cache = csv.FrameCache(pool, cache_bytes, G ** 3)
     model = Model(gran, cap)
     out = []
     try:
-        frames_along(csv, orc, blob, refs, n_frames, radius, stats, check_all, pool, cache, model, out)
+        frames_along(csv, orc, blob, refs, n_frames, radius, stats, check_all, pool, cache, model, out, cache_bytes,
+                     density, labels)
     finally:
         cache.close()
     return out
 
 
-def frames_along(csv, orc, blob, refs, n_frames, radius, stats, check_all, pool, cache, model, out):
+def frames_along(csv, orc, blob, refs, n_frames, radius, stats, check_all, pool, cache, model, out, cache_bytes,
+                 density, labels):
     torch = torch_cuda()
     for k, pos in enumerate(path(n_frames)):
         ids, lods = synth.frame_requests(G, G, G, pos, D0)
         pred = synth.near_bricks(G, G, G, pos, radius) if radius else np.zeros(0, np.uint32)
-        want_served, want_ds = model.frame(ids, lods, pred)
-        log("frame %d at x=%.0f: %d full-LOD requests, %d predicted, stats %s"
-            % (k + 1, pos[0], int((lods == 0).sum()), len(pred), stats))
+        vis, bits, n_lab = None, None, 0
+        if density is not None and k % 2 == 1:
+            n_lab = int(max(l.max() for l in labels)) + 1
+            show = np.random.default_rng(200 + k).random(n_lab) < density
+            words = np.zeros((n_lab + 31) // 32, np.uint32)
+            idx = np.nonzero(show)[0].astype(np.uint64)
+            np.bitwise_or.at(words, (idx >> 5).astype(np.int64),
+                             (np.uint64(1) << (idx & np.uint64(31))).astype(np.uint32))
+            bits = torch.from_numpy(words.view(np.int32)).cuda()
+            vis = np.array([bool(show[labels[i]].any()) for i in ids])
+        want_served, want_ds, error = model.frame(ids, lods, pred, vis, cache_bytes)
+        log("frame %d at x=%.0f: %d full-LOD requests, %d predicted, %s visible, stats %s, %s"
+            % (k + 1, pos[0], int((lods == 0).sum()), len(pred), "all" if vis is None else int(vis.sum()), stats,
+               "does not fit" if error else "fits"))
         d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
         d_lods = torch.from_numpy(lods).cuda()
         d_pred = torch.from_numpy(pred.view(np.int32)).cuda() if len(pred) else None
-        slots, served, st, ds = cache.frame_detail(d_ids, d_lods, predict=d_pred, stats=stats)
+        slots = torch.empty(len(ids), dtype=torch.int64, device="cuda")
+        served = torch.empty(len(ids), dtype=torch.uint8, device="cuda")
+        st = ds = None
+        if error and stats:
+            with pytest.raises(csv.CsvError) as e:
+                cache.frame_detail(d_ids, d_lods, predict=d_pred, visible_bits=bits, n_label_bits=n_lab,
+                                   slots=slots, served=served)
+            assert e.value.code == csv.CSV_ENOMEM
+        else:
+            _, _, st, ds = cache.frame_detail(d_ids, d_lods, predict=d_pred, visible_bits=bits, n_label_bits=n_lab,
+                                              slots=slots, served=served, stats=stats)
         torch.cuda.synchronize()
         assert pool.last_error() == (0, 0)
         served = served.cpu().numpy()
         slots = slots.cpu().numpy()
-        np.testing.assert_array_equal(served, np.where(lods < 5, want_served, 0xFF))
+        np.testing.assert_array_equal(served, want_served)
+        if error:
+            assert (slots == -1).all()
+            if not stats:
+                with pytest.raises(csv.CsvError):
+                    cache.last_stats()
+            out.append((served, None))
+            continue
         if stats:
             assert ds == want_ds, (k, ds, want_ds)
             assert st["frame"] == k + 1
@@ -151,7 +195,7 @@ def frames_along(csv, orc, blob, refs, n_frames, radius, stats, check_all, pool,
 
 
 def test_without_prediction_a_fallback_lasts_one_frame(setup, orc):
-    csv, blob, refs = setup
+    csv, blob, refs, _ = setup
     res = run(csv, orc, blob, refs, 12)
     fbs = [ds["fallbacks"] for _, ds in res]
     log("fallbacks per frame %s" % fbs)
@@ -166,7 +210,7 @@ def test_without_prediction_a_fallback_lasts_one_frame(setup, orc):
 
 
 def test_prediction_hides_the_lag(setup, orc):
-    csv, blob, refs = setup
+    csv, blob, refs, _ = setup
     res = run(csv, orc, blob, refs, 12, radius=D0 + 2 * STEP)
     fbs = [ds["fallbacks"] for _, ds in res]
     log("fallbacks per frame with prediction %s" % fbs)
@@ -175,15 +219,26 @@ def test_prediction_hides_the_lag(setup, orc):
 
 
 def test_small_staging_buffer(setup, orc):
-    csv, blob, refs = setup
+    csv, blob, refs, _ = setup
     res = run(csv, orc, blob, refs, 10, radius=D0 + 2 * STEP, staging=16 << 10)
     log("detail stats %s" % [ds for _, ds in res])
     assert sum(ds["released"] for _, ds in res) > 0
     assert sum(ds["fallbacks"] for _, ds in res[1:]) > 0
 
 
+@pytest.mark.parametrize("cache_mib,radius", [(256, None), (22, D0 + STEP), (12, None), (12, D0 + STEP)])
+def test_visibility_rebuilds_and_frames_too_large(setup, orc, cache_mib, radius):
+    # invisible requests are not stored and want no detail; a cache a little
+    # larger than a frame rebuilds; frames larger than the cache store
+    # nothing, and their fallbacks are still listed for the next frame
+    csv, blob, refs, labels = setup
+    res = run(csv, orc, blob, refs, 10, radius=radius, cache_bytes=cache_mib << 20, density=0.02, labels=labels)
+    if cache_mib == 12:
+        assert any(ds is None for _, ds in res)
+
+
 def test_frames_without_statistics_serve_the_same(setup, orc):
-    csv, blob, refs = setup
+    csv, blob, refs, _ = setup
     a = run(csv, orc, blob, refs, 8, radius=D0 + STEP, check_all=False)
     b = run(csv, orc, blob, refs, 8, radius=D0 + STEP, stats=False, check_all=False)
     for (sa, _), (sb, _) in zip(a, b):
@@ -191,7 +246,7 @@ def test_frames_without_statistics_serve_the_same(setup, orc):
 
 
 def test_plain_frames_refused_and_pools_without_detail(setup, orc):
-    csv, blob, refs = setup
+    csv, blob, refs, _ = setup
     torch = torch_cuda()
     pool, _ = detail_pool(csv, blob)
     cache = csv.FrameCache(pool, 64 << 20, 64)
