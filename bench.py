@@ -605,6 +605,24 @@ def main():
             "compressed_bytes": len(blob2), "compression_ratio_pct": round(100.0 * len(blob2) / vol2.nbytes, 4)}
         log("cells %s" % extra["cells512_full_lod"])
 
+        # ---- small batches of the same volume (full LOD): time per call with
+        # the library's shape (the paired front kernel) and with one wave per brick ----
+        small, rng_s = [], np.random.default_rng(11)
+        for nb in (32, 128, 512, 1024):
+            ids_s = torch.from_numpy(rng_s.permutation(B2)[:nb].astype(np.int32)).to(dev)
+            o_a = out2[:nb * 32 ** 3]
+            o_b = torch.empty_like(o_a)
+            auto = pool2.shape_for(nb, 0, False)
+            ms_a = timed_calls(torch, lambda: pool2.decode(ids_s, o_a, lod=0), args.steps, args.warmup)
+            unpaired = (8, 3, 0, 0, 1)
+            ms_b = timed_calls(torch, lambda: pool2.decode(ids_s, o_b, lod=0, shape=unpaired), args.steps, args.warmup)
+            assert pool2.last_error()[0] == 0 and torch.equal(o_a, o_b), "small batch outputs differ"
+            small.append({"bricks": nb, "ms_per_call": round(ms_a, 4), "shape": list(auto),
+                          "one_wave_per_brick_ms": round(ms_b, 4), "one_wave_per_brick_shape": list(unpaired)})
+            del o_b
+        extra["cells512_small_batches"] = small
+        log("small batches %s" % small)
+
         # ---- 16,384 uneven mixed-LOD requests over three volumes, one persistent launch ----
         log("mixed requests over three volumes")
         vol1 = synth.voronoi_bg(n=64, sites=200, bg=0.30, seed=1)

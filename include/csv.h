@@ -331,7 +331,10 @@ int csv_decode_bricks_plain(const csv_pool *pool, const uint32_t *brick_ids, con
 /* Launch shape of a batched decode.  Every shape gives the same bytes. */
 typedef struct {
     int waves_per_group;    /* front kernel: wavefronts per workgroup, 4, 8 or 16 (each decodes its
-                               own bricks; 8 KiB of LDS per wavefront) */
+                               own bricks; 8 KiB of LDS per wavefront), or 2: two wavefronts per
+                               brick, one decoding the symbols while the other replays the levels
+                               above L_0 (shorter per-brick latency for batches too small to fill
+                               the GPU; no work counter) */
     uint32_t groups_per_cu; /* leaf kernel: 8-wavefront workgroups per compute unit, 1..8; each holds
                                160 KiB / groups_per_cu of LDS (rounded down to 4 KiB; bricks
                                whose arrays do not fit take a slower path through a global-memory
@@ -398,9 +401,13 @@ int csv_autotune(csv_pool *pool, const uint32_t *brick_ids, const uint8_t *lods,
 /* Tuned shapes are kept per class of request set: the bit length of n,
  * how the levels of detail are given (all full LOD; all one coarser LOD;
  * per request) and the bit length of the pool's mean record size.
- * csv_decode_bricks, _status and _noalloc use the shape tuned for the
- * class of their request set (else the tuned class of the same kind and
- * record size with the nearest n, else the pool's shape).
+ * csv_decode_bricks, _status, _devcount and _noalloc use the shape tuned
+ * for the class of their request set (else the tuned class of the same kind
+ * and record size with the nearest n, else the pool's shape).  Without a
+ * tuned class of its own, a request set that the paired front kernel
+ * (waves_per_group 2) takes all at once (one two-wave workgroup per
+ * request; 2,048 requests on 256 CUs with 10-bit tables) runs paired,
+ * unless the pool's shape was set with csv_pool_set_shape.
  * csv_pool_tuning_save writes them to a text file: a first line
  * "csv-tuning 1 <device architecture name> <compute units>", then one line
  * per class "<n bits> <lod kind> <record bits> <waves> <groups> <queue>

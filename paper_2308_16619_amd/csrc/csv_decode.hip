@@ -310,6 +310,11 @@ struct Hdr {
     }
 };
 
+// a hook that does nothing (the default of the kernels' optional hooks)
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
 enum ReqKind { kReqBadLod, kReqBadId, kReqCorrupt, kReqFill, kReqDecode };
 
 // read and check request rq; for kReqFill, fill is the value of every output label
@@ -591,10 +596,24 @@ __device__ __forceinline__ void wave_sync() {
 // Entropy decode of the first n symbols of a brick (the prefix for its
 // level of detail) into packed nibbles at out (global); ring32: this wave's
 // 2 KB of LDS.  False on a malformed stream.
-template <bool kLutLds>
+// at_upper (with the paired front kernel) is called once, in wave-uniform
+// control flow, as soon as the nibble dwords of the first c_1 symbols (the
+// levels above L_0) are written, else at the end
+template <bool kLutLds, class Hook = NoHook>
 __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h, const uint32_t *slut,
                                                uint32_t *ring32, uint32_t *out, uint32_t *lcopy, uint32_t n,
-                                               uint32_t &words) {
+                                               uint32_t &words, Hook at_upper = Hook{}) {
+    constexpr bool kHook = !std::is_same<Hook, NoHook>::value;
+    const uint32_t upper = (h.c1 + 7u) & ~7u;  // whole nibble dwords
+    bool fired = false;
+    auto upper_done = [&](uint32_t decoded) {
+        if constexpr (kHook) {
+            if (!fired && decoded >= upper) {
+                fired = true;
+                at_upper();
+            }
+        }
+    };
     const uint32_t L = lane();
     const uint32_t hdr = csv::record_header_words(kLog2);
     const uint16_t *ring = reinterpret_cast<const uint16_t *>(ring32);
@@ -699,11 +718,16 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
             if ((s << 3) + L < kWDeltaDw) lcopy[(s << 3) + L] = packed;
             wsync();
             s += 8;
+            upper_done(s << 6);
         };
         const uint32_t full = n >> 6, s_int = min(leaf >> 6, full);
         while (s + 8 <= s_int) block8(std::false_type{});
         while (s + 8 <= full) block8(std::true_type{});
-        for (; s < full; s++) step(std::true_type{});
+        for (; s < full;) {
+            step(std::true_type{});
+            s++;
+            upper_done(s << 6);
+        }
         // words past the end of the stream came from stale ring entries
         bad = cursor > h.nw;
         if (bad) s = steps;
@@ -746,6 +770,10 @@ __device__ __forceinline__ bool entropy_decode(const DecodeArgs &a, const Hdr &h
             if (full) acc = 0;
         }
         if (cursor >= ring_lo + 512) refill();
+        upper_done((s + 1) << lw);
+    }
+    if constexpr (kHook) {
+        if (!fired) at_upper();
     }
     // a complete decode ends in the encoder's initial states with every word read
     if (!bad && h.t == 0) bad = (__ballot(L < W && x != csv::kRansLower) != 0) || cursor != h.nw;
@@ -1017,9 +1045,22 @@ __device__ __forceinline__ void upper_output_up2(const IdxT *lv, const uint32_t 
 
 // one brick of the front kernel after its entropy decode; false on a
 // malformed stream
+// With e1_ipl (the paired front kernel) a t = 0 request is not yet handed to
+// the leaf kernel: E_1 and ipl go to e1_ipl[0..1] for hand_off.
+__device__ __forceinline__ void hand_off(const Hdr &h, const LaunchA &l, uint32_t E1, uint32_t ipl, uint32_t *dst) {
+    if (lane() == 0) {
+        const uint32_t at = atomicAdd(l.leaf_count, 1u);
+        uint4 *d = reinterpret_cast<uint4 *>(l.leaf_list + at);
+        const uint64_t ra = reinterpret_cast<uintptr_t>(h.rec), da = reinterpret_cast<uintptr_t>(dst);
+        d[0] = make_uint4(h.rq, h.id, h.P, h.c0);
+        d[1] = make_uint4(h.c1, E1, ipl, 0u);
+        d[2] = make_uint4((uint32_t)ra, (uint32_t)(ra >> 32), (uint32_t)da, (uint32_t)(da >> 32));
+    }
+}
+
 template <class IdxT, bool kG>
 __device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, const uint32_t *nib, uint8_t *slot,
-                                             uint8_t *wl, uint32_t *dst) {
+                                             uint8_t *wl, uint32_t *dst, uint32_t *e1_ipl = nullptr) {
     const uint32_t L = lane();
     const uint32_t hdr = csv::record_header_words(kLog2);
     uint8_t *slv = slot + 4 * l.slot_dw;
@@ -1048,13 +1089,11 @@ __device__ __forceinline__ bool front_replay(const Hdr &h, const LaunchA &l, con
         for (int q = 0; q < 4; q++) reinterpret_cast<uint4 *>(slv)[L + 64 * q] = src[L + 64 * q];
     }
     if (L < 32) reinterpret_cast<uint4 *>(sbm)[L] = reinterpret_cast<const uint4 *>(bm)[L];
-    if (L == 0) {
-        const uint32_t at = atomicAdd(l.leaf_count, 1u);
-        uint4 *d = reinterpret_cast<uint4 *>(l.leaf_list + at);
-        const uint64_t ra = reinterpret_cast<uintptr_t>(h.rec), da = reinterpret_cast<uintptr_t>(dst);
-        d[0] = make_uint4(h.rq, h.id, h.P, h.c0);
-        d[1] = make_uint4(h.c1, E1, ipl, 0u);
-        d[2] = make_uint4((uint32_t)ra, (uint32_t)(ra >> 32), (uint32_t)da, (uint32_t)(da >> 32));
+    if (e1_ipl) {
+        e1_ipl[0] = E1;
+        e1_ipl[1] = ipl;
+    } else {
+        hand_off(h, l, E1, ipl, dst);
     }
     return true;
 }
@@ -1149,6 +1188,89 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(4))) v
     }
 }
 
+// LDS of the paired kernel's decoding wave: the word ring with its mirrored
+// start and the symbol bytes of a block of 8 steps (entropy_decode), then
+// two verdict words
+constexpr uint32_t kPairOk = 2 * kRingWords + 128 + 512;
+constexpr uint32_t kPairDecLds = align16(kPairOk + 8);
+
+// Paired front kernel for small batches (shape waves_per_group 2), where a
+// decode lasts as long as its slowest brick's serial chain: a workgroup of
+// two waves per brick.  Wave 0 decodes the brick's symbols; as soon as the
+// symbols of the levels above L_0 are out (entropy_decode's hook, a
+// workgroup barrier), wave 1 replays those levels while wave 0 decodes the
+// L_0 symbols.  A second barrier ends the brick: wave 1 then hands a
+// full-LOD request to the leaf kernel, or reports a malformed stream.  The
+// chain becomes the upper symbols' decode plus the longer of the L_0
+// decode and the replay.  Both waves take every brick of the workgroup
+// (static round robin) and pass the same barriers on every path.
+template <bool kLutLds>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void front_pair_kernel(DecodeArgs a,
+                                                                                                LaunchA l) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *slut = reinterpret_cast<uint32_t *>(smem);
+    if (kLutLds)
+        for (uint32_t e = threadIdx.x; e < l.lut_lds_words; e += blockDim.x) slut[e] = a.luts[e];
+    __syncthreads();
+    const uint32_t L = lane(), wave = uniform(threadIdx.x >> 6);
+    uint8_t *wl0 = smem + align16(4 * l.lut_lds_words);  // wave 0: the word ring
+    uint8_t *wl1 = wl0 + kPairDecLds;                      // wave 1: the levels (first nibbles at kWPal)
+    uint32_t *ok_word = reinterpret_cast<uint32_t *>(wl0 + kPairOk);  // wave 0's verdict, by brick parity
+    const uint32_t n_req = a.n_dev ? min(a.n, ld_s(a.n_dev)) : a.n;
+    for (uint32_t k = 0;; k++) {
+        const uint32_t req = l.base + blockIdx.x + k * gridDim.x;
+        if (req >= n_req) break;
+        const uint32_t rq = l.order ? ld_s(l.order + req) : req;
+        Hdr h;
+        uint32_t *dst, count, fill;
+        const ReqKind kind = load_request(a, rq, h, dst, count, fill);
+        if (kind != kReqDecode) {
+            if (wave == 0) {
+                if (kind == kReqBadLod) {
+                    if (L == 0) fail(a, rq, CSV_ERANGE, a.rq_base + rq);
+                } else {
+                    if (kind != kReqFill && L == 0)
+                        fail(a, rq, kind == kReqBadId ? CSV_ERANGE : CSV_ECORRUPT,
+                             kind == kReqBadId ? a.rq_base + rq : h.id);
+                    fill_labels<64>(dst, count, kind == kReqFill ? fill : 0u, L);
+                }
+            }
+            continue;
+        }
+        if (h.up && L == 0 && wave == 0) fail(a, rq, CSV_EDETAIL, h.id);
+        const uint32_t n = h.c(h.t);
+        uint8_t *slot = glob(l.slots) + (size_t)rq * l.slot_bytes;
+        uint32_t *nib = reinterpret_cast<uint32_t *>(slot);
+        if (n + 16 > 8 * l.slot_dw) {  // the slots are sized for the pool's largest brick
+            if (wave == 0) {
+                if (L == 0) fail(a, rq, CSV_EINVAL, h.id);
+                fill_labels<64>(dst, count, 0u, L);
+            }
+            continue;
+        }
+        if (wave == 0) {
+            uint32_t words = 0;
+            const bool ok = entropy_decode<kLutLds>(a, h, slut, reinterpret_cast<uint32_t *>(wl0), nib,
+                                                    reinterpret_cast<uint32_t *>(wl1 + kWPal), n, words,
+                                                    [] { __syncthreads(); });
+            if (L == 0) ok_word[k & 1u] = ok ? 1u : 0u;
+            __syncthreads();
+        } else {
+            __syncthreads();  // the symbols above L_0 are out
+            uint32_t e1_ipl[2] = {0u, 0u};
+            bool ok = h.P <= kPalFast ? front_replay<uint8_t, false>(h, l, nib, slot, wl1, dst, e1_ipl)
+                                      : front_replay<uint16_t, true>(h, l, nib, slot, wl1, dst, e1_ipl);
+            __syncthreads();  // wave 0 is done with the brick
+            ok = ok && ok_word[k & 1u] != 0u;
+            if (ok && h.t == 0) hand_off(h, l, e1_ipl[0], e1_ipl[1], dst);
+            if (!ok) {
+                if (L == 0) fail(a, rq, CSV_ECORRUPT, h.id);
+                fill_labels<64>(dst, count, 0u, L);
+            }
+        }
+    }
+}
+
 // ===========================================================================
 // B. leaf kernel
 // ===========================================================================
@@ -1235,9 +1357,6 @@ __device__ __forceinline__ uint32_t chase(const IdxT *D, uint32_t i, uint32_t v)
 // after_pass2() runs once pass 2 is complete and checked, on every thread,
 // before the references and the output (the leaf kernel issues the next
 // brick's loads there, ahead of this brick's output stores).
-struct NoHook {
-    __device__ void operator()() const {}
-};
 template <class IdxT, bool kG, int NW, class Hook = NoHook>
 __device__ __forceinline__ bool leaf_replay(const Hdr &h, uint32_t E1, uint32_t ipl, const uint32_t *nib,
                                             uint32_t nib0, const IdxT *l1m, const uint64_t *bm1w,
@@ -2065,6 +2184,7 @@ struct csv_pool {
     uint64_t hbm_budget = 0;                  // HBM the pool may hold (0: no limit)
     uint32_t generation = 0;                  // bumped when device tables move
     csv_shape shape{16, 3, 0, 0, 4, 0.f};     // launch shape of csv_decode_bricks (untuned classes)
+    bool shape_set = false;                   // shape given by csv_pool_set_shape
     std::map<uint32_t, csv_shape> tuned;      // autotuned shapes by request-set class (tune_key)
     char device_name[64] = {0};
     uint64_t record_bytes = 0;
@@ -2295,7 +2415,20 @@ void launch_a(const DecodeArgs &a, const LaunchA &l, uint32_t grid, size_t lds, 
         hipLaunchKernelGGL((front_kernel<WPG, false>), dim3(grid), dim3(64 * WPG), lds, s, a, l);
 }
 
-// waves_a: front-kernel waves per workgroup; groups_b: leaf workgroups
+void launch_pair(const DecodeArgs &a, const LaunchA &l, uint32_t grid, size_t lds, hipStream_t s) {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)set_lds_attr(front_pair_kernel<true>);
+        (void)set_lds_attr(front_pair_kernel<false>);
+    });
+    if (l.lut_lds_words)
+        hipLaunchKernelGGL((front_pair_kernel<true>), dim3(grid), dim3(128), lds, s, a, l);
+    else
+        hipLaunchKernelGGL((front_pair_kernel<false>), dim3(grid), dim3(128), lds, s, a, l);
+}
+
+// waves_a: front-kernel waves per workgroup (2: the paired kernel, two
+// waves per brick); groups_b: leaf workgroups
 // per CU; fixed: buffers owned by the caller (a captured graph), else the
 // stream's own set
 // CSV_REF_LIST_CAP (a decimal count) bounds the leaf kernel's list of
@@ -2319,8 +2452,11 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     if (lods && !out_off) return CSV_EINVAL;
     if (n == 0) return CSV_OK;
     if (pool->rec_ptr.empty() || !pool->d_err) return CSV_EINVAL;
-    if (waves_a != 4 && waves_a != 8 && waves_a != 16) return CSV_EINVAL;
+    if (waves_a != 2 && waves_a != 4 && waves_a != 8 && waves_a != 16) return CSV_EINVAL;
     if (groups_b < 1 || groups_b > kMaxGroupsB) return CSV_EINVAL;
+    // the paired kernel takes no work counter and has no prefix pass
+    if (waves_a == 2 && words_out) waves_a = 4;
+    if (waves_a == 2) queue = false;
     DeviceGuard g(pool->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     static std::once_flag once_b;
@@ -2459,13 +2595,18 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     lb.slow_list = slow ? B->slow_list : nullptr;
     // a small batch takes smaller front workgroups, so that its bricks spread over the CUs
     while (waves_a > 4 && (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a < cu) waves_a /= 2;
-    // front kernel: as many workgroups as a CU's LDS and 32 wave slots allow
-    const uint32_t lds_a = align16(4 * la.lut_lds_words) + (uint32_t)waves_a * kWaveLds;
+    // front kernel: as many workgroups as a CU's LDS and 32 wave slots allow;
+    // bricks_a of them in flight at once (one per wave, or one per paired workgroup)
+    const uint32_t per_wg = waves_a == 2 ? 1u : (uint32_t)waves_a;
+    const uint32_t lds_a = align16(4 * la.lut_lds_words) +
+                           (waves_a == 2 ? kPairDecLds + kWaveLds : (uint32_t)waves_a * kWaveLds);
     const uint32_t fit_a = std::max(1u, std::min(kLdsBytes / lds_a, 32u / (uint32_t)waves_a));
-    const uint32_t grid_a = std::max(1u, std::min(cu * fit_a, (n + (uint32_t)waves_a - 1) / (uint32_t)waves_a));
+    const uint32_t grid_a = std::max(1u, std::min(cu * fit_a, (n + per_wg - 1) / per_wg));
+    const uint32_t bricks_a = grid_a * per_wg;
     const uint32_t grid_b = std::min(cu * groups_b, n);
     auto go_a = [&](const DecodeArgs &aa, const LaunchA &L, uint32_t grid) {
         switch (waves_a) {
+            case 2: launch_pair(aa, L, grid, lds_a, s); break;
             case 4: launch_a<4>(aa, L, grid, lds_a, s); break;
             case 8: launch_a<8>(aa, L, grid, lds_a, s); break;
             default: launch_a<16>(aa, L, grid, lds_a, s); break;
@@ -2484,11 +2625,10 @@ int launch_one(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint32_
     } else {
         // with at most one request per front wave the order changes nothing;
         // with a device-side count the order kernels would not know it
-        if (lpt && !n_dev && n > grid_a * (uint32_t)waves_a) {
+        if (lpt && !n_dev && n > bricks_a) {
             const uint32_t grid_o = std::min(256u, (n + 255) / 256);
             hipLaunchKernelGGL(order_count, dim3(grid_o), dim3(256), 0, s, a, B->small);
-            hipLaunchKernelGGL(order_place, dim3(grid_o), dim3(256), 0, s, a, B->small, B->order,
-                               grid_a * (uint32_t)waves_a);
+            hipLaunchKernelGGL(order_place, dim3(grid_o), dim3(256), 0, s, a, B->small, B->order, bricks_a);
             la.order = B->order;
         }
         go_a(a, la, grid_a);
@@ -2591,8 +2731,21 @@ uint32_t tune_key(const csv_pool *p, const uint8_t *lods, uint32_t lod_scalar, u
 // The shape for a request set: the tuned one of its class, else of the
 // class with the same level-of-detail kind and record size and the nearest
 // n, else the pool's shape.  pool->mu held.
+// Requests that the paired front kernel takes all at once: one workgroup of
+// two waves per request, as many as a CU's LDS holds.
+uint32_t pair_capacity(const csv_pool *p) {
+    const uint32_t lds = align16(4 * lut_lds_words(p)) + kPairDecLds + kWaveLds;
+    return (uint32_t)std::max(1, p->n_cu) * std::min(kLdsBytes / lds, 16u);
+}
+
+// The shape for a request set: the tuned one of its class; else, for a
+// batch the paired front kernel takes all at once (there every request's
+// latency is its own serial chain, which the pairing shortens) and a pool
+// whose shape was not set, that of the nearest tuned class with the front
+// kernel paired; else the tuned one of the class with the same
+// level-of-detail kind and record size and the nearest n; else the pool's
+// shape.  pool->mu held.
 csv_shape shape_for(const csv_pool *p, const uint8_t *lods, uint32_t lod_scalar, uint32_t n) {
-    if (p->tuned.empty()) return p->shape;
     const uint32_t key = tune_key(p, lods, lod_scalar, n);
     const auto it = p->tuned.find(key);
     if (it != p->tuned.end()) return it->second;
@@ -2606,11 +2759,14 @@ csv_shape shape_for(const csv_pool *p, const uint8_t *lods, uint32_t lod_scalar,
                 best = &e.second;
             }
         }
-    return best ? *best : p->shape;
+    csv_shape sh = best ? *best : p->shape;
+    if (!p->shape_set && n <= pair_capacity(p)) sh.waves_per_group = 2;
+    return sh;
 }
 
 bool valid_shape(const csv_shape &sh) {
-    return (sh.waves_per_group == 4 || sh.waves_per_group == 8 || sh.waves_per_group == 16) &&
+    return (sh.waves_per_group == 2 || sh.waves_per_group == 4 || sh.waves_per_group == 8 ||
+            sh.waves_per_group == 16) &&
            sh.groups_per_cu >= 1 && sh.groups_per_cu <= kMaxGroupsB && sh.chunks >= 1 && sh.chunks <= 64;
 }
 
@@ -3122,7 +3278,9 @@ int csv_decode_bricks_shaped(const csv_pool *pool, const uint32_t *ids, const ui
 
 int csv_pool_set_shape(csv_pool *pool, const csv_shape *shape) {
     if (!pool || !shape || !valid_shape(*shape)) return CSV_EINVAL;
+    std::lock_guard<std::mutex> lk(pool->mu);
     pool->shape = *shape;
+    pool->shape_set = true;
     return CSV_OK;
 }
 
@@ -3173,9 +3331,9 @@ int csv_autotune(csv_pool *pool, const uint32_t *ids, const uint8_t *lods, uint3
     // split in up to four chunks, then the chunk count, then the work
     // counters and the longest-first order
     const uint32_t c0 = std::max(1u, std::min(4u, n / kMinChunk));
-    const int waves[2] = {8, 16};
+    const int waves[3] = {2, 8, 16};
     const uint32_t groups[3] = {2, 3, 4};
-    for (int wi = 0; wi < 2; wi++)
+    for (int wi = 0; wi < 3; wi++)
         for (int gi = 0; gi < 3; gi++) consider(csv_shape{waves[wi], groups[gi], 0, 0, c0, 0.f});
     const csv_shape base = win;
     for (uint32_t c : {1u, 2u, 4u, 8u})

@@ -125,10 +125,13 @@ def test_twelve_bit_tables_in_lds_and_in_global_memory(csvlib, orc, cfg1):
     np.testing.assert_array_equal(got, np.concatenate([w.ravel() for w in want]))
 
 
-def test_plain_per_brick_launch_matches(csvlib, orc, cfg1):
+@pytest.mark.parametrize("shape", [None, (2, 3, 0, 0, 1)])
+def test_plain_per_brick_launch_matches(csvlib, orc, cfg1, shape):
     vol, blob = cfg1
     pool = csvlib.Pool()
     pool.add_volume(blob)
+    if shape:
+        pool.set_shape(shape)
     ids = np.array([7, 0, 3, 3, 5])
     lods = np.array([0, 1, 2, 0, 4])
     log("plain per-brick launches")
@@ -168,9 +171,11 @@ def test_out_of_range_request_is_reported(csvlib, orc, cfg1):
     assert pool.last_error() == (0, 0)
 
 
-def test_status_names_each_failed_request(csvlib, orc, cfg1):
+@pytest.mark.parametrize("shape", [None, (2, 3, 0, 0, 1)])
+def test_status_names_each_failed_request(csvlib, orc, cfg1, shape):
     # csv_decode_bricks_status: an unknown id, a bad LOD and a corrupt
     # record each mark their own request; the others stay 0 and decode
+    # (also with the paired front kernel)
     torch = torch_cuda()
     vol, blob = cfg1
     info = orc.volume_info(blob)
@@ -182,6 +187,8 @@ def test_status_names_each_failed_request(csvlib, orc, cfg1):
     bad[rs + int(idx[6]) + 4 * (8 + int(w[0]) + int(w[1])) + 2 * (int(w[2]) // 2)] ^= 0x10
     pool = csvlib.Pool()
     pool.add_volume(bytes(bad))
+    if shape:
+        pool.set_shape(shape)
     ids = np.array([2, 77, 6, 3, 1], np.uint32)
     lods = np.array([0, 0, 0, 9, 1], np.uint8)
     off, tot = csvlib.output_offsets(np.minimum(lods, 5))
@@ -198,7 +205,8 @@ def test_status_names_each_failed_request(csvlib, orc, cfg1):
     np.testing.assert_array_equal(got[int(off[4]):int(off[4]) + 4096], orc.decode_brick(blob, 1, 1).ravel())
 
 
-def test_corrupt_record_is_reported(csvlib, orc, cfg1):
+@pytest.mark.parametrize("shape", [None, (2, 3, 0, 0, 1)])
+def test_corrupt_record_is_reported(csvlib, orc, cfg1, shape):
     vol, blob = cfg1
     info = orc.volume_info(blob)
     B = info["n_bricks"]
@@ -210,7 +218,9 @@ def test_corrupt_record_is_reported(csvlib, orc, cfg1):
     bad[rs + int(idx[4]) + 4 * (8 + P + W) + 2 * (nw // 2)] ^= 0x10
     pool = csvlib.Pool()
     pool.add_volume(bytes(bad))
-    log("corrupt record")
+    if shape:
+        pool.set_shape(shape)
+    log("corrupt record, shape %s" % (shape,))
     got, err = gpu_decode(pool, [3, 4, 5], [0, 0, 0], check_error=False)
     assert err == (csvlib.CSV_ECORRUPT, 4)
     np.testing.assert_array_equal(got[32768:65536], 0)
@@ -260,7 +270,7 @@ def test_config2_lower_lods(csvlib, orc, cfg2, lod):
     np.testing.assert_array_equal(got, orc.decode_bricks(blob, np.arange(4096), [lod] * 4096))
 
 
-@pytest.mark.parametrize("shape", [(4, 1, 1), (8, 3, 0), (16, 4, 1), (16, 8, 1), (4, 2, 0)])
+@pytest.mark.parametrize("shape", [(4, 1, 1), (8, 3, 0), (16, 4, 1), (16, 8, 1), (4, 2, 0), (2, 3, 0), (2, 2, 1)])
 def test_launch_shapes_agree(csvlib, orc, cfg2, shape):
     # every launch shape decodes the same bytes; 8 waves per group leave an
     # LDS arena too small for the densest bricks, which then take the
@@ -281,7 +291,7 @@ def test_launch_shapes_agree(csvlib, orc, cfg2, shape):
 
 
 @pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (16, 3, 0, 0, 2), (8, 2, 1, 1, 4), (16, 4, 0, 0, 8),
-                                   (8, 3, 0, 1, 4), (16, 3, 0, 1, 1)])
+                                   (8, 3, 0, 1, 4), (16, 3, 0, 1, 1), (2, 3, 0, 0, 2), (2, 3, 0, 1, 4)])
 def test_pipelined_chunks_agree(csvlib, orc, cfg1, cfg2, shape):
     # the requests split into chunks that alternate between the caller's
     # stream and the pool's second stream: mixed LODs over two volumes with
@@ -389,7 +399,7 @@ def test_tuning_file_round_trip(csvlib, orc, cfg1, cfg2, tmp_path):
     assert e.value.code == csvlib.CSV_ECORRUPT
 
 
-@pytest.mark.parametrize("shape", [(16, 4, 1, 0), (8, 5, 1, 1)])
+@pytest.mark.parametrize("shape", [(16, 4, 1, 0), (8, 5, 1, 1), (2, 3, 0, 1)])
 def test_graph_replays(csvlib, orc, cfg2, shape):
     # a captured decode replayed several times, with eager work and
     # synchronisation in between; every replay must match
@@ -420,7 +430,7 @@ def test_graph_replays(csvlib, orc, cfg2, shape):
     g.close()
 
 
-@pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (8, 3, 1, 1, 4)])
+@pytest.mark.parametrize("shape", [(16, 3, 0, 0, 1), (8, 3, 1, 1, 4), (2, 3, 0, 0, 1)])
 def test_device_count_decodes_a_prefix(csvlib, orc, cfg1, cfg2, shape):
     # csv_decode_bricks_devcount: the kernels decode min(n_max, *n_dev)
     # requests and leave the other outputs untouched (a lpt or chunked shape
