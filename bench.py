@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # what the same counters read for a plain 256 MiB device copy; see
 # profiles/decode_neurite1024_hbm_traffic.md.  Valid only for the decoder
 # source the counters were taken on (at the launch shape named here).
-TRAFFIC = {"decoder_sha256_16": "f6c6d995b70c45ed", "shape": (8, 3, 0, 0, 4), "bytes": 5093783252}
+TRAFFIC = {"decoder_sha256_16": "200266273e9e1f32", "shape": (8, 3, 0, 0, 4), "bytes": 5094037997}
 PAPER_GBS = {"cells": 9.9, "fiber": 10.4, "cortex": 9.3}  # Table 3, RTX 3070 Ti (context only)
 
 
