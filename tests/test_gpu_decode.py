@@ -471,3 +471,28 @@ def test_device_count_decodes_a_prefix(csvlib, orc, cfg1, cfg2, shape):
     got = out.cpu().numpy().view(np.uint32)
     np.testing.assert_array_equal(got[:123 * g ** 3], want)
     assert (got[123 * g ** 3:] == 0xFFFFFFFF).all()
+
+
+def test_small_batches_take_the_paired_kernel(csvlib, orc, cfg1):
+    # untuned, a batch the paired front kernel takes at once runs paired;
+    # larger batches and pools whose shape was set keep their shape, and the
+    # paired and unpaired decodes agree
+    torch = torch_cuda()
+    vol, blob = cfg1
+    pool = csvlib.Pool()
+    pool.add_volume(blob)
+    assert pool.shape_for(8)[0] == 2 and pool.shape_for(2048)[0] == 2
+    assert pool.shape_for(1 << 16)[0] != 2
+    ids = torch.tensor([5, 0, 7, 7, 2], dtype=torch.int32, device="cuda")
+    a = torch.full((5 * 32768,), -1, dtype=torch.int32, device="cuda")
+    b = torch.full_like(a, -1)
+    log("small batch, library shape %s" % (pool.shape_for(5),))
+    pool.decode(ids, a, lod=0)
+    pool.set_shape((8, 3, 0, 0, 1))
+    assert pool.shape_for(8)[0] == 8
+    pool.decode(ids, b, lod=0)
+    torch.cuda.synchronize()
+    assert pool.last_error() == (0, 0)
+    assert torch.equal(a, b)
+    np.testing.assert_array_equal(a.cpu().numpy().view(np.uint32),
+                                  orc.decode_bricks(blob, [5, 0, 7, 7, 2], [0] * 5))
